@@ -1,0 +1,213 @@
+/*
+ * sde.h -- C ABI of libsde: ensemble integration of stochastic differential
+ * equations on one AMD Instinct MI355X (gfx950), after Januszewski & Kostur,
+ * "Accelerating numerical solution of Stochastic Differential Equations with
+ * CUDA" (arXiv:0903.3852).
+ *
+ * Two models of the paper are integrated:
+ *   - the noisy driven Josephson junction / Stewart-McCumber equation
+ *     (Eq. 1), here with the potential force -sin(phi):
+ *        m phi'' + gamma phi' = -sin phi + a cos(omega t) + f + sqrt(2 gamma D) xi(t),
+ *     many independent paths of many parameter points (Sec. 4.1, Alg. 1);
+ *   - the noisy Kuramoto model of N globally coupled phase oscillators
+ *     (Eq. 2 with gamma = 1 and D = k_B T):
+ *        phi_i' = omega_i + sum_j K_ij sin(phi_j - phi_i) + sqrt(2 D) xi_i(t),
+ *     with the coupling sum evaluated every step by the mean-field identity
+ *     (Eq. 3), the LDS-tiled all-pairs sum (Alg. 3 / Fig. 3) or, for a dense
+ *     heterogeneous K_ij, a per-step matrix product.
+ * The stepper is the stochastic second-order Runge-Kutta (Heun) scheme of
+ * Alg. 2, or Euler-Maruyama.  Noise comes from a counter-based Philox4x32-10
+ * generator keyed by (seed, path, step) with Box-Muller Gaussians, so a run
+ * can be resumed at any step and reproduced exactly.
+ *
+ * Conventions for every call:
+ *   - Buffers marked [device] are raw HIP device pointers owned by the
+ *     caller; the library never frees or retains them past the call.
+ *     Descriptors and [host] buffers are host memory read during the call.
+ *   - Work is enqueued on `hip_stream` (a hipStream_t; NULL = the null
+ *     stream).  Calls return once the work is enqueued, except where stated.
+ *   - Arguments are validated before anything is launched; on an error the
+ *     output buffers are untouched and the call returns a negative status.
+ *     sde_last_error() then describes the failure.
+ *   - A context is used by one host thread at a time.
+ *   - No C++ exception crosses this interface.
+ */
+#ifndef SDE_H
+#define SDE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+enum {
+    SDE_OK = 0,
+    SDE_ERR_INVALID = -1,     /* bad argument (null, zero size, non-finite, misaligned) */
+    SDE_ERR_NOMEM = -2,       /* device workspace allocation failed                    */
+    SDE_ERR_DEVICE = -3,      /* a HIP runtime call failed                             */
+    SDE_ERR_UNSUPPORTED = -4, /* valid but not implemented (e.g. wrong GPU)            */
+    SDE_ERR_NUMERIC = -5      /* the state became NaN or Inf                           */
+};
+
+/* stepper */
+enum { SDE_HEUN = 0, SDE_EULER = 1 };
+/* initial state */
+enum { SDE_INIT_PHILOX = 0, SDE_INIT_FROM_STATE = 1 };
+/* Kuramoto coupling evaluation */
+enum {
+    SDE_MEANFIELD = 0,   /* Eq. 3: two sums per realization and stage, K_ij = K/N      */
+    SDE_TILED = 1,       /* Alg. 3: all N^2 sin terms, LDS tiles, K_ij = K/N           */
+    SDE_DENSE_FP32 = 2,  /* explicit K_ij: FP32 product K [sin | cos]                  */
+    SDE_DENSE_BF16X3 = 3,/* explicit K_ij: bf16 hi/lo split, 3 MFMA products, FP32 acc */
+    SDE_DENSE_FP16X3 = 4 /* explicit K_ij: fp16 hi/lo split, 3 MFMA products, FP32 acc */
+};
+/* Philox counter word 3 of each random stream */
+enum { SDE_TAG_NOISE = 0, SDE_TAG_INIT = 1 };
+
+typedef struct sde_ctx sde_ctx;
+
+/* Creates a context on HIP device `hip_device` (makes it current).  Returns
+ * SDE_ERR_UNSUPPORTED if the device is not gfx950, SDE_ERR_DEVICE if it
+ * cannot be opened. */
+int sde_create(int hip_device, sde_ctx** out);
+/* Frees the context's workspace (after synchronizing its device). */
+void sde_destroy(sde_ctx* ctx);
+/* Static text for a status code. */
+const char* sde_strerror(int status);
+/* Text describing the last failing call on `ctx` ("" if none). */
+const char* sde_last_error(const sde_ctx* ctx);
+/* Synchronizes the context's device and reports SDE_ERR_NUMERIC if any
+ * integration since the last check produced a NaN/Inf state. */
+int sde_check(sde_ctx* ctx);
+
+/* ---- run options shared by both models ----------------------------------- */
+typedef struct {
+    uint64_t seed;          /* Philox key: (seed mod 2^32, seed >> 32)                 */
+    uint64_t step0;         /* absolute index of the first step (resume at any step)   */
+    int32_t scheme;         /* SDE_HEUN | SDE_EULER                                    */
+    int32_t init;           /* SDE_INIT_PHILOX | SDE_INIT_FROM_STATE                   */
+    uint32_t sample_every;  /* M: FP32 partial sums are folded into FP64 every M       */
+                            /* absolute steps (JJ); order-parameter sampling interval  */
+                            /* (Kuramoto).  0 selects the paper's M = 100 (Sec. 4.1).  */
+    int32_t sync;           /* nonzero: synchronize the stream before returning and    */
+                            /* return SDE_ERR_NUMERIC if the state became NaN/Inf      */
+} sde_run;
+
+/* ---- Josephson junction (Eq. 1, Alg. 1, Alg. 2) -------------------------- */
+typedef struct {
+    double m, gamma, a, omega, f, D; /* Eq. 1; m = 0 selects the overdamped limit    */
+                                     /* gamma phi' = -sin phi + a cos wt + f + noise */
+    uint32_t n_paths;                /* independent paths of this point              */
+    uint32_t steps_per_period;       /* S: dt = 2 pi / (omega S); the drive phase    */
+                                     /* is kept as the step index mod S (Sec. 5)     */
+    uint64_t n_steps;                /* steps of this call                           */
+    uint64_t n_transient;            /* absolute step index where averaging begins   */
+} sde_jj_point;
+
+/*
+ * Integrates every path of every point for pts[q].n_steps Heun (or Euler)
+ * steps starting at absolute step run->step0, one persistent launch over
+ * all (point, path-chunk) work items.
+ *
+ * Path p of point q (0 <= p < pts[q].n_paths) lives at index
+ * off(q) + p of the per-path arrays, off(q) = sum of n_paths of points < q.
+ *   theta   [device] float,   per path, phase in revolutions in [0, 1):
+ *                             phi = 2 pi (theta + winding)
+ *   winding [device] int32,   per path, whole revolutions
+ *   v       [device] float,   per path, velocity phi' (m = 0: the step's
+ *                             mean velocity (phi_{n+1} - phi_n)/dt)
+ *   acc     [device] double,  per path, sum of v after each window step
+ *                             (absolute step n >= n_transient)
+ * Each may be NULL (state not kept) unless run->init is
+ * SDE_INIT_FROM_STATE, which reads all four.  With SDE_INIT_PHILOX the
+ * initial state is theta = U(x0), v = -2 + 4 U(x1) from
+ * Philox(ctr = (0, p, q, SDE_TAG_INIT)), winding = 0, acc = 0.
+ *   point_sums [device] double [n_pts][2] or NULL: (sum_p vbar_p,
+ *                             sum_p vbar_p^2) with vbar_p = acc_p / W,
+ *                             W = number of window steps before
+ *                             step0 + n_steps (0 if none: sums are 0).
+ * The noise of path p of point q at absolute step n is component n & 3 of
+ * the Box-Muller Gaussians of Philox(ctr = (n >> 2, p, q, SDE_TAG_NOISE)).
+ * Errors: SDE_ERR_INVALID for n_pts = 0, n_paths = 0, steps_per_period = 0,
+ * omega <= 0, gamma < 0 (or 0 with m = 0), m < 0, D < 0, non-finite
+ * parameters, misaligned pointers, FROM_STATE with a NULL state array.
+ */
+int sde_jj_integrate(sde_ctx* ctx, const sde_jj_point* pts /* [host] */, uint32_t n_pts,
+                     const sde_run* run, float* theta, int32_t* winding, float* v, double* acc,
+                     double* point_sums, void* hip_stream);
+
+/* ---- Kuramoto (Eq. 2, Eq. 3, Alg. 3) ------------------------------------- */
+typedef struct {
+    uint32_t N;            /* oscillators per realization                         */
+    uint32_t R;            /* independent realizations (own phases and noise)     */
+    double K;              /* uniform coupling K_ij = K / N (MEANFIELD, TILED)    */
+    double D;              /* noise intensity: sqrt(2 D) xi_i                     */
+    double dt;             /* step                                                */
+    uint64_t n_steps;      /* steps of this call                                  */
+    int32_t coupling;      /* SDE_MEANFIELD | SDE_TILED | SDE_DENSE_*             */
+    int32_t reserved;      /* must be 0                                           */
+} sde_kuramoto_desc;
+
+/*
+ * Integrates R realizations of N oscillators for n_steps steps.
+ *   phi      [device] float [R][N], in/out: phases in revolutions
+ *            (phi_i / 2 pi), kept wrapped to [0, 1).  Read only when
+ *            run->init is SDE_INIT_FROM_STATE; otherwise phase i of
+ *            realization r starts at U(Philox(ctr = (0, i, r, SDE_TAG_INIT)).x0).
+ *   omega    [device] float [N], natural frequencies (shared by realizations)
+ *   K        [device] float [N][N] row-major K_ij for SDE_DENSE_*, NULL
+ *            otherwise.  The dense variants scale K by an exact power of two
+ *            internally so that its largest entry lies in [1, 2).
+ *   r_samples[device] double [R][n_steps / M + 1] or NULL: order parameter
+ *            r = |N^-1 sum_j exp(2 pi i phi_j)| at local steps 0, M, 2M, ...
+ *            (M = run->sample_every, default 100).
+ * The noise of oscillator i of realization r at absolute step n is component
+ * n & 3 of the Box-Muller Gaussians of Philox(ctr = (n >> 2, i, r, NOISE)).
+ * Errors: SDE_ERR_INVALID for N or R = 0, dt <= 0, D < 0, non-finite K, D or
+ * dt, DENSE without K or MEANFIELD/TILED with K, misaligned pointers.
+ */
+int sde_kuramoto_integrate(sde_ctx* ctx, const sde_kuramoto_desc* desc, const sde_run* run,
+                           float* phi, const float* omega, const float* K, double* r_samples,
+                           void* hip_stream);
+
+/* ---- ensemble observables ------------------------------------------------ */
+enum {
+    SDE_OBS_MEAN_F32 = 0,  /* in float:  (mean, standard error of the mean)          */
+    SDE_OBS_MEAN_F64 = 1,  /* in double: (mean, standard error of the mean)          */
+    SDE_OBS_MEANSQ_F32 = 2,/* in float:  (mean of x^2, its standard error)           */
+    SDE_OBS_ORDER = 3      /* in float revolutions: (r, psi/2pi) of the Kuramoto     */
+                           /* order parameter r exp(i psi) = mean exp(2 pi i x)      */
+};
+/*
+ * Reduces consecutive groups of a device array: group g covers counts[g]
+ * elements following those of groups < g.  Sums are taken in FP64 with a
+ * fixed order (wavefront shuffles, then LDS, then a second pass), so the
+ * result is bitwise reproducible.  Writes host_out[g][0..1].  Synchronizes
+ * `hip_stream`.  The standard error uses the n-1 sample variance (0 when
+ * counts[g] < 2).  Example: <v> +- SE of each point from the per-path
+ * `v` array of sde_jj_integrate (ensemble average, Sec. 3 and Sec. 5).
+ */
+int sde_observables(sde_ctx* ctx, int kind, const void* dev_in /* [device] */,
+                    const uint32_t* counts /* [host] */, uint32_t n_groups,
+                    double* host_out /* [host] [n_groups][2] */, void* hip_stream);
+
+/* ---- test hooks ---------------------------------------------------------- */
+/* dev_out[k][0..3] = Philox4x32-10 words at counter (ctr0_first + k, a, b, tag)
+ * for k < n_blocks (the raw integers the integrators consume). */
+int sde_debug_philox(sde_ctx* ctx, uint64_t seed, uint32_t tag, uint32_t a, uint32_t b,
+                     uint64_t ctr0_first, uint64_t n_blocks, uint32_t* dev_out /* [device] */,
+                     void* hip_stream);
+/* dev_out[k] = Gaussian number n_first + k of stream (tag, a, b), as the
+ * integrators compute it (FP32 Box-Muller on the 24-bit uniforms). */
+int sde_debug_gauss(sde_ctx* ctx, uint64_t seed, uint32_t tag, uint32_t a, uint32_t b,
+                    uint64_t n_first, uint64_t count, float* dev_out /* [device] */,
+                    void* hip_stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif

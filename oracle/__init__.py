@@ -63,7 +63,7 @@ def lib():
         L.oracle_gauss.restype = d
         L.oracle_gauss_stream.argtypes = [u64, u32, u32, u32, u64, u64, pd]
         L.oracle_gauss_stream.restype = None
-        L.oracle_jj_integrate.argtypes = [P(JJPoint), u32, u64, u64, i32, i32, pd, pd, pd, pd,
+        L.oracle_jj_integrate.argtypes = [P(JJPoint), u32, P(u32), u64, u64, i32, i32, pd, pd, pd, pd,
                                           u32, pd, pd, i32]
         L.oracle_jj_integrate.restype = i32
         L.oracle_ou_integrate.argtypes = [d, d, d, u64, i32, u64, u32, pd, i32]
@@ -121,9 +121,11 @@ def make_points(params):
     return arr
 
 
-def jj_integrate(params, seed, step0=0, scheme=HEUN, state=None, n_record=0, n_threads=0):
+def jj_integrate(params, seed, step0=0, scheme=HEUN, state=None, n_record=0, n_threads=0,
+                 point_ids=None):
     """Integrate every path of every point.  `state` = (phi, v, acc) float64
     arrays to resume from (copied), else Philox INIT initial conditions.
+    `point_ids[q]` replaces q in the Philox counters (a subset of a batch).
 
     Returns dict(phi, v, acc, point_sums [n_pts,2], rec_phi, rec_v)."""
     pts = make_points(params)
@@ -137,7 +139,10 @@ def jj_integrate(params, seed, step0=0, scheme=HEUN, state=None, n_record=0, n_t
     sums = np.zeros((len(params), 2))
     rec_phi = np.zeros((n_record, total)) if n_record else None
     rec_v = np.zeros((n_record, total)) if n_record else None
-    rc = lib().oracle_jj_integrate(pts, len(params), seed, step0, scheme, init, _pd(phi),
+    ids = None
+    if point_ids is not None:
+        ids = (ctypes.c_uint32 * len(params))(*[int(x) for x in point_ids])
+    rc = lib().oracle_jj_integrate(pts, len(params), ids, seed, step0, scheme, init, _pd(phi),
                                    _pd(v), _pd(acc), _pd(sums), n_record, _pd(rec_phi),
                                    _pd(rec_v), n_threads)
     if rc != 0:

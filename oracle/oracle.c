@@ -182,8 +182,8 @@ static int jj_point_valid(const oracle_jj_point* P)
     return 1;
 }
 
-int oracle_jj_integrate(const oracle_jj_point* pts, uint32_t n_pts, uint64_t seed,
-                        uint64_t step0, int scheme, int init_from_state,
+int oracle_jj_integrate(const oracle_jj_point* pts, uint32_t n_pts, const uint32_t* point_ids,
+                        uint64_t seed, uint64_t step0, int scheme, int init_from_state,
                         double* phi, double* v, double* acc, double* point_sums,
                         uint32_t n_record, double* rec_phi, double* rec_v,
                         int n_threads)
@@ -209,12 +209,13 @@ int oracle_jj_integrate(const oracle_jj_point* pts, uint32_t n_pts, uint64_t see
         const double s = inertial ? sqrt(2.0 * P->gamma * P->D * dt) / P->m
                                   : sqrt(2.0 * P->D * dt / P->gamma);
         const int64_t np = (int64_t)P->n_paths;
+        const uint32_t qid = point_ids ? point_ids[q] : q;
 #pragma omp parallel for num_threads(nt) schedule(static)
         for (int64_t p = 0; p < np; ++p) {
             const uint64_t gi = first[q] + (uint64_t)p;
             double x[2], F1[2], F2[2], xp[2], noise[2];
             if (!init_from_state) {
-                uint32_t ctr[4] = {0u, (uint32_t)p, q, ORC_TAG_INIT}, r[4];
+                uint32_t ctr[4] = {0u, (uint32_t)p, qid, ORC_TAG_INIT}, r[4];
                 oracle_philox(seed, ctr, r);
                 phi[gi] = 2.0 * PI * u_closed0(r[0]);
                 v[gi] = -2.0 + 4.0 * u_closed0(r[1]);
@@ -224,7 +225,7 @@ int oracle_jj_integrate(const oracle_jj_point* pts, uint32_t n_pts, uint64_t see
             x[1] = v[gi];
             double a_sum = acc[gi];
             gauss_stream gs;
-            gs_init(&gs, seed, ORC_TAG_NOISE, (uint32_t)p, q);
+            gs_init(&gs, seed, ORC_TAG_NOISE, (uint32_t)p, qid);
             for (uint64_t k = 0; k < P->n_steps; ++k) {
                 const uint64_t n = step0 + k;
                 const double psi = gs_get(&gs, n);

@@ -83,12 +83,15 @@ typedef struct {
  *                 (absolute step n with n >= n_transient) up to step0+n_steps.
  *   rec_phi/v   : optional [n_record][total paths]: state after each of the
  *                 first n_record steps.
+ *   point_ids   : optional [n_pts]: the point index b that enters the Philox
+ *                 counters of point q (default q), so that a subset of a
+ *                 larger batch draws the same random numbers as in the batch.
  * Returns 0, or -1 on invalid arguments.
  * Parity: pinned by the equilibrium (Boltzmann) moments, the overdamped
  * washboard velocity and the deterministic order-2 convergence.
  */
-int oracle_jj_integrate(const oracle_jj_point* pts, uint32_t n_pts, uint64_t seed,
-                        uint64_t step0, int scheme, int init_from_state,
+int oracle_jj_integrate(const oracle_jj_point* pts, uint32_t n_pts, const uint32_t* point_ids,
+                        uint64_t seed, uint64_t step0, int scheme, int init_from_state,
                         double* phi, double* v, double* acc, double* point_sums,
                         uint32_t n_record, double* rec_phi, double* rec_v,
                         int n_threads);

@@ -1,0 +1,511 @@
+// jj.hip -- ensemble integration of the driven, damped, noisy Josephson
+// junction (Eq. 1 with the -sin(phi) potential force) over many independent
+// paths and parameter points, stochastic Heun (Alg. 2) or Euler-Maruyama.
+//
+// Design (gfx950):
+//  * One persistent launch.  Every wavefront pops work items (point, path
+//    chunk of 64*PPT paths) from a device-scope counter until the queue is
+//    empty; items are queued longest-first so uneven batches finish together.
+//    Paths are independent (Sec. 4.1), so which wave runs an item does not
+//    change any result.
+//  * Per-path state stays in VGPRs for the whole item (Alg. 1 keeps x, v in
+//    registers for m steps and touches global memory only at the ends); the
+//    point's parameters are wave-uniform and live in SGPRs.
+//  * The phase is kept in revolutions, theta in [0, 1), plus an integer
+//    winding count, so the hardware v_sin_f32 (which takes revolutions) needs
+//    no range reduction and FP32 never adds a tiny increment to a large phase
+//    (the precision issue of Sec. 5).  The drive phase is the step index mod
+//    S read from a cos table, the integer form of keeping time modulo the
+//    drive period (Sec. 5).
+//  * One Philox4x32-10 block per path gives the Gaussians of four
+//    consecutive steps; Box-Muller uses the hardware log2/sqrt/sin/cos.
+//  * The time average of v is summed in FP32 over M steps and folded into an
+//    FP64 accumulator every M absolute steps (Sec. 4.1 samples every M).
+//  * Per-chunk FP64 sums of vbar and vbar^2 are written without atomics and
+//    combined per point in a fixed order by a second kernel, so results are
+//    bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdlib>
+#include <map>
+
+#include "device_common.h"
+#include "sde_internal.h"
+
+namespace sde {
+
+struct JJPointDev {
+    float dt, hdt, dt2pi, hdt2pi;  // dt, dt/2, dt/(2 pi), dt/(4 pi)
+    float gim, im, a_im, f_im;     // gamma/m, 1/m, a/m, f/m (overdamped: 1/gamma for m)
+    float c2, sig_v;               // c2 = -2 ln2 sigma^2 with sigma the noise increment per
+                                   // Gaussian: on v (inertial) or on theta in revolutions
+                                   // (overdamped); sig_v = 2 pi / dt turns the latter into
+                                   // a velocity
+    uint32_t S, lut_off, n_paths, inertial;
+    uint64_t path_first, n_steps, n_transient;
+    double inv_W;
+    uint32_t chunk_first, n_chunks;
+};
+static_assert(sizeof(JJPointDev) % 8 == 0, "layout");
+
+struct JJItem {
+    uint32_t point, chunk;
+};
+
+struct JJArgs {
+    const JJPointDev* pts;
+    const JJItem* items;
+    const float* lut;
+    uint32_t* queue;
+    int* flag;
+    float* theta;
+    int32_t* winding;
+    float* v;
+    double* acc;
+    double* partials;
+    uint64_t step0;
+    uint32_t key0, key1;
+    uint32_t n_items, M;
+    int32_t init_from_state;
+};
+
+// One step n -> n + 1 of the PPT paths held by this lane.  e0, e1 are the
+// uniform drive terms (a cos(w t) + f)/m at t_n and t_{n+1} (the second
+// drift evaluation of Alg. 2 is taken at t + dt), ns the noise increments.
+template <int PPT, int SCHEME, bool INERTIAL, bool ACC>
+__device__ __forceinline__ void jj_step(const JJPointDev& P, float e0, float e1, const float (&ns)[PPT],
+                                        float (&th)[PPT], float (&vv)[PPT], float (&af)[PPT])
+{
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        if (INERTIAL) {
+            // X = (phi, v), F = (v, (-sin phi - gamma v + a cos wt + f)/m), noise on v
+            const float F1 = fmaf(-P.im, sin_rev(th[k]), fmaf(-P.gim, vv[k], e0));
+            if (SCHEME == SDE_HEUN) {
+                const float vt = fmaf(P.dt, F1, vv[k]) + ns[k];
+                const float tt = fmaf(P.dt2pi, vv[k], th[k]);
+                const float F2 = fmaf(-P.im, sin_rev(tt), fmaf(-P.gim, vt, e1));
+                th[k] = fmaf(P.hdt2pi, vv[k] + vt, th[k]);
+                vv[k] = fmaf(P.hdt, F1 + F2, vv[k]) + ns[k];
+            } else {
+                th[k] = fmaf(P.dt2pi, vv[k], th[k]);
+                vv[k] = fmaf(P.dt, F1, vv[k]) + ns[k];
+            }
+        } else {
+            // overdamped: phi' = (-sin phi + a cos wt + f)/gamma + noise on phi;
+            // v reports the step's mean velocity (phi_{n+1} - phi_n)/dt
+            const float F1 = fmaf(-P.im, sin_rev(th[k]), e0);
+            if (SCHEME == SDE_HEUN) {
+                const float tt = fmaf(P.dt2pi, F1, th[k]) + ns[k];
+                const float F2 = fmaf(-P.im, sin_rev(tt), e1);
+                th[k] = fmaf(P.hdt2pi, F1 + F2, th[k]) + ns[k];
+                vv[k] = fmaf(0.5f, F1 + F2, P.sig_v * ns[k]);
+            } else {
+                th[k] = fmaf(P.dt2pi, F1, th[k]) + ns[k];
+                vv[k] = fmaf(P.sig_v, ns[k], F1);
+            }
+        }
+        if (ACC) af[k] += vv[k];
+    }
+}
+
+template <int PPT, int SCHEME, bool INERTIAL>
+__device__ __forceinline__ void jj_item(const JJArgs& A, uint32_t q, uint32_t chunk)
+{
+    const JJPointDev P = load_uniform(A.pts + q);
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+
+    float th[PPT], vv[PPT], af[PPT];
+    int32_t wd[PPT];
+    double ad[PPT];
+    uint32_t pid[PPT];
+    bool live[PPT];
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        pid[k] = chunk * (kWave * PPT) + k * kWave + lane;
+        live[k] = pid[k] < P.n_paths;
+        const uint64_t gi = P.path_first + pid[k];
+        if (A.init_from_state) {
+            th[k] = live[k] ? A.theta[gi] : 0.f;
+            vv[k] = live[k] ? A.v[gi] : 0.f;
+            wd[k] = live[k] ? A.winding[gi] : 0;
+            ad[k] = live[k] ? A.acc[gi] : 0.0;
+        } else {
+            const U4 x = philox4x32_10(U4{0u, pid[k], q, (uint32_t)SDE_TAG_INIT}, A.key0, A.key1);
+            th[k] = (float)(x.x >> 8) * 0x1p-24f;
+            vv[k] = -2.0f + 4.0f * ((float)(x.y >> 8) * 0x1p-24f);
+            wd[k] = 0;
+            ad[k] = 0.0;
+        }
+        af[k] = 0.f;
+    }
+
+    const float* lut = A.lut + P.lut_off;  // cos(2 pi k / S) for k < S + 8
+    const uint64_t n_end = A.step0 + P.n_steps;
+    uint64_t n = A.step0;
+    uint32_t kk = (uint32_t)(n % P.S);        // drive phase index of step n
+    uint32_t mc = (uint32_t)((n + 1) % A.M);  // (n + 1) mod M: fold after the step when 0
+
+    auto fold_tick = [&]() {
+        if (mc == 0) {
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                ad[k] += (double)af[k];
+                af[k] = 0.f;
+            }
+        }
+        mc = (mc + 1 == A.M) ? 0u : mc + 1;
+    };
+
+    while (n < n_end) {
+        const uint32_t j0 = (uint32_t)n & 3u;
+        const uint64_t left = n_end - n;
+        const uint32_t jn = left >= (uint64_t)(4u - j0) ? 4u : j0 + (uint32_t)left;
+        // sigma * Gaussians of steps 4b .. 4b+3 (b = n >> 2) of each path
+        float g[PPT][4];
+#pragma unroll
+        for (int k = 0; k < PPT; ++k)
+            gauss4_scaled(U4{(uint32_t)(n >> 2), pid[k], q, (uint32_t)SDE_TAG_NOISE}, A.key0, A.key1, P.c2, g[k]);
+        if (j0 == 0 && jn == 4) {
+            float e[5];
+#pragma unroll
+            for (int j = 0; j < 5; ++j) e[j] = fmaf(P.a_im, load_uniform(lut + kk + j), P.f_im);
+            if (n >= P.n_transient) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    float ns[PPT];
+#pragma unroll
+                    for (int k = 0; k < PPT; ++k) ns[k] = g[k][j];
+                    jj_step<PPT, SCHEME, INERTIAL, true>(P, e[j], e[j + 1], ns, th, vv, af);
+                    fold_tick();
+                }
+            } else if (n + 4 <= P.n_transient) {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    float ns[PPT];
+#pragma unroll
+                    for (int k = 0; k < PPT; ++k) ns[k] = g[k][j];
+                    jj_step<PPT, SCHEME, INERTIAL, false>(P, e[j], e[j + 1], ns, th, vv, af);
+                    fold_tick();
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    float ns[PPT];
+#pragma unroll
+                    for (int k = 0; k < PPT; ++k) ns[k] = g[k][j];
+                    if (n + j >= P.n_transient)
+                        jj_step<PPT, SCHEME, INERTIAL, true>(P, e[j], e[j + 1], ns, th, vv, af);
+                    else
+                        jj_step<PPT, SCHEME, INERTIAL, false>(P, e[j], e[j + 1], ns, th, vv, af);
+                    fold_tick();
+                }
+            }
+            n += 4;
+            kk += 4;
+            while (kk >= P.S) kk -= P.S;
+        } else {
+            // partial block (first or last of the call): one step at a time
+            for (uint32_t j = j0; j < jn; ++j) {
+                float ns[PPT];
+#pragma unroll
+                for (int k = 0; k < PPT; ++k)
+                    ns[k] = j == 0 ? g[k][0] : j == 1 ? g[k][1] : j == 2 ? g[k][2] : g[k][3];
+                const float ea = fmaf(P.a_im, load_uniform(lut + kk), P.f_im);
+                const float eb = fmaf(P.a_im, load_uniform(lut + kk + 1), P.f_im);
+                if (n >= P.n_transient)
+                    jj_step<PPT, SCHEME, INERTIAL, true>(P, ea, eb, ns, th, vv, af);
+                else
+                    jj_step<PPT, SCHEME, INERTIAL, false>(P, ea, eb, ns, th, vv, af);
+                fold_tick();
+                ++n;
+                kk = (kk + 1 == P.S) ? 0u : kk + 1;
+            }
+        }
+        // keep theta in [0, 1): move whole revolutions into the winding count
+#pragma unroll
+        for (int k = 0; k < PPT; ++k) {
+            const float fl = floorf(th[k]);
+            th[k] -= fl;
+            wd[k] += (int32_t)fl;
+        }
+    }
+
+    double s1 = 0.0, s2 = 0.0;
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < PPT; ++k) {
+        ad[k] += (double)af[k];
+        if (live[k]) {
+            const uint64_t gi = P.path_first + pid[k];
+            if (A.theta) A.theta[gi] = th[k];
+            if (A.winding) A.winding[gi] = wd[k];
+            if (A.v) A.v[gi] = vv[k];
+            if (A.acc) A.acc[gi] = ad[k];
+            const double vb = ad[k] * P.inv_W;
+            s1 += vb;
+            s2 += vb * vb;
+            bad |= !(isfinite(th[k]) && isfinite(vv[k]));
+        }
+    }
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    if (lane == 0) {
+        A.partials[2 * (P.chunk_first + chunk)] = s1;
+        A.partials[2 * (P.chunk_first + chunk) + 1] = s2;
+    }
+    if (__ballot(bad) != 0 && lane == 0) atomicOr(A.flag, 1);
+}
+
+template <int PPT, int SCHEME, bool INERTIAL>
+__global__ __launch_bounds__(256) void jj_persistent_kernel(JJArgs A)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    for (;;) {
+        uint32_t item = 0;
+        if (lane == 0) item = atomicAdd(A.queue, 1u);
+        item = uniform_u32(__shfl(item, 0, kWave));
+        if (item >= A.n_items) break;
+        const JJItem it = load_uniform(A.items + item);
+        jj_item<PPT, SCHEME, INERTIAL>(A, it.point, it.chunk);
+    }
+}
+
+// Stage 2: per point, the chunk partials in chunk order.
+__global__ void jj_point_sums_kernel(const JJPointDev* pts, uint32_t n_pts, const double* partials,
+                                     double* out)
+{
+    const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_pts) return;
+    const uint32_t first = pts[q].chunk_first, nc = pts[q].n_chunks;
+    double s1 = 0.0, s2 = 0.0;
+    for (uint32_t c = 0; c < nc; ++c) {
+        s1 += partials[2 * (first + c)];
+        s2 += partials[2 * (first + c) + 1];
+    }
+    out[2 * q] = s1;
+    out[2 * q + 1] = s2;
+}
+
+// Test hooks: raw Philox words and the integrators' Gaussians.
+__global__ void philox_dump_kernel(uint32_t k0, uint32_t k1, uint32_t tag, uint32_t a, uint32_t b,
+                                   uint64_t c0, uint64_t n, uint32_t* out)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const U4 x = philox4x32_10(U4{(uint32_t)(c0 + i), a, b, tag}, k0, k1);
+    out[4 * i] = x.x;
+    out[4 * i + 1] = x.y;
+    out[4 * i + 2] = x.z;
+    out[4 * i + 3] = x.w;
+}
+
+__global__ void gauss_dump_kernel(uint32_t k0, uint32_t k1, uint32_t tag, uint32_t a, uint32_t b,
+                                  uint64_t n0, uint64_t n, float* out)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint64_t s = n0 + i;
+    float g[4];
+    gauss4(U4{(uint32_t)(s >> 2), a, b, tag}, k0, k1, g);
+    const uint32_t j = (uint32_t)s & 3u;
+    out[i] = j == 0 ? g[0] : j == 1 ? g[1] : j == 2 ? g[2] : g[3];
+}
+
+// ------------------------------------------------------------------ host --
+
+using JJKernel = void (*)(JJArgs);
+
+template <bool INERTIAL>
+static JJKernel pick_kernel(int ppt, int scheme)
+{
+    if (scheme == SDE_HEUN) {
+        if (ppt == 1) return jj_persistent_kernel<1, SDE_HEUN, INERTIAL>;
+        if (ppt == 4) return jj_persistent_kernel<4, SDE_HEUN, INERTIAL>;
+        return jj_persistent_kernel<2, SDE_HEUN, INERTIAL>;
+    }
+    if (ppt == 1) return jj_persistent_kernel<1, SDE_EULER, INERTIAL>;
+    if (ppt == 4) return jj_persistent_kernel<4, SDE_EULER, INERTIAL>;
+    return jj_persistent_kernel<2, SDE_EULER, INERTIAL>;
+}
+
+static bool finite_point(const sde_jj_point& p)
+{
+    return std::isfinite(p.m) && std::isfinite(p.gamma) && std::isfinite(p.a) && std::isfinite(p.omega) &&
+           std::isfinite(p.f) && std::isfinite(p.D);
+}
+
+int jj_paths_per_thread()
+{
+    const char* e = std::getenv("SDE_JJ_PPT");
+    if (e) {
+        int v = std::atoi(e);
+        if (v == 1 || v == 2 || v == 4) return v;
+    }
+    return 2;
+}
+
+int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run,
+                      float* theta, int32_t* winding, float* v, double* acc, double* point_sums,
+                      hipStream_t stream)
+{
+    if (!pts || !run || n_pts == 0) return fail(ctx, SDE_ERR_INVALID, "null points/run or n_pts = 0");
+    if (run->scheme != SDE_HEUN && run->scheme != SDE_EULER)
+        return fail(ctx, SDE_ERR_INVALID, "unknown scheme %d", run->scheme);
+    if (run->init != SDE_INIT_PHILOX && run->init != SDE_INIT_FROM_STATE)
+        return fail(ctx, SDE_ERR_INVALID, "unknown init %d", run->init);
+    if (run->init == SDE_INIT_FROM_STATE && (!theta || !winding || !v || !acc))
+        return fail(ctx, SDE_ERR_INVALID, "SDE_INIT_FROM_STATE needs theta, winding, v and acc");
+    if (!aligned(theta, 4) || !aligned(winding, 4) || !aligned(v, 4) || !aligned(acc, 8) ||
+        !aligned(point_sums, 8))
+        return fail(ctx, SDE_ERR_INVALID, "misaligned device pointer");
+    const uint32_t M = run->sample_every ? run->sample_every : 100u;
+    const int ppt = jj_paths_per_thread();
+    const uint32_t chunk_paths = (uint32_t)(kWave * ppt);
+
+    std::vector<JJPointDev> P(n_pts);
+    std::vector<JJItem> items, items_od;  // inertial points, overdamped points
+    std::map<uint32_t, uint32_t> lut_of;  // S -> offset
+    std::vector<float> lut;
+    uint64_t path_first = 0;
+    uint32_t chunk_first = 0;
+    for (uint32_t q = 0; q < n_pts; ++q) {
+        const sde_jj_point& p = pts[q];
+        if (!finite_point(p)) return fail(ctx, SDE_ERR_INVALID, "point %u: non-finite parameter", q);
+        if (p.n_paths == 0 || p.steps_per_period == 0)
+            return fail(ctx, SDE_ERR_INVALID, "point %u: n_paths and steps_per_period must be > 0", q);
+        if (!(p.omega > 0) || p.m < 0 || p.gamma < 0 || p.D < 0 || (p.m == 0 && !(p.gamma > 0)))
+            return fail(ctx, SDE_ERR_INVALID, "point %u: need omega > 0, m >= 0, D >= 0, gamma >= 0 "
+                        "(gamma > 0 when m = 0)", q);
+        const double dt = 2.0 * M_PI / (p.omega * (double)p.steps_per_period);
+        JJPointDev& d = P[q];
+        d.dt = (float)dt;
+        d.hdt = (float)(0.5 * dt);
+        d.dt2pi = (float)(dt / (2.0 * M_PI));
+        d.hdt2pi = (float)(dt / (4.0 * M_PI));
+        d.inertial = p.m > 0 ? 1u : 0u;
+        if (d.inertial) {
+            d.im = (float)(1.0 / p.m);
+            d.gim = (float)(p.gamma / p.m);
+            d.a_im = (float)(p.a / p.m);
+            d.f_im = (float)(p.f / p.m);
+            const double sig = std::sqrt(2.0 * p.gamma * p.D * dt) / p.m;
+            d.c2 = (float)(-2.0 * M_LN2 * sig * sig);
+            d.sig_v = 0.f;
+        } else {
+            const double s = std::sqrt(2.0 * p.D * dt / p.gamma);
+            d.im = (float)(1.0 / p.gamma);
+            d.gim = 0.f;
+            d.a_im = (float)(p.a / p.gamma);
+            d.f_im = (float)(p.f / p.gamma);
+            const double sig = s / (2.0 * M_PI);
+            d.c2 = (float)(-2.0 * M_LN2 * sig * sig);
+            d.sig_v = (float)(2.0 * M_PI / dt);
+        }
+        d.S = p.steps_per_period;
+        auto it = lut_of.find(d.S);
+        if (it == lut_of.end()) {
+            const uint32_t off = (uint32_t)lut.size();
+            for (uint32_t k = 0; k < d.S + 8; ++k)
+                lut.push_back((float)std::cos(2.0 * M_PI * (double)(k % d.S) / (double)d.S));
+            it = lut_of.emplace(d.S, off).first;
+        }
+        d.lut_off = it->second;
+        d.n_paths = p.n_paths;
+        d.path_first = path_first;
+        d.n_steps = p.n_steps;
+        d.n_transient = p.n_transient;
+        const uint64_t end = run->step0 + p.n_steps;
+        const uint64_t W = end > p.n_transient ? end - p.n_transient : 0;
+        d.inv_W = W ? 1.0 / (double)W : 0.0;
+        d.n_chunks = (p.n_paths + chunk_paths - 1) / chunk_paths;
+        d.chunk_first = chunk_first;
+        for (uint32_t c = 0; c < d.n_chunks; ++c) (d.inertial ? items : items_od).push_back(JJItem{q, c});
+        chunk_first += d.n_chunks;
+        path_first += p.n_paths;
+    }
+    // Longest items first, so that an uneven batch ends with short items.
+    auto longest_first = [&](const JJItem& x, const JJItem& y) { return P[x.point].n_steps > P[y.point].n_steps; };
+    std::stable_sort(items.begin(), items.end(), longest_first);
+    std::stable_sort(items_od.begin(), items_od.end(), longest_first);
+    const uint32_t n_inertial = (uint32_t)items.size();
+    items.insert(items.end(), items_od.begin(), items_od.end());
+
+    int st;
+    if ((st = upload(ctx, kSlotJJPoints, 0, P.data(), P.size() * sizeof(JJPointDev), stream))) return st;
+    if ((st = upload(ctx, kSlotJJItems, 1, items.data(), items.size() * sizeof(JJItem), stream))) return st;
+    if ((st = upload(ctx, kSlotJJLut, 2, lut.data(), lut.size() * sizeof(float), stream))) return st;
+    void* partials = nullptr;
+    if ((st = ensure_ws(ctx, kSlotJJPartials, (size_t)chunk_first * 2 * sizeof(double), &partials))) return st;
+    if ((st = zero_counters(ctx, 0, 2, stream))) return st;
+
+    JJArgs A;
+    A.pts = static_cast<const JJPointDev*>(ctx->ws[kSlotJJPoints].ptr);
+    A.lut = static_cast<const float*>(ctx->ws[kSlotJJLut].ptr);
+    A.flag = ctx->flag;
+    A.theta = theta;
+    A.winding = winding;
+    A.v = v;
+    A.acc = acc;
+    A.partials = static_cast<double*>(partials);
+    A.step0 = run->step0;
+    A.key0 = (uint32_t)(run->seed & 0xffffffffu);
+    A.key1 = (uint32_t)(run->seed >> 32);
+    A.M = M;
+    A.init_from_state = run->init == SDE_INIT_FROM_STATE;
+    const JJItem* all_items = static_cast<const JJItem*>(ctx->ws[kSlotJJItems].ptr);
+
+    for (int kind = 0; kind < 2; ++kind) {  // 0: inertial points, 1: overdamped points
+        const uint32_t first = kind == 0 ? 0u : n_inertial;
+        const uint32_t count = kind == 0 ? n_inertial : (uint32_t)items.size() - n_inertial;
+        if (count == 0) continue;
+        A.items = all_items + first;
+        A.n_items = count;
+        A.queue = ctx->counters + kind;
+        JJKernel kern = kind == 0 ? pick_kernel<true>(ppt, run->scheme) : pick_kernel<false>(ppt, run->scheme);
+        int per_cu = 0;
+        SDE_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), 256, 0));
+        if (per_cu < 1) per_cu = 1;
+        const uint64_t want = ((uint64_t)count + 3) / 4;  // 4 waves per block, one item each at least
+        const uint32_t grid = (uint32_t)std::min<uint64_t>(want, (uint64_t)per_cu * ctx->n_cu);
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, stream, A);
+        SDE_HIP(ctx, hipGetLastError());
+    }
+    if (point_sums) {
+        hipLaunchKernelGGL(jj_point_sums_kernel, dim3((n_pts + 255) / 256), dim3(256), 0, stream, A.pts, n_pts,
+                           A.partials, point_sums);
+        SDE_HIP(ctx, hipGetLastError());
+    }
+    if (run->sync) return sync_and_check(ctx, stream);
+    return SDE_OK;
+}
+
+int debug_philox_impl(sde_ctx* ctx, uint64_t seed, uint32_t tag, uint32_t a, uint32_t b, uint64_t c0,
+                      uint64_t n, uint32_t* out, hipStream_t stream)
+{
+    if (!out || n == 0) return fail(ctx, SDE_ERR_INVALID, "null output or zero blocks");
+    if (!aligned(out, 4)) return fail(ctx, SDE_ERR_INVALID, "misaligned output");
+    const uint64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffffu) return fail(ctx, SDE_ERR_INVALID, "too many blocks");
+    hipLaunchKernelGGL(philox_dump_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, (uint32_t)seed,
+                       (uint32_t)(seed >> 32), tag, a, b, c0, n, out);
+    SDE_HIP(ctx, hipGetLastError());
+    return SDE_OK;
+}
+
+int debug_gauss_impl(sde_ctx* ctx, uint64_t seed, uint32_t tag, uint32_t a, uint32_t b, uint64_t n0,
+                     uint64_t n, float* out, hipStream_t stream)
+{
+    if (!out || n == 0) return fail(ctx, SDE_ERR_INVALID, "null output or zero count");
+    if (!aligned(out, 4)) return fail(ctx, SDE_ERR_INVALID, "misaligned output");
+    const uint64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffffu) return fail(ctx, SDE_ERR_INVALID, "count too large");
+    hipLaunchKernelGGL(gauss_dump_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, (uint32_t)seed,
+                       (uint32_t)(seed >> 32), tag, a, b, n0, n, out);
+    SDE_HIP(ctx, hipGetLastError());
+    return SDE_OK;
+}
+
+}  // namespace sde

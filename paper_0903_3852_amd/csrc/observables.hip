@@ -1,0 +1,114 @@
+// observables.hip -- ensemble averages of per-path / per-oscillator arrays
+// (the quantities of interest of Sec. 3: averages over realizations, the
+// asymptotic velocity of Sec. 5, the Kuramoto order parameter).
+//
+// One workgroup per group.  Thread t takes elements t, t + 256, ... in FP64;
+// partial sums are combined by a wavefront butterfly and then by wave index
+// through LDS, always in the same order, so results are bitwise
+// reproducible.  The spread is taken about the mean in a second pass over
+// the group (no cancellation from sum of squares minus squared sum).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "device_common.h"
+#include "sde_internal.h"
+
+namespace sde {
+
+constexpr int kObsThreads = 256;
+
+__device__ double block_sum(double x, double* lds)
+{
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    x = wave_sum(x);
+    if (lane == 0) lds[wid] = x;
+    __syncthreads();
+    double t = 0.0;
+#pragma unroll
+    for (int w = 0; w < kObsThreads / kWave; ++w) t += lds[w];
+    __syncthreads();
+    return t;
+}
+
+template <typename T>
+__device__ __forceinline__ double load_value(const void* in, uint64_t i, int square)
+{
+    const double x = (double)static_cast<const T*>(in)[i];
+    return square ? x * x : x;
+}
+
+__global__ __launch_bounds__(kObsThreads) void obs_kernel(int kind, const void* in, const uint64_t* first,
+                                                          const uint32_t* counts, double* out)
+{
+    __shared__ double lds[kObsThreads / kWave];
+    const uint32_t g = blockIdx.x;
+    const uint64_t base = first[g];
+    const uint32_t n = counts[g];
+    if (kind == SDE_OBS_ORDER) {
+        double c = 0.0, s = 0.0;
+        for (uint32_t i = threadIdx.x; i < n; i += kObsThreads) {
+            double sn, cs;
+            sincospi(2.0 * (double)static_cast<const float*>(in)[base + i], &sn, &cs);
+            c += cs;
+            s += sn;
+        }
+        c = block_sum(c, lds);
+        s = block_sum(s, lds);
+        if (threadIdx.x == 0) {
+            const double inv = n ? 1.0 / (double)n : 0.0;
+            out[2 * g] = std::sqrt(c * c + s * s) * inv;
+            out[2 * g + 1] = n ? atan2(s, c) / (2.0 * M_PI) : 0.0;
+        }
+        return;
+    }
+    const int square = kind == SDE_OBS_MEANSQ_F32;
+    double sum = 0.0;
+    for (uint32_t i = threadIdx.x; i < n; i += kObsThreads)
+        sum += kind == SDE_OBS_MEAN_F64 ? load_value<double>(in, base + i, 0) : load_value<float>(in, base + i, square);
+    sum = block_sum(sum, lds);
+    const double mean = n ? sum / (double)n : 0.0;
+    double ss = 0.0;
+    for (uint32_t i = threadIdx.x; i < n; i += kObsThreads) {
+        const double x = kind == SDE_OBS_MEAN_F64 ? load_value<double>(in, base + i, 0)
+                                                  : load_value<float>(in, base + i, square);
+        ss += (x - mean) * (x - mean);
+    }
+    ss = block_sum(ss, lds);
+    if (threadIdx.x == 0) {
+        out[2 * g] = mean;
+        out[2 * g + 1] = n > 1 ? std::sqrt(ss / (double)(n - 1) / (double)n) : 0.0;
+    }
+}
+
+int observables_impl(sde_ctx* ctx, int kind, const void* in, const uint32_t* counts, uint32_t n_groups,
+                     double* host_out, hipStream_t stream)
+{
+    if (kind < SDE_OBS_MEAN_F32 || kind > SDE_OBS_ORDER) return fail(ctx, SDE_ERR_INVALID, "unknown kind %d", kind);
+    if (!in || !counts || !host_out || n_groups == 0) return fail(ctx, SDE_ERR_INVALID, "null argument or no groups");
+    if (!aligned(in, kind == SDE_OBS_MEAN_F64 ? 8 : 4)) return fail(ctx, SDE_ERR_INVALID, "misaligned input");
+    // layout of the workspace: first[n_groups] (u64) | counts[n_groups] (u32) | out[n_groups][2]
+    std::vector<unsigned char> meta((size_t)n_groups * 12);
+    uint64_t off = 0;
+    for (uint32_t g = 0; g < n_groups; ++g) {
+        std::memcpy(meta.data() + 8 * (size_t)g, &off, 8);
+        off += counts[g];
+    }
+    std::memcpy(meta.data() + 8 * (size_t)n_groups, counts, 4 * (size_t)n_groups);
+    int st = upload(ctx, kSlotMisc, 3, meta.data(), meta.size(), stream);
+    if (st) return st;
+    void* outbuf = nullptr;
+    if ((st = ensure_ws(ctx, kSlotObs, (size_t)n_groups * 2 * sizeof(double), &outbuf))) return st;
+    const unsigned char* dmeta = static_cast<const unsigned char*>(ctx->ws[kSlotMisc].ptr);
+    hipLaunchKernelGGL(obs_kernel, dim3(n_groups), dim3(kObsThreads), 0, stream, kind, in,
+                       reinterpret_cast<const uint64_t*>(dmeta),
+                       reinterpret_cast<const uint32_t*>(dmeta + 8 * (size_t)n_groups),
+                       static_cast<double*>(outbuf));
+    SDE_HIP(ctx, hipGetLastError());
+    SDE_HIP(ctx, hipMemcpyAsync(host_out, outbuf, (size_t)n_groups * 2 * sizeof(double), hipMemcpyDeviceToHost,
+                                stream));
+    SDE_HIP(ctx, hipStreamSynchronize(stream));
+    return SDE_OK;
+}
+
+}  // namespace sde

@@ -1,0 +1,243 @@
+// sde_api.hip -- the C ABI entry points: context life cycle, status text,
+// workspace management, validation shared by all integrators.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <new>
+
+#include "sde_internal.h"
+
+namespace sde {
+
+__global__ void zero_u32_kernel(uint32_t* p, size_t n)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+int ensure_ws(sde_ctx* ctx, int slot, size_t bytes, void** out)
+{
+    DevBuf& b = ctx->ws[slot];
+    if (b.bytes < bytes) {
+        if (b.ptr) {
+            SDE_HIP(ctx, hipDeviceSynchronize());
+            SDE_HIP(ctx, hipFree(b.ptr));
+            b.ptr = nullptr;
+            b.bytes = 0;
+            ctx->uploaded[slot].clear();
+        }
+        size_t cap = bytes < 4096 ? 4096 : bytes + bytes / 4;
+        if (hipMalloc(&b.ptr, cap) != hipSuccess) {
+            (void)hipGetLastError();
+            b.ptr = nullptr;
+            return fail(ctx, SDE_ERR_NOMEM, "workspace slot %d: cannot allocate %zu bytes", slot, cap);
+        }
+        b.bytes = cap;
+    }
+    *out = b.ptr;
+    return SDE_OK;
+}
+
+int upload(sde_ctx* ctx, int slot, int stage, const void* src, size_t bytes, hipStream_t stream)
+{
+    void* dst = nullptr;
+    int st = ensure_ws(ctx, slot, bytes, &dst);
+    if (st) return st;
+    std::vector<unsigned char>& have = ctx->uploaded[slot];
+    if (have.size() == bytes && std::memcmp(have.data(), src, bytes) == 0) return SDE_OK;
+    Staging& s = ctx->staging[stage];
+    if (s.pending) {
+        SDE_HIP(ctx, hipEventSynchronize(s.done));
+        s.pending = false;
+    }
+    if (s.bytes < bytes) {
+        if (s.host) SDE_HIP(ctx, hipHostFree(s.host));
+        s.host = nullptr;
+        s.bytes = 0;
+        size_t cap = bytes < 65536 ? 65536 : bytes + bytes / 4;
+        SDE_HIP(ctx, hipHostMalloc(&s.host, cap, hipHostMallocDefault));
+        s.bytes = cap;
+    }
+    if (!s.done) SDE_HIP(ctx, hipEventCreateWithFlags(&s.done, hipEventDisableTiming));
+    std::memcpy(s.host, src, bytes);
+    SDE_HIP(ctx, hipMemcpyAsync(dst, s.host, bytes, hipMemcpyHostToDevice, stream));
+    SDE_HIP(ctx, hipEventRecord(s.done, stream));
+    s.pending = true;
+    have.assign(static_cast<const unsigned char*>(src), static_cast<const unsigned char*>(src) + bytes);
+    return SDE_OK;
+}
+
+int ensure_counters(sde_ctx* ctx, size_t n)
+{
+    if (ctx->n_counters >= n) return SDE_OK;
+    if (ctx->counters) {
+        SDE_HIP(ctx, hipDeviceSynchronize());
+        SDE_HIP(ctx, hipFree(ctx->counters));
+        ctx->counters = nullptr;
+    }
+    size_t cap = n < 1024 ? 1024 : n;
+    if (hipMalloc(&ctx->counters, cap * sizeof(uint32_t)) != hipSuccess) {
+        (void)hipGetLastError();
+        ctx->n_counters = 0;
+        return fail(ctx, SDE_ERR_NOMEM, "cannot allocate %zu counters", cap);
+    }
+    SDE_HIP(ctx, hipMemset(ctx->counters, 0, cap * sizeof(uint32_t)));
+    ctx->n_counters = cap;
+    return SDE_OK;
+}
+
+int zero_counters(sde_ctx* ctx, size_t first, size_t n, hipStream_t stream)
+{
+    int st = ensure_counters(ctx, first + n);
+    if (st) return st;
+    const unsigned threads = 256;
+    const unsigned blocks = (unsigned)((n + threads - 1) / threads);
+    zero_u32_kernel<<<blocks, threads, 0, stream>>>(ctx->counters + first, n);
+    SDE_HIP(ctx, hipGetLastError());
+    return SDE_OK;
+}
+
+int sync_and_check(sde_ctx* ctx, hipStream_t stream)
+{
+    SDE_HIP(ctx, hipStreamSynchronize(stream));
+    int flag = 0;
+    SDE_HIP(ctx, hipMemcpy(&flag, ctx->flag, sizeof flag, hipMemcpyDeviceToHost));
+    if (flag) {
+        SDE_HIP(ctx, hipMemset(ctx->flag, 0, sizeof(int)));
+        return fail(ctx, SDE_ERR_NUMERIC, "the integrated state became NaN or Inf");
+    }
+    return SDE_OK;
+}
+
+}  // namespace sde
+
+using namespace sde;
+
+extern "C" {
+
+int sde_create(int hip_device, sde_ctx** out)
+{
+    if (!out) return SDE_ERR_INVALID;
+    *out = nullptr;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || hip_device < 0 || hip_device >= n) {
+        (void)hipGetLastError();
+        return SDE_ERR_DEVICE;
+    }
+    if (hipSetDevice(hip_device) != hipSuccess) return SDE_ERR_DEVICE;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, hip_device) != hipSuccess) return SDE_ERR_DEVICE;
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) return SDE_ERR_UNSUPPORTED;
+    sde_ctx* ctx = new (std::nothrow) sde_ctx();
+    if (!ctx) return SDE_ERR_NOMEM;
+    ctx->device = hip_device;
+    ctx->n_cu = prop.multiProcessorCount;
+    ctx->arch = prop.gcnArchName;
+    if (hipMalloc(&ctx->flag, sizeof(int)) != hipSuccess || hipMemset(ctx->flag, 0, sizeof(int)) != hipSuccess ||
+        ensure_counters(ctx, 1024) != SDE_OK) {
+        sde_destroy(ctx);
+        return SDE_ERR_NOMEM;
+    }
+    *out = ctx;
+    return SDE_OK;
+}
+
+void sde_destroy(sde_ctx* ctx)
+{
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (auto& b : ctx->ws)
+        if (b.ptr) (void)hipFree(b.ptr);
+    for (auto& s : ctx->staging) {
+        if (s.host) (void)hipHostFree(s.host);
+        if (s.done) (void)hipEventDestroy(s.done);
+    }
+    if (ctx->flag) (void)hipFree(ctx->flag);
+    if (ctx->counters) (void)hipFree(ctx->counters);
+    delete ctx;
+}
+
+const char* sde_strerror(int status)
+{
+    switch (status) {
+    case SDE_OK: return "ok";
+    case SDE_ERR_INVALID: return "invalid argument";
+    case SDE_ERR_NOMEM: return "out of device memory";
+    case SDE_ERR_DEVICE: return "HIP runtime error";
+    case SDE_ERR_UNSUPPORTED: return "unsupported";
+    case SDE_ERR_NUMERIC: return "state became NaN or Inf";
+    default: return "unknown status";
+    }
+}
+
+const char* sde_last_error(const sde_ctx* ctx) { return ctx ? ctx->last_error.c_str() : ""; }
+
+int sde_check(sde_ctx* ctx)
+{
+    if (!ctx) return SDE_ERR_INVALID;
+    if (hipSetDevice(ctx->device) != hipSuccess) return fail(ctx, SDE_ERR_DEVICE, "hipSetDevice failed");
+    if (hipDeviceSynchronize() != hipSuccess) return fail(ctx, SDE_ERR_DEVICE, "hipDeviceSynchronize failed");
+    return sync_and_check(ctx, nullptr);
+}
+
+int sde_jj_integrate(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run,
+                     float* theta, int32_t* winding, float* v, double* acc, double* point_sums,
+                     void* hip_stream)
+{
+    if (!ctx) return SDE_ERR_INVALID;
+    ctx->last_error.clear();
+    try {
+        return jj_integrate_impl(ctx, pts, n_pts, run, theta, winding, v, acc, point_sums,
+                                 static_cast<hipStream_t>(hip_stream));
+    } catch (...) {
+        return fail(ctx, SDE_ERR_NOMEM, "host allocation failed");
+    }
+}
+
+int sde_kuramoto_integrate(sde_ctx* ctx, const sde_kuramoto_desc* desc, const sde_run* run,
+                           float* phi, const float* omega, const float* K, double* r_samples,
+                           void* hip_stream)
+{
+    if (!ctx) return SDE_ERR_INVALID;
+    ctx->last_error.clear();
+    try {
+        return kuramoto_impl(ctx, desc, run, phi, omega, K, r_samples,
+                             static_cast<hipStream_t>(hip_stream));
+    } catch (...) {
+        return fail(ctx, SDE_ERR_NOMEM, "host allocation failed");
+    }
+}
+
+int sde_observables(sde_ctx* ctx, int kind, const void* dev_in, const uint32_t* counts,
+                    uint32_t n_groups, double* host_out, void* hip_stream)
+{
+    if (!ctx) return SDE_ERR_INVALID;
+    ctx->last_error.clear();
+    try {
+        return observables_impl(ctx, kind, dev_in, counts, n_groups, host_out,
+                                static_cast<hipStream_t>(hip_stream));
+    } catch (...) {
+        return fail(ctx, SDE_ERR_NOMEM, "host allocation failed");
+    }
+}
+
+int sde_debug_philox(sde_ctx* ctx, uint64_t seed, uint32_t tag, uint32_t a, uint32_t b,
+                     uint64_t ctr0_first, uint64_t n_blocks, uint32_t* dev_out, void* hip_stream)
+{
+    if (!ctx) return SDE_ERR_INVALID;
+    ctx->last_error.clear();
+    return debug_philox_impl(ctx, seed, tag, a, b, ctr0_first, n_blocks, dev_out,
+                             static_cast<hipStream_t>(hip_stream));
+}
+
+int sde_debug_gauss(sde_ctx* ctx, uint64_t seed, uint32_t tag, uint32_t a, uint32_t b,
+                    uint64_t n_first, uint64_t count, float* dev_out, void* hip_stream)
+{
+    if (!ctx) return SDE_ERR_INVALID;
+    ctx->last_error.clear();
+    return debug_gauss_impl(ctx, seed, tag, a, b, n_first, count, dev_out,
+                            static_cast<hipStream_t>(hip_stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,116 @@
+// sde_internal.h -- host-side context and helpers shared by the library's
+// translation units (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sde.h"
+
+namespace sde {
+
+// A device buffer that only grows; freed with the context.
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+};
+
+// A pinned host staging buffer whose last upload is fenced by an event, so
+// it is never overwritten while an asynchronous copy may still read it.
+struct Staging {
+    void* host = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+    bool pending = false;
+};
+
+struct TuneEntry;
+
+}  // namespace sde
+
+struct sde_ctx {
+    int device = 0;
+    int n_cu = 0;
+    int xcds = 8;
+    std::string arch;
+    std::string last_error;
+    int* flag = nullptr;          // device: nonzero once a state became NaN/Inf
+    uint32_t* counters = nullptr; // device: work-queue counters and barrier words
+    size_t n_counters = 0;
+    sde::DevBuf ws[16];           // device workspaces, by slot (see sde::Slot)
+    sde::Staging staging[4];
+    std::vector<unsigned char> uploaded[16];  // host copy of what each slot holds
+};
+
+namespace sde {
+
+enum Slot {
+    kSlotJJPoints = 0,
+    kSlotJJItems = 1,
+    kSlotJJLut = 2,
+    kSlotJJPartials = 3,
+    kSlotObs = 4,
+    kSlotKuraPartials = 5,
+    kSlotKuraWork = 6,
+    kSlotDenseA = 7,
+    kSlotDenseB = 8,
+    kSlotDenseOut = 9,
+    kSlotMisc = 10,
+};
+
+// Status helpers -----------------------------------------------------------
+inline int fail(sde_ctx* ctx, int status, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+inline int fail(sde_ctx* ctx, int status, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->last_error = buf;
+    return status;
+}
+
+#define SDE_HIP(ctx, call)                                                                   \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return ::sde::fail((ctx), SDE_ERR_DEVICE, "%s failed: %s", #call,                \
+                               hipGetErrorString(e_));                                       \
+    } while (0)
+
+// Grows workspace slot `slot` to at least `bytes`; returns its pointer or null.
+int ensure_ws(sde_ctx* ctx, int slot, size_t bytes, void** out);
+// Copies `bytes` from host `src` into workspace slot `slot` on `stream`
+// unless the slot already holds exactly these bytes.  Staging buffer
+// `stage` carries the asynchronous copy.
+int upload(sde_ctx* ctx, int slot, int stage, const void* src, size_t bytes, hipStream_t stream);
+// Resets `n` device counters starting at `first` to zero with a kernel
+// (stream-ordered, safe under graph capture).
+int zero_counters(sde_ctx* ctx, size_t first, size_t n, hipStream_t stream);
+int ensure_counters(sde_ctx* ctx, size_t n);
+// Synchronizes `stream` and reports SDE_ERR_NUMERIC if the NaN flag is set.
+int sync_and_check(sde_ctx* ctx, hipStream_t stream);
+
+inline bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// Launchers implemented in the kernel translation units.
+int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run,
+                      float* theta, int32_t* winding, float* v, double* acc, double* point_sums,
+                      hipStream_t stream);
+int debug_philox_impl(sde_ctx* ctx, uint64_t seed, uint32_t tag, uint32_t a, uint32_t b,
+                      uint64_t c0, uint64_t n, uint32_t* out, hipStream_t stream);
+int debug_gauss_impl(sde_ctx* ctx, uint64_t seed, uint32_t tag, uint32_t a, uint32_t b,
+                     uint64_t n0, uint64_t n, float* out, hipStream_t stream);
+int observables_impl(sde_ctx* ctx, int kind, const void* in, const uint32_t* counts,
+                     uint32_t n_groups, double* host_out, hipStream_t stream);
+int kuramoto_impl(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, float* phi,
+                  const float* omega, const float* K, double* r_samples, hipStream_t stream);
+
+}  // namespace sde

@@ -18,3 +18,22 @@ def orc():
     import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(scope="session")
+def gpu():
+    """(sde module, context handle, torch device) on cuda:0."""
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0903_3852_amd as sde
+    ctx = sde.sde_create(0)
+    yield sde, ctx, torch.device("cuda:0")
+    torch.cuda.synchronize()
+    sde.sde_destroy(ctx)
+
+
+def rel_err(got, ref):
+    """|got - ref| / max(|ref|, 1), elementwise."""
+    import numpy as np
+    return np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
