@@ -1,17 +1,22 @@
 """Benchmark of the SDE-ensemble hot path on one MI355X.
 
-Default workload: the Josephson-junction (f, D) scan -- 128 x 128 points
-(f = 0.5 i/127, D = 10^(-4 + 3 j/127)), 1024 paths per point, 2*10^5
-stochastic-Heun steps of dt = 2 pi/omega/200 (10^5 transient), FP32 state
-with FP64 <v> accumulation, all 16384 points in one persistent launch.
-A "step" of this benchmark is one such full integration (3.36e12
-path-steps); inputs (parameters) are resident before timing starts.
+Default workload (--workload jj_scan): the Josephson-junction (f, D) scan --
+128 x 128 points (f = 0.5 i/127, D = 10^(-4 + 3 j/127)), 1024 paths per
+point, 2*10^5 stochastic-Heun steps of dt = 2 pi/omega/200 (10^5
+transient), FP32 state with FP64 <v> accumulation, all 16384 points in one
+persistent launch.  A benchmark "step" is one such full integration
+(3.36e12 path-steps) with the parameters resident before timing starts.
 
-Prints one JSON line with the throughput in path-steps/s, the ALU roofline
-fraction of the integration kernel and the FP64 CPU oracle timed on a
-bounded sample of the same workload.
+The other workloads (--workload kuramoto_*) time the Kuramoto kernels on
+their own configurations; the default run also reports short measurements
+of them under "kuramoto".
+
+Prints one JSON line: throughput, the roofline fraction of the dominant
+kernel (timed with HIP events on the stream it runs on) and the FP64 CPU
+oracle timed on a bounded sample of the same workload.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,61 +30,217 @@ sys.path.insert(0, ROOT)
 import sde_inputs  # noqa: E402
 
 # ---------------------------------------------------------------------------
-# ALU roofline of the Josephson-junction kernel.
-# Peak: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 full-rate VALU lane
-# slots per second (a wave64 VALU instruction occupies its SIMD for 4 cycles;
-# packed FP32 forms are not used).  Algorithmic cost of one Heun path-step of
-# Eq. 1, counted from the method (not from the compiled code), each operation
-# weighted by its issue cost in full-rate slots:
-#   Philox4x32-10 / 4 steps: 20 wide 32x32->64 multiplies, 40 xor
-#   Box-Muller / 2 steps:    2 shifts, 1 add, 2 int->float, 2 scale,
-#                            1 log2, 1 mul, 1 sqrt, 1 sin, 1 cos, 2 mul
-#   Heun step (Alg. 2):      2 sin + 13 add/mul/fma (drift twice, predictor,
-#                            corrector, window sum)
-#   phase wrap / 4 steps:    floor, sub, convert, add
+# ALU roofline.  Peak: the FP32 vector rate, 256 CUs x 128 FP32 lanes x
+# 2.4 GHz = 7.86e13 FMA lane-operations per second (157.3 TFLOP/s).  On
+# gfx950 a 32-bit integer operation (xor, shift, add, v_mad_u64_u32,
+# conversions) issues at half that rate and a transcendental (v_sin, v_cos,
+# v_log, v_sqrt) at a quarter, so algorithmic work is counted in FP32-FMA
+# equivalents: FP32 add/mul/fma = 1, integer op or FP64 op = 2,
+# transcendental = 4.
 # ---------------------------------------------------------------------------
-PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
-W_MUL64 = 4.0   # v_mad_u64_u32 issue cost in full-rate slots
-W_TRANS = 4.0   # v_sin/v_cos/v_log/v_sqrt issue cost in full-rate slots
+PEAK_FMA_LANES = 256 * 128 * 2.4e9
+PEAK_MFMA_16BIT = 2.5e15           # dense bf16 / fp16 MFMA FLOP/s
+W_INT = 2.0
+W_TRANS = 4.0
+# Noise per path (or oscillator) and step: Philox4x32-10 (20 wide
+# multiplies + 40 xor per four steps) and Box-Muller (per two Gaussians 5
+# integer, 5 FP32 operations, log2, sqrt, sin, cos).
+NOISE_OPS = (20 + 40) * W_INT / 4 + (5 * W_INT + 5 + 4 * W_TRANS) / 2
 
 
-def jj_slots_per_path_step(w_mul=W_MUL64, w_trans=W_TRANS):
-    philox = (20 * w_mul + 40) / 4
-    box_muller = (2 + 1 + 2 + 2 + 1 + 2 + 3 * w_trans + w_trans) / 2
-    heun = 13 + 2 * w_trans
-    wrap = 4 / 4
-    return philox + box_muller + heun + wrap
+def jj_ops_per_path_step():
+    """One stochastic-Heun path-step of Eq. 1: noise, 2 sin + 13 FP32 (two
+    drift evaluations, predictor, corrector, window sum), phase wrap per four
+    steps (floor, sub, convert, add)."""
+    return NOISE_OPS + 13 + 2 * W_TRANS + (2 + 2 * W_INT) / 4
 
 
 def jj_flops_per_path_step():
-    """FP32 floating-point operations (transcendentals count 1)."""
-    return (2 + 1 + 2 + 4 + 2) / 2 + 13 + 2 + 1
+    """FP32 floating-point operations (a transcendental counts 1)."""
+    return (5 + 4) / 2 + 13 + 2 + 2 / 4
 
 
-def cpu_baseline(seed, target_s):
-    """FP64 oracle on 16 scan points (4 x 4 sub-grid) x 256 paths x the full
-    2*10^5 steps, all host threads."""
+def mf_ops_per_osc_step(heun):
+    """Mean-field Kuramoto per oscillator-step: noise; per stage sin + cos,
+    two FP64 conversions and adds, drift (4 FP32), update (2 FP32); wrap."""
+    stage = 2 * W_TRANS + 2 * W_INT + 2 * W_INT + 4 + 2
+    return NOISE_OPS + stage * (2 if heun else 1) + 2
+
+
+# HBM traffic of the JJ kernel per launch, from profiles/jj_scan_hbm_counters.md
+# (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, copy-calibrated).  Only valid for
+# the kernel source it was measured on.
+JJ_TRAFFIC_BYTES = (9279 + 6697) * 1024
+JJ_TRAFFIC_SOURCE_SHA1 = "7a996f3f1f409908a4493fa4cfd990d0a300b9da"
+
+
+def _jj_source_sha1():
+    h = hashlib.sha1()
+    for f in ("jj.hip", "device_common.h"):
+        with open(os.path.join(ROOT, "paper_0903_3852_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def cpu_baseline_jj(seed, target_s):
+    """FP64 oracle on 16 scan points (4 x 4 sub-grid) x 1024 paths x the full
+    2*10^5 steps (fewer paths if this host would take longer than target_s),
+    all host threads.  Returns (baseline record, oracle result, qs, paths)."""
     import oracle
     qs = [128 * i + j for i in (0, 42, 85, 127) for j in (0, 42, 85, 127)]
-    n_paths = 256
-    pts = sde_inputs.jj_scan(n_paths=n_paths, indices=qs)
+    n_paths = 1024
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-    # scale the sample down if this host is slow (about target_s seconds)
-    probe = [dict(pts[0], n_paths=64, n_steps=20000, n_transient=10000)]
+    probe = [sde_inputs.jj_scan(n_paths=64, n_steps=20000, n_transient=10000, indices=[qs[0]])[0]]
     t0 = time.perf_counter()
     oracle.jj_integrate(probe, seed, point_ids=[qs[0]], n_threads=threads)
     rate_est = 64 * 20000 / (time.perf_counter() - t0)
-    full = len(qs) * n_paths * 200000
-    if full / rate_est > target_s:
-        n_paths = max(16, int(n_paths * target_s * rate_est / full) // 16 * 16)
-        pts = sde_inputs.jj_scan(n_paths=n_paths, indices=qs)
+    if len(qs) * n_paths * 200000 / rate_est > target_s:
+        n_paths = max(16, int(target_s * rate_est / (len(qs) * 200000)) // 16 * 16)
+    pts = sde_inputs.jj_scan(n_paths=n_paths, indices=qs)
     t0 = time.perf_counter()
-    oracle.jj_integrate(pts, seed, point_ids=qs, n_threads=threads)
+    ref = oracle.jj_integrate(pts, seed, point_ids=qs, n_threads=threads)
     dt = time.perf_counter() - t0
     work = len(qs) * n_paths * 200000
-    return {"value": work / dt, "unit": "path-steps/s", "cores": threads, "kind": "oracle",
-            "sample": f"{len(qs)} scan points (4x4 sub-grid) x {n_paths} paths x 2e5 Heun steps, "
-                      f"FP64, {dt:.1f} s"}
+    rec = {"value": work / dt, "unit": "path-steps/s", "cores": threads, "kind": "oracle",
+           "sample": f"{len(qs)} scan points (4x4 sub-grid) x {n_paths} paths x 2e5 Heun steps, "
+                     f"FP64, {dt:.1f} s"}
+    return rec, ref, qs, n_paths
+
+
+def bench_jj(args, sde, torch, dev):
+    seed = sde_inputs.seed_of(2)
+    n_steps = args.model_steps
+    pts = sde.make_points(sde_inputs.jj_scan(n_steps=n_steps, n_transient=n_steps // 2))
+    path_steps = 16384 * 1024 * n_steps
+    ps = torch.empty((16384, 2), dtype=torch.float64, device=dev)
+    ctx = sde.sde_create(0)
+    run = sde.make_run(seed)
+    stream = torch.cuda.current_stream()
+    for w in range(args.warmup):
+        sde.sde_jj_integrate(ctx, pts, run, point_sums=ps)
+        torch.cuda.synchronize()
+        print(f"warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
+    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        starts[k].record(stream)
+        sde.sde_jj_integrate(ctx, pts, run, point_sums=ps)
+        ends[k].record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    sde.sde_check(ctx)
+    sde.sde_destroy(ctx)
+    ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
+    kernel_s = float(np.mean(ms)) / 1e3
+    sums = ps.cpu().numpy()
+    assert np.all(np.isfinite(sums))
+    print(f"timed {args.steps} steps: {ms} ms per step, wall {wall:.2f} s", file=sys.stderr, flush=True)
+    ops = jj_ops_per_path_step()
+    achieved = ops * path_steps / kernel_s
+    traffic = JJ_TRAFFIC_BYTES if (_jj_source_sha1() == JJ_TRAFFIC_SOURCE_SHA1 and n_steps == 200000) else None
+    out = {
+        "metric": "path-steps/s (Josephson-junction scan, stochastic Heun)",
+        "value": path_steps * args.steps / wall, "unit": "path-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "jj_scan", "points": 16384, "paths_per_point": 1024,
+                   "heun_steps": n_steps, "transient": n_steps // 2, "dt": "2pi/omega/200",
+                   "path_steps_per_step": path_steps},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FMA_LANES / 1e12,
+                     "unit": "T FP32-FMA-equivalent lane-ops/s", "frac": achieved / PEAK_FMA_LANES,
+                     "traffic": traffic, "ops_per_path_step": ops,
+                     "kernel": "jj_persistent_kernel<2, HEUN, inertial>"},
+        "fp32_tflops": jj_flops_per_path_step() * path_steps / kernel_s / 1e12,
+        "kernel_ms": float(np.mean(ms)),
+    }
+    if not args.no_cpu_baseline:
+        cb, ref, qs, n_paths = cpu_baseline_jj(seed, args.cpu_seconds)
+        out["cpu_baseline"] = cb
+        out["gpu_over_cpu"] = out["value"] / cb["value"]
+        if n_steps == 200000:
+            # parity of the timed run at the sample points: the GPU mean over
+            # 1024 paths against the oracle's mean over the first n_paths of
+            # the same paths (same Philox streams)
+            g = sums[qs, 0] / 1024
+            o = ref["point_sums"][:, 0] / n_paths
+            var_o = np.maximum(ref["point_sums"][:, 1] / n_paths - o * o, 0.0)
+            se = np.sqrt(var_o / n_paths + var_o / 1024)
+            ratio = np.abs(g - o) / (3 * se + 1e-4)
+            out["parity"] = {"points": len(qs), "max_abs_diff_vmean": float(np.abs(g - o).max()),
+                             "max_diff_over_3se_plus_1e-4": float(ratio.max()), "ok": bool(ratio.max() <= 1.0)}
+    return out
+
+
+KURA = {
+    "kuramoto_mf": dict(cfg="uniform", coupling=0, scheme=0, steps=100000),
+    "kuramoto_mf_em": dict(cfg="uniform", coupling=0, scheme=1, steps=100000),
+    "kuramoto_tiled": dict(cfg="uniform", coupling=1, scheme=0, steps=100),
+    "kuramoto_dense_fp32": dict(cfg="dense", coupling=2, scheme=0, steps=2000),
+    "kuramoto_dense_bf16x3": dict(cfg="dense", coupling=3, scheme=0, steps=20000),
+    "kuramoto_dense_fp16x3": dict(cfg="dense", coupling=4, scheme=0, steps=20000),
+}
+
+
+def bench_kuramoto(name, args, sde, torch, dev, steps=None, reps=1):
+    spec = KURA[name]
+    cfg = sde_inputs.kuramoto_uniform() if spec["cfg"] == "uniform" else sde_inputs.kuramoto_dense()
+    N, R = cfg["N"], cfg["R"]
+    n = steps or spec["steps"]
+    om = torch.from_numpy(cfg["omega"]).to(dev)
+    Kt = torch.from_numpy(cfg["Kmat"]).to(dev) if spec["coupling"] >= 2 else None
+    ph = torch.empty((R, N), dtype=torch.float32, device=dev)
+    rs = torch.zeros((R, n // 100 + 1), dtype=torch.float64, device=dev)
+    ctx = sde.sde_create(0)
+    desc = sde.sde_kuramoto_desc(N, R, cfg["K"], cfg["D"], cfg["dt"], n, spec["coupling"], 0)
+    run = sde.make_run(cfg["seed"], scheme=spec["scheme"])
+    stream = torch.cuda.current_stream()
+    # warm-up on a short run (kernel load, workspace)
+    wdesc = sde.sde_kuramoto_desc(N, R, cfg["K"], cfg["D"], cfg["dt"], min(n, 8), spec["coupling"], 0)
+    sde.sde_kuramoto_integrate(ctx, wdesc, run, ph, om, Kt, None)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record(stream)
+        sde.sde_kuramoto_integrate(ctx, desc, run, ph, om, Kt, rs)
+        e.record(stream)
+        torch.cuda.synchronize()
+        times.append(s.elapsed_time(e) / 1e3)
+    sde.sde_check(ctx)
+    sde.sde_destroy(ctx)
+    t = float(np.mean(times))
+    osc_steps = N * R * n
+    heun = spec["scheme"] == 0
+    rec = {"workload": name, "N": N, "R": R, "steps": n, "scheme": "heun" if heun else "euler",
+           "seconds": t, "osc_steps_per_s": osc_steps / t,
+           "r_final_mean": float(rs.cpu().numpy()[:, -1].mean())}
+    if spec["coupling"] == 0:
+        ops = mf_ops_per_osc_step(heun)
+        rec["roofline"] = {"bound": "alu", "achieved": ops * osc_steps / t / 1e12,
+                           "peak": PEAK_FMA_LANES / 1e12, "unit": "T FP32-FMA-equivalent lane-ops/s",
+                           "frac": ops * osc_steps / t / PEAK_FMA_LANES, "traffic": None}
+        rec["us_per_stage"] = t / (n * (2 if heun else 1)) * 1e6
+    elif spec["coupling"] == 1:
+        pairs = float(N) * N * R * n * (2 if heun else 1)
+        ops = 1 + W_TRANS + 1
+        rec["pairs_per_s"] = pairs / t
+        rec["roofline"] = {"bound": "alu", "achieved": ops * pairs / t / 1e12, "peak": PEAK_FMA_LANES / 1e12,
+                           "unit": "T FP32-FMA-equivalent lane-ops/s", "frac": ops * pairs / t / PEAK_FMA_LANES,
+                           "traffic": None}
+    else:
+        gemm_flop = 2.0 * N * N * 2 * R * n * (2 if heun else 1)
+        if spec["coupling"] == 2:
+            rec["roofline"] = {"bound": "alu", "achieved": gemm_flop / t / 1e12, "peak": 2 * PEAK_FMA_LANES / 1e12,
+                               "unit": "TFLOP/s", "frac": gemm_flop / t / (2 * PEAK_FMA_LANES), "traffic": None}
+        else:
+            executed = 3 * gemm_flop
+            rec["gemm_equivalent_tflops"] = gemm_flop / t / 1e12
+            rec["roofline"] = {"bound": "mfma", "achieved": executed / t / 1e12, "peak": PEAK_MFMA_16BIT / 1e12,
+                               "unit": "TFLOP/s", "frac": executed / t / PEAK_MFMA_16BIT, "traffic": None}
+    return rec
 
 
 def main():
@@ -87,10 +248,14 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="jj_scan", choices=["jj_scan"] + sorted(KURA))
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kuramoto", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--model-steps", type=int, default=200000,
                     help="Heun steps per path (the workload uses 2e5; smaller only for profiling)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the JJ scan would shard "
@@ -103,61 +268,20 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
-    seed = sde_inputs.seed_of(2)
-    n_steps = args.model_steps
-    pts = sde.make_points(sde_inputs.jj_scan(n_steps=n_steps, n_transient=n_steps // 2))
-    path_steps = 16384 * 1024 * n_steps
-    ps = torch.empty((16384, 2), dtype=torch.float64, device=dev)
-    ctx = sde.sde_create(0)
-    run = sde.make_run(seed)
-    stream = torch.cuda.current_stream()
-
-    for w in range(args.warmup):
-        sde.sde_jj_integrate(ctx, pts, run, point_sums=ps)
+    if args.workload == "jj_scan":
+        out = bench_jj(args, sde, torch, dev)
+        if not args.no_kuramoto:
+            out["kuramoto"] = [bench_kuramoto(w, args, sde, torch, dev, steps=s)
+                               for w, s in [("kuramoto_mf", 20000), ("kuramoto_dense_bf16x3", 2000)]]
+    else:
+        out = bench_kuramoto(args.workload, args, sde, torch, dev, reps=args.steps)
+    if args.calibrate_copy:
+        x = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        y = torch.empty_like(x)
+        for _ in range(3):
+            y.copy_(x)
         torch.cuda.synchronize()
-        print(f"warmup {w + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-
-    starts = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    ends = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps)]
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        starts[k].record(stream)
-        sde.sde_jj_integrate(ctx, pts, run, point_sums=ps)
-        ends[k].record(stream)
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    sde.sde_check(ctx)
-    ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
-    kernel_s = float(np.mean(ms)) / 1e3
-    sums = ps.cpu().numpy()
-    assert np.all(np.isfinite(sums))
-    print(f"timed {args.steps} steps: {ms} ms per step, wall {wall:.2f} s", file=sys.stderr, flush=True)
-
-    value = path_steps * args.steps / wall
-    slots = jj_slots_per_path_step()
-    achieved = slots * path_steps / kernel_s / 1e12
-    out = {
-        "metric": "path-steps/s (Josephson-junction scan, stochastic Heun)",
-        "value": value, "unit": "path-steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "jj_scan", "points": 16384, "paths_per_point": 1024,
-                   "heun_steps": n_steps, "transient": n_steps // 2, "dt": "2pi/omega/200",
-                   "path_steps_per_step": path_steps},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_SLOTS / 1e12,
-                     "unit": "T VALU-slots/s", "frac": achieved * 1e12 / PEAK_SLOTS,
-                     "traffic": None},
-        "fp32_tflops": jj_flops_per_path_step() * path_steps / kernel_s / 1e12,
-        "kernel_ms": float(np.mean(ms)),
-        "mean_v_range": [float(sums[:, 0].min() / 1024), float(sums[:, 0].max() / 1024)],
-    }
-    sde.sde_destroy(ctx)
-    if not args.no_cpu_baseline:
-        cb = cpu_baseline(seed, args.cpu_seconds)
-        out["cpu_baseline"] = cb
-        out["gpu_over_cpu"] = value / cb["value"]
+        out["copy_calibration_bytes"] = 1 << 30
     print(json.dumps(out), flush=True)
 
 

@@ -1,15 +1,551 @@
-// kuramoto.hip -- noisy Kuramoto model (Eq. 2): host dispatch.
+// kuramoto.hip -- the noisy Kuramoto model (Eq. 2 with gamma = 1):
+//   dphi_i = [omega_i + sum_j K_ij sin(phi_j - phi_i)] dt + sqrt(2 D) dW_i,
+// R independent realizations of N oscillators, stochastic Heun (Alg. 2) or
+// Euler-Maruyama, phases kept in revolutions theta = phi / 2 pi in [0, 1).
+//
+// Uniform coupling K_ij = K/N is evaluated two ways:
+//  * MEANFIELD (Eq. 3): per realization and stage only two sums, S = sum_j
+//    sin phi_j and C = sum_j cos phi_j, then F_i = omega_i + (K/N)(cos phi_i S
+//    - sin phi_i C).  One cooperative persistent launch runs every step: the
+//    G workgroups of a realization hold its oscillators in registers, write
+//    FP64 partial sums, meet at a per-realization barrier, and read all G
+//    partials in a fixed order (bitwise reproducible).  Workgroups are mapped
+//    so that each realization sits on one XCD (workgroups are dealt to the 8
+//    XCDs round robin), keeping its barrier traffic in that XCD's L2.
+//  * TILED (Alg. 3, Fig. 3): all N^2 terms sin(2 pi (theta_j - theta_i)),
+//    theta_j staged through LDS in tiles and read by every lane (broadcast),
+//    one hardware v_sin_f32 per pair.  One launch per Heun stage; the stage
+//    boundary is the global synchronization.
+// The noise of oscillator i in realization r at step n is component n & 3 of
+// the Box-Muller Gaussians of Philox(ctr = (n >> 2, i, r, NOISE)).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <cmath>
+
+#include "device_common.h"
+#include "kuramoto_common.h"
 #include "sde_internal.h"
 
 namespace sde {
 
-int kuramoto_impl(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, float* phi,
-                  const float* omega, const float* K, double* r_samples, hipStream_t stream)
+// ---------------------------------------------------------------- MF ------
+constexpr int kMFThreads = 1024;
+
+struct MFArgs {
+    float* theta;            // [R][N] revolutions, in/out (this launch's realizations)
+    const float* omega;      // [N]
+    double* r_samples;       // [R][n_samples] or null
+    double* partials;        // [2 slots][R][G][2]
+    uint32_t* barrier;       // [R] arrival counters, zero at launch
+    int* flag;               // error flag (NaN state, or a barrier that timed out)
+    uint32_t N, R, G, M;
+    uint32_t r_base;         // global index of this launch's first realization
+    uint64_t step0, n_steps, n_samples;
+    uint32_t key0, key1;
+    float omega_scale;       // dt / (2 pi) (revolutions per unit of F)
+    float hdt2pi;            // dt / (4 pi)
+    float kn;                // K / N
+    float c2;                // -2 ln2 sigma^2, sigma = sqrt(2 D dt) / (2 pi)
+    int32_t init_from_state;
+    int32_t xcd_map;         // 1: realization r lives on XCD r / (R / 8)
+    uint32_t spin_limit;     // barrier give-up bound (iterations of s_sleep)
+};
+
+// Publish this workgroup's FP64 partial sums (s, c) for stage `epoch` of
+// realization r and wait until all G workgroups of r have published theirs.
+// The partials are stored and later read with agent-scope atomics; the
+// arrival counter is incremented with release and polled with acquire
+// semantics.  One lane does the waiting.  Returns false if the wait exceeded
+// the spin bound (the error flag is then set and the kernel winds down).
+__device__ __forceinline__ bool publish_and_wait(const MFArgs& A, uint32_t r, uint32_t w, uint32_t epoch,
+                                                 double s, double c, double* lds, int* lds_ok)
 {
-    (void)d; (void)run; (void)phi; (void)omega; (void)K; (void)r_samples; (void)stream;
-    return fail(ctx, SDE_ERR_UNSUPPORTED, "Kuramoto integration not built yet");
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    s = wave_sum(s);
+    c = wave_sum(c);
+    if (lane == 0) {
+        lds[2 * wid] = s;
+        lds[2 * wid + 1] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double S = 0.0, C = 0.0;
+#pragma unroll 1
+        for (int k = 0; k < kMFThreads / kWave; ++k) {
+            S += lds[2 * k];
+            C += lds[2 * k + 1];
+        }
+        double* mine = A.partials + (((uint64_t)(epoch & 1u) * A.R + r) * A.G + w) * 2;
+        __hip_atomic_store(mine, S, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(mine + 1, C, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint32_t target = (epoch + 1) * A.G;
+        __hip_atomic_fetch_add(A.barrier + r, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        uint32_t spins = 0;
+        int ok = 1;
+        while (__hip_atomic_load(A.barrier + r, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > A.spin_limit) {
+                ok = 0;
+                atomicOr(A.flag, 2);
+                break;
+            }
+        }
+        *lds_ok = ok;
+    }
+    __syncthreads();
+    return *lds_ok != 0;
+}
+
+template <int OPT, int SCHEME>
+__global__ __launch_bounds__(kMFThreads, 1) void kuramoto_mf_kernel(MFArgs A)
+{
+    __shared__ double lds[2 * kMFThreads / kWave];
+    __shared__ int lds_ok;
+    // workgroup -> (realization r, slice w)
+    uint32_t r, w;
+    if (A.xcd_map) {
+        const uint32_t x = blockIdx.x & 7u, l = blockIdx.x >> 3, per = A.R >> 3;
+        r = x * per + l / A.G;
+        w = l % A.G;
+    } else {
+        r = blockIdx.x / A.G;
+        w = blockIdx.x % A.G;
+    }
+    const uint32_t N = A.N;
+    float th[OPT], F1[OPT];
+    uint32_t idx[OPT];
+    bool live[OPT];
+#pragma unroll
+    for (int k = 0; k < OPT; ++k) {
+        idx[k] = (w * OPT + k) * kMFThreads + threadIdx.x;
+        live[k] = idx[k] < N;
+        const uint32_t i = live[k] ? idx[k] : 0u;
+        if (A.init_from_state) {
+            th[k] = live[k] ? A.theta[(uint64_t)r * N + i] : 0.f;
+        } else {
+            const U4 x = philox4x32_10(U4{0u, i, A.r_base + r, (uint32_t)SDE_TAG_INIT}, A.key0, A.key1);
+            th[k] = (float)(x.x >> 8) * 0x1p-24f;
+        }
+    }
+
+    uint32_t epoch = 0;
+    const double invN = 1.0 / (double)N;
+    // sums of sin and cos over the realization at phases t[]; FP32 terms,
+    // FP64 accumulation
+    auto reduce = [&](const float (&t)[OPT], float& Sf, float& Cf, double& Sd, double& Cd) -> bool {
+        double s = 0.0, c = 0.0;
+#pragma unroll
+        for (int k = 0; k < OPT; ++k) {
+            if (live[k]) {
+                s += (double)sin_rev(t[k]);
+                c += (double)cos_rev(t[k]);
+            }
+        }
+        if (!publish_and_wait(A, r, w, epoch, s, c, lds, &lds_ok)) return false;
+        const double* all = A.partials + ((uint64_t)(epoch & 1u) * A.R + r) * A.G * 2;
+        ++epoch;
+        double S = 0.0, C = 0.0;
+#pragma unroll 1
+        for (uint32_t g = 0; g < A.G; ++g) {
+            S += __hip_atomic_load(all + 2 * g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            C += __hip_atomic_load(all + 2 * g + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        Sd = S;
+        Cd = C;
+        Sf = (float)S;
+        Cf = (float)C;
+        return true;
+    };
+
+    uint64_t n = A.step0;
+    const uint64_t n_end = A.step0 + A.n_steps;
+    uint64_t local = 0;
+    bool ok = true;
+    float g[OPT][4];                 // sigma * Gaussians of the current block of 4 steps
+    uint64_t gblk = ~0ull;
+    for (;;) {
+        // one stage-1 reduction at theta_n: the drift and, every M steps, r
+        float S, C;
+        double Sd, Cd;
+        if (!(ok = reduce(th, S, C, Sd, Cd))) break;
+        if (A.r_samples && local % A.M == 0 && w == 0 && threadIdx.x == 0)
+            A.r_samples[(uint64_t)r * A.n_samples + local / A.M] = std::sqrt(Sd * Sd + Cd * Cd) * invN;
+        if (n == n_end) break;
+        if ((n >> 2) != gblk) {
+            gblk = n >> 2;
+#pragma unroll
+            for (int k = 0; k < OPT; ++k)
+                gauss4_scaled(U4{(uint32_t)gblk, idx[k], A.r_base + r, (uint32_t)SDE_TAG_NOISE}, A.key0, A.key1,
+                              A.c2, g[k]);
+        }
+        const uint32_t j = (uint32_t)n & 3u;
+        auto noise = [&](int k) { return j == 0 ? g[k][0] : j == 1 ? g[k][1] : j == 2 ? g[k][2] : g[k][3]; };
+        auto omega_of = [&](int k) { return live[k] ? A.omega[idx[k]] : 0.f; };
+        float tt[OPT];
+#pragma unroll
+        for (int k = 0; k < OPT; ++k) {
+            F1[k] = fmaf(A.kn, fmaf(cos_rev(th[k]), S, -sin_rev(th[k]) * C), omega_of(k));
+            tt[k] = fmaf(A.omega_scale, F1[k], th[k]) + noise(k);
+        }
+        if (SCHEME == SDE_HEUN) {
+            float S2, C2;
+            double S2d, C2d;
+            if (!(ok = reduce(tt, S2, C2, S2d, C2d))) break;
+#pragma unroll
+            for (int k = 0; k < OPT; ++k) {
+                const float F2 = fmaf(A.kn, fmaf(cos_rev(tt[k]), S2, -sin_rev(tt[k]) * C2), omega_of(k));
+                const float t = fmaf(A.hdt2pi, F1[k] + F2, th[k]) + noise(k);
+                th[k] = t - floorf(t);
+            }
+        } else {
+#pragma unroll
+            for (int k = 0; k < OPT; ++k) th[k] = tt[k] - floorf(tt[k]);
+        }
+        ++n;
+        ++local;
+    }
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < OPT; ++k) {
+        if (live[k]) {
+            A.theta[(uint64_t)r * N + idx[k]] = th[k];
+            bad |= !isfinite(th[k]);
+        }
+    }
+    if (__ballot(bad) != 0 && (threadIdx.x & (kWave - 1)) == 0) atomicOr(A.flag, 1);
+    (void)ok;
+}
+
+// ------------------------------------------------------------- TILED ------
+constexpr int kTileThreads = 256;
+
+struct TiledArgs {
+    const float* src;        // [R][N] phases the coupling sum is taken over
+    const float* base;       // [R][N] phases theta_n the step starts from
+    float* dst;              // [R][N] output phases
+    float* F1;               // [R][N] stage-1 drift (written by stage 1, read by stage 2)
+    const float* omega;      // [N]
+    uint32_t N, R;
+    uint64_t n;              // absolute step index
+    uint32_t key0, key1;
+    float omega_scale, hdt2pi, kn, c2;
+    int32_t stage;           // 1: predictor (or Euler step), 2: corrector
+    int32_t euler;
+};
+
+// One stage for OPT oscillators per lane: F_i = omega_i + kn sum_j
+// sin(2 pi (src_j - src_i)) over all j, then the stage's update.
+template <int OPT>
+__global__ __launch_bounds__(kTileThreads) void kuramoto_tiled_kernel(TiledArgs A)
+{
+    constexpr int TILE = kTileThreads * OPT;
+    __shared__ float tile[TILE];
+    const uint32_t r = blockIdx.y;
+    const uint32_t N = A.N;
+    const float* src = A.src + (uint64_t)r * N;
+    float mine[OPT], acc[OPT];
+    uint32_t idx[OPT];
+#pragma unroll
+    for (int k = 0; k < OPT; ++k) {
+        idx[k] = blockIdx.x * TILE + k * kTileThreads + threadIdx.x;
+        mine[k] = idx[k] < N ? src[idx[k]] : 0.f;
+        acc[k] = 0.f;
+    }
+    for (uint32_t j0 = 0; j0 < N; j0 += TILE) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < OPT; ++k) {
+            const uint32_t j = j0 + k * kTileThreads + threadIdx.x;
+            tile[k * kTileThreads + threadIdx.x] = j < N ? src[j] : 0.f;
+        }
+        __syncthreads();
+        const uint32_t cnt = N - j0 < (uint32_t)TILE ? N - j0 : (uint32_t)TILE;
+        if (cnt == (uint32_t)TILE) {
+#pragma unroll 8
+            for (int t = 0; t < TILE; ++t) {
+                const float x = tile[t];
+#pragma unroll
+                for (int k = 0; k < OPT; ++k) acc[k] += sin_rev(x - mine[k]);
+            }
+        } else {
+            for (uint32_t t = 0; t < cnt; ++t) {
+                const float x = tile[t];
+#pragma unroll
+                for (int k = 0; k < OPT; ++k) acc[k] += sin_rev(x - mine[k]);
+            }
+        }
+    }
+    const uint32_t j = (uint32_t)A.n & 3u;
+#pragma unroll
+    for (int k = 0; k < OPT; ++k) {
+        if (idx[k] >= N) continue;
+        const uint64_t gi = (uint64_t)r * N + idx[k];
+        const float F = fmaf(A.kn, acc[k], A.omega[idx[k]]);
+        float g[4];
+        gauss4_scaled(U4{(uint32_t)(A.n >> 2), idx[k], r, (uint32_t)SDE_TAG_NOISE}, A.key0, A.key1, A.c2, g);
+        const float ns = j == 0 ? g[0] : j == 1 ? g[1] : j == 2 ? g[2] : g[3];
+        const float th = A.base[gi];
+        if (A.stage == 1) {
+            const float t = fmaf(A.omega_scale, F, th) + ns;
+            A.dst[gi] = A.euler ? t - floorf(t) : t;
+            if (!A.euler) A.F1[gi] = F;
+        } else {
+            const float t = fmaf(A.hdt2pi, A.F1[gi] + F, th) + ns;
+            A.dst[gi] = t - floorf(t);
+        }
+    }
+}
+
+// r = |N^-1 sum_j exp(2 pi i theta_j)| of each realization, written to
+// out[r * stride + col].  One workgroup per realization, FP64 sums.
+__global__ __launch_bounds__(256) void order_parameter_kernel(const float* theta, uint32_t N, double* out,
+                                                              uint64_t stride, uint64_t col)
+{
+    __shared__ double lds[2 * 256 / kWave];
+    const uint32_t r = blockIdx.x;
+    double s = 0.0, c = 0.0;
+    for (uint32_t i = threadIdx.x; i < N; i += 256) {
+        const float t = theta[(uint64_t)r * N + i];
+        s += (double)sin_rev(t);
+        c += (double)cos_rev(t);
+    }
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    s = wave_sum(s);
+    c = wave_sum(c);
+    if (lane == 0) {
+        lds[2 * wid] = s;
+        lds[2 * wid + 1] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double S = 0.0, C = 0.0;
+        for (int w = 0; w < 256 / kWave; ++w) {
+            S += lds[2 * w];
+            C += lds[2 * w + 1];
+        }
+        out[(uint64_t)r * stride + col] = std::sqrt(S * S + C * C) / (double)N;
+    }
+}
+
+// Initial phases theta = U(Philox(0, i, r, INIT).x0), one thread per oscillator.
+__global__ void kuramoto_init_kernel(float* theta, uint32_t N, uint32_t R, uint32_t key0, uint32_t key1)
+{
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (uint64_t)N * R) return;
+    const uint32_t r = (uint32_t)(g / N), i = (uint32_t)(g % N);
+    const U4 x = philox4x32_10(U4{0u, i, r, (uint32_t)SDE_TAG_INIT}, key0, key1);
+    theta[g] = (float)(x.x >> 8) * 0x1p-24f;
+}
+
+// ------------------------------------------------------------------ host --
+
+void launch_order_parameter(const float* theta, uint32_t N, uint32_t R, double* out, uint64_t stride,
+                            uint64_t col, hipStream_t stream)
+{
+    hipLaunchKernelGGL(order_parameter_kernel, dim3(R), dim3(256), 0, stream, theta, N, out, stride, col);
+}
+
+void launch_kuramoto_init(float* theta, uint32_t N, uint32_t R, uint64_t seed, hipStream_t stream)
+{
+    const uint64_t NR = (uint64_t)N * R;
+    hipLaunchKernelGGL(kuramoto_init_kernel, dim3((uint32_t)((NR + 255) / 256)), dim3(256), 0, stream, theta, N,
+                       R, (uint32_t)seed, (uint32_t)(seed >> 32));
+}
+
+static int validate(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, const float* phi,
+                    const float* omega, const float* K, const double* r_samples)
+{
+    if (!d || !run) return fail(ctx, SDE_ERR_INVALID, "null descriptor or run");
+    if (d->N == 0 || d->R == 0) return fail(ctx, SDE_ERR_INVALID, "N and R must be > 0");
+    if (!std::isfinite(d->K) || !std::isfinite(d->D) || !std::isfinite(d->dt) || !(d->dt > 0) || d->D < 0)
+        return fail(ctx, SDE_ERR_INVALID, "need finite K, D >= 0, dt > 0");
+    if (d->reserved != 0) return fail(ctx, SDE_ERR_INVALID, "reserved field must be 0");
+    if (run->scheme != SDE_HEUN && run->scheme != SDE_EULER)
+        return fail(ctx, SDE_ERR_INVALID, "unknown scheme %d", run->scheme);
+    if (run->init != SDE_INIT_PHILOX && run->init != SDE_INIT_FROM_STATE)
+        return fail(ctx, SDE_ERR_INVALID, "unknown init %d", run->init);
+    if (!phi || !omega) return fail(ctx, SDE_ERR_INVALID, "phi and omega are required");
+    const bool dense = d->coupling == SDE_DENSE_FP32 || d->coupling == SDE_DENSE_BF16X3 ||
+                       d->coupling == SDE_DENSE_FP16X3;
+    if (d->coupling < SDE_MEANFIELD || d->coupling > SDE_DENSE_FP16X3)
+        return fail(ctx, SDE_ERR_INVALID, "unknown coupling %d", d->coupling);
+    if (dense && !K) return fail(ctx, SDE_ERR_INVALID, "dense coupling needs K");
+    if (!dense && K) return fail(ctx, SDE_ERR_INVALID, "uniform coupling takes no K matrix");
+    if (!aligned(phi, 4) || !aligned(omega, 4) || !aligned(K, 16) || !aligned(r_samples, 8))
+        return fail(ctx, SDE_ERR_INVALID, "misaligned device pointer");
+    if ((uint64_t)d->N * d->R > (1ull << 40)) return fail(ctx, SDE_ERR_INVALID, "N * R too large");
+    return SDE_OK;
+}
+
+KuraConsts kuramoto_consts(const sde_kuramoto_desc* d)
+{
+    KuraConsts c;
+    c.omega_scale = (float)(d->dt / (2.0 * M_PI));
+    c.hdt2pi = (float)(d->dt / (4.0 * M_PI));
+    c.kn = (float)(d->K / (double)d->N);
+    const double sig = std::sqrt(2.0 * d->D * d->dt) / (2.0 * M_PI);
+    c.c2 = (float)(-2.0 * M_LN2 * sig * sig);
+    return c;
+}
+
+template <int OPT, int SCHEME>
+static void* mf_kernel_ptr()
+{
+    return reinterpret_cast<void*>(kuramoto_mf_kernel<OPT, SCHEME>);
+}
+
+static int run_meanfield(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, float* phi,
+                         const float* omega, double* r_samples, uint64_t n_samples, uint32_t M,
+                         hipStream_t stream)
+{
+    const KuraConsts kc = kuramoto_consts(d);
+    // oscillators per lane: smallest power of two so that one realization
+    // needs at most 16 workgroups of 1024 lanes
+    // oscillators per lane: smallest of 1, 2, 4 that needs at most 16
+    // workgroups of 1024 lanes per realization (more workgroups if N is larger)
+    int opt = 1;
+    while (opt < 4 && (uint64_t)d->N > (uint64_t)16 * kMFThreads * opt) opt *= 2;
+    const uint64_t G64 = (d->N + (uint64_t)kMFThreads * opt - 1) / ((uint64_t)kMFThreads * opt);
+    const uint32_t G = (uint32_t)G64;
+    void* kern = nullptr;
+    const bool heun = run->scheme == SDE_HEUN;
+    switch (opt) {
+    case 1: kern = heun ? mf_kernel_ptr<1, SDE_HEUN>() : mf_kernel_ptr<1, SDE_EULER>(); break;
+    case 2: kern = heun ? mf_kernel_ptr<2, SDE_HEUN>() : mf_kernel_ptr<2, SDE_EULER>(); break;
+    default: kern = heun ? mf_kernel_ptr<4, SDE_HEUN>() : mf_kernel_ptr<4, SDE_EULER>(); break;
+    }
+    int per_cu = 0;
+    SDE_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kMFThreads, 0));
+    const uint64_t capacity = (uint64_t)std::max(per_cu, 0) * ctx->n_cu;
+    if (capacity < G64)
+        return fail(ctx, SDE_ERR_UNSUPPORTED, "mean-field kernel: N = %u needs %llu co-resident workgroups, the "
+                    "device holds %llu", d->N, (unsigned long long)G64, (unsigned long long)capacity);
+    // realizations per cooperative launch: as many as fit co-resident
+    const uint32_t r_per_launch = (uint32_t)std::min<uint64_t>(d->R, capacity / G);
+
+    void* partials = nullptr;
+    int st = ensure_ws(ctx, kSlotKuraPartials, (size_t)2 * r_per_launch * G * 2 * sizeof(double), &partials);
+    if (st) return st;
+    for (uint32_t r0 = 0; r0 < d->R; r0 += r_per_launch) {
+        const uint32_t nr = std::min(r_per_launch, d->R - r0);
+        if ((st = zero_counters(ctx, 0, nr, stream))) return st;
+        MFArgs A;
+        A.theta = phi + (uint64_t)r0 * d->N;
+        A.omega = omega;
+        A.r_samples = r_samples ? r_samples + (uint64_t)r0 * n_samples : nullptr;
+        A.partials = static_cast<double*>(partials);
+        A.barrier = ctx->counters;
+        A.flag = ctx->flag;
+        A.N = d->N;
+        A.R = nr;
+        A.G = G;
+        A.M = M;
+        A.step0 = run->step0;
+        A.n_steps = d->n_steps;
+        A.n_samples = n_samples;
+        A.key0 = (uint32_t)run->seed;
+        A.key1 = (uint32_t)(run->seed >> 32);
+        A.omega_scale = kc.omega_scale;
+        A.hdt2pi = kc.hdt2pi;
+        A.kn = kc.kn;
+        A.c2 = kc.c2;
+        A.init_from_state = run->init == SDE_INIT_FROM_STATE;
+        A.xcd_map = (ctx->xcds == 8 && nr % 8 == 0) ? 1 : 0;
+        A.spin_limit = 1u << 26;
+        A.r_base = r0;
+        void* args[] = {&A};
+        SDE_HIP(ctx, hipLaunchCooperativeKernel(kern, dim3(nr * G), dim3(kMFThreads), args, 0, stream));
+    }
+    return SDE_OK;
+}
+
+template <int OPT>
+static int launch_tiled(sde_ctx* ctx, const TiledArgs& A, hipStream_t stream)
+{
+    constexpr uint32_t TILE = kTileThreads * OPT;
+    dim3 grid((A.N + TILE - 1) / TILE, A.R);
+    hipLaunchKernelGGL(kuramoto_tiled_kernel<OPT>, grid, dim3(kTileThreads), 0, stream, A);
+    SDE_HIP(ctx, hipGetLastError());
+    return SDE_OK;
+}
+
+static int run_tiled(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, float* phi,
+                     const float* omega, double* r_samples, uint64_t n_samples, uint32_t M,
+                     hipStream_t stream)
+{
+    const KuraConsts kc = kuramoto_consts(d);
+    const uint64_t NR = (uint64_t)d->N * d->R;
+    void* work = nullptr;
+    int st = ensure_ws(ctx, kSlotKuraWork, (size_t)2 * NR * sizeof(float), &work);
+    if (st) return st;
+    float* tilde = static_cast<float*>(work);
+    float* F1 = tilde + NR;
+    const int opt = d->N >= 4096 ? 4 : 1;
+    TiledArgs A;
+    A.omega = omega;
+    A.N = d->N;
+    A.R = d->R;
+    A.key0 = (uint32_t)run->seed;
+    A.key1 = (uint32_t)(run->seed >> 32);
+    A.omega_scale = kc.omega_scale;
+    A.hdt2pi = kc.hdt2pi;
+    A.kn = kc.kn;
+    A.c2 = kc.c2;
+    A.F1 = F1;
+    A.euler = run->scheme == SDE_EULER;
+    for (uint64_t k = 0;; ++k) {
+        if (r_samples && k % M == 0) {
+            hipLaunchKernelGGL(order_parameter_kernel, dim3(d->R), dim3(256), 0, stream, phi, d->N, r_samples,
+                               n_samples, k / M);
+            SDE_HIP(ctx, hipGetLastError());
+        }
+        if (k == d->n_steps) break;
+        A.n = run->step0 + k;
+        A.stage = 1;
+        A.src = phi;
+        A.base = phi;
+        A.dst = A.euler ? phi : tilde;
+        // Euler reads and writes phi in place: every lane reads all of src
+        // before any lane writes, so stage 1 of Euler uses a separate buffer.
+        if (A.euler) A.dst = tilde;
+        st = opt == 4 ? launch_tiled<4>(ctx, A, stream) : launch_tiled<1>(ctx, A, stream);
+        if (st) return st;
+        if (A.euler) {
+            SDE_HIP(ctx, hipMemcpyAsync(phi, tilde, NR * sizeof(float), hipMemcpyDeviceToDevice, stream));
+            continue;
+        }
+        A.stage = 2;
+        A.src = tilde;
+        A.base = phi;
+        A.dst = phi;
+        st = opt == 4 ? launch_tiled<4>(ctx, A, stream) : launch_tiled<1>(ctx, A, stream);
+        if (st) return st;
+    }
+    return SDE_OK;
+}
+
+int kuramoto_impl(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, float* phi, const float* omega,
+                  const float* K, double* r_samples, hipStream_t stream)
+{
+    int st = validate(ctx, d, run, phi, omega, K, r_samples);
+    if (st) return st;
+    const uint32_t M = run->sample_every ? run->sample_every : 100u;
+    const uint64_t n_samples = d->n_steps / M + 1;
+    if (run->init == SDE_INIT_PHILOX && d->coupling != SDE_MEANFIELD) {
+        const uint64_t NR = (uint64_t)d->N * d->R;
+        hipLaunchKernelGGL(kuramoto_init_kernel, dim3((uint32_t)((NR + 255) / 256)), dim3(256), 0, stream, phi,
+                           d->N, d->R, (uint32_t)run->seed, (uint32_t)(run->seed >> 32));
+        SDE_HIP(ctx, hipGetLastError());
+    }
+    switch (d->coupling) {
+    case SDE_MEANFIELD: st = run_meanfield(ctx, d, run, phi, omega, r_samples, n_samples, M, stream); break;
+    case SDE_TILED: st = run_tiled(ctx, d, run, phi, omega, r_samples, n_samples, M, stream); break;
+    default: st = dense_impl(ctx, d, run, phi, omega, K, r_samples, n_samples, M, stream); break;
+    }
+    if (st) return st;
+    if (run->sync) return sync_and_check(ctx, stream);
+    return SDE_OK;
 }
 
 }  // namespace sde

@@ -1,0 +1,206 @@
+"""GPU parity of the Kuramoto path (Eq. 2, Eq. 3, Alg. 3) against the FP64
+oracle, through the C ABI.
+
+Phases are compared on the circle: the GPU keeps theta = phi / 2 pi wrapped
+to [0, 1), the oracle an unwrapped phi; the error is the circular distance
+in radians.  Tolerances:
+  * mean-field, tiled, dense FP32 and dense FP16x3, first 100 steps under
+    shared noise: |d phi| <= 1e-5 max(|phi_ref|, 1) per oscillator;
+  * dense BF16x3: the split product keeps ~16 mantissa bits per term, so
+    the per-step drift error is bounded by 1.5 K 2^-15 ~ 2e-4 (worst case,
+    all terms of one sign); over 100 steps of dt = 0.005 that is 1e-4 rad,
+    the stated bound for that variant;
+  * order parameter samples: paired differences within 3 SE + 1e-4.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import sde_inputs
+
+pytestmark = pytest.mark.gpu
+
+
+def _circ_err(theta_gpu, phi_ref):
+    d = 2 * np.pi * theta_gpu.astype(np.float64) - phi_ref
+    d = np.mod(d + np.pi, 2 * np.pi) - np.pi
+    return np.abs(d) / np.maximum(np.abs(phi_ref), 1.0)
+
+
+def _run(gpu, N, R, K, D, dt, n_steps, coupling, scheme=0, seed=1, omega=None, Kmat=None, phi=None,
+         step0=0, M=100, samples=True):
+    sde, ctx, dev = gpu
+    om = torch.from_numpy(np.asarray(omega, dtype=np.float32)).to(dev)
+    Kt = None if Kmat is None else torch.from_numpy(np.ascontiguousarray(Kmat, dtype=np.float32)).to(dev)
+    if phi is None:
+        ph = torch.empty((R, N), dtype=torch.float32, device=dev)
+        init = sde.SDE_INIT_PHILOX
+    else:
+        ph = phi
+        init = sde.SDE_INIT_FROM_STATE
+    rs = torch.zeros((R, n_steps // M + 1), dtype=torch.float64, device=dev) if samples else None
+    desc = sde.sde_kuramoto_desc(N, R, K, D, dt, n_steps, coupling, 0)
+    run = sde.make_run(seed, step0=step0, scheme=scheme, init=init, sample_every=M, sync=1)
+    sde.sde_kuramoto_integrate(ctx, desc, run, ph, om, Kt, rs)
+    return ph, rs
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_meanfield_uniform_first_100_steps(gpu, scheme):
+    """The uniform-coupling workload (N = 65536, omega ~ N(0,1), K = 3,
+    D = 0.1, dt = 0.01, 16 realizations), first 100 steps, per oscillator."""
+    cfg = sde_inputs.kuramoto_uniform()
+    N, R = cfg["N"], cfg["R"]
+    ph, rs = _run(gpu, N, R, cfg["K"], cfg["D"], cfg["dt"], 100, 0, scheme, cfg["seed"], cfg["omega"])
+    ref, rref = oracle.kuramoto_integrate(N, R, cfg["K"], cfg["D"], cfg["dt"], 100, 100, oracle.MEANFIELD,
+                                          scheme, cfg["seed"], cfg["omega"].astype(np.float64))
+    err = _circ_err(ph.cpu().numpy(), ref)
+    print(f"mean-field scheme {scheme}: max phase error {err.max():.2e}")
+    assert err.max() <= 1e-5
+    np.testing.assert_allclose(rs.cpu().numpy(), rref, rtol=0, atol=1e-6)
+
+
+def test_meanfield_order_parameter_trajectory(gpu):
+    """r(t) every 100 steps over 2000 Heun steps at N = 8192, 8 realizations."""
+    cfg = sde_inputs.kuramoto_uniform(N=8192, R=8)
+    N, R = 8192, 8
+    n = 2000
+    _, rs = _run(gpu, N, R, cfg["K"], cfg["D"], cfg["dt"], n, 0, 0, cfg["seed"], cfg["omega"])
+    _, rref = oracle.kuramoto_integrate(N, R, cfg["K"], cfg["D"], cfg["dt"], n, 100, oracle.MEANFIELD, 0,
+                                        cfg["seed"], cfg["omega"].astype(np.float64))
+    d = rs.cpu().numpy() - rref
+    se = d.std(ddof=1) / np.sqrt(d.size)
+    print(f"r(t): max |diff| {np.abs(d).max():.2e}, mean {d.mean():.2e}, SE {se:.2e}")
+    assert abs(d.mean()) <= 3 * se + 1e-4
+    assert np.abs(d).max() <= 1e-3
+
+
+@pytest.mark.parametrize("scheme", [0, 1])
+def test_tiled_first_100_steps(gpu, scheme):
+    """Alg. 3 (all N^2 sin terms) against the oracle's Eq. 3 sums, N = 3000
+    (ragged against the 1024-oscillator tiles), 3 realizations."""
+    N, R = 3000, 3
+    rng = np.random.default_rng(4)
+    omega = rng.standard_normal(N).astype(np.float32)
+    ph, rs = _run(gpu, N, R, 3.0, 0.1, 0.01, 100, 1, scheme, 9, omega)
+    ref, rref = oracle.kuramoto_integrate(N, R, 3.0, 0.1, 0.01, 100, 100, oracle.MEANFIELD, scheme, 9,
+                                          omega.astype(np.float64))
+    err = _circ_err(ph.cpu().numpy(), ref)
+    print(f"tiled scheme {scheme}: max phase error {err.max():.2e}")
+    assert err.max() <= 1e-5
+    np.testing.assert_allclose(rs.cpu().numpy(), rref, rtol=0, atol=1e-6)
+
+
+def test_tiled_matches_meanfield_on_gpu(gpu):
+    N, R = 4096, 2
+    omega = sde_inputs.kuramoto_omega(N, 1.0, 3)
+    a, ra = _run(gpu, N, R, 3.0, 0.1, 0.01, 200, 0, 0, 5, omega)
+    b, rb = _run(gpu, N, R, 3.0, 0.1, 0.01, 200, 1, 0, 5, omega)
+    d = a.cpu().numpy().astype(np.float64) - b.cpu().numpy()
+    d = np.abs(np.mod(d + 0.5, 1.0) - 0.5) * 2 * np.pi
+    assert d.max() <= 2e-5
+    np.testing.assert_allclose(ra.cpu().numpy(), rb.cpu().numpy(), atol=1e-6)
+
+
+@pytest.mark.parametrize("coupling,tol", [(2, 1e-5), (3, 1e-4), (4, 1e-5)])
+def test_dense_first_100_steps(gpu, coupling, tol):
+    """Dense heterogeneous K_ij (FP32, BF16x3, FP16x3 products): N = 520,
+    R = 40 (both ragged against the 128-row / 32-realization tiles)."""
+    N, R = 520, 40
+    Kmat = sde_inputs.dense_coupling(N, 4.0, 11)
+    omega = sde_inputs.kuramoto_omega(N, 0.5, 12)
+    ph, rs = _run(gpu, N, R, 4.0, 0.05, 0.005, 100, coupling, 0, 13, omega, Kmat)
+    ref, rref = oracle.kuramoto_integrate(N, R, 4.0, 0.05, 0.005, 100, 100, oracle.DENSE, 0, 13,
+                                          omega.astype(np.float64), Kmat=Kmat.astype(np.float64))
+    err = _circ_err(ph.cpu().numpy(), ref)
+    print(f"dense coupling {coupling}: max phase error {err.max():.2e}, mean {err.mean():.2e}")
+    assert err.max() <= tol
+    np.testing.assert_allclose(rs.cpu().numpy(), rref, rtol=0, atol=10 * tol)
+
+
+def test_dense_full_size_sampled(gpu):
+    """The dense workload at its size -- N = 4096, 256 realizations, the
+    BF16x3 product -- for 200 steps, realizations 0..3 checked against the
+    oracle (which draws the same keyed noise)."""
+    cfg = sde_inputs.kuramoto_dense()
+    N, R = cfg["N"], cfg["R"]
+    n = 200
+    ph, _ = _run(gpu, N, R, cfg["K"], cfg["D"], cfg["dt"], n, 3, 0, cfg["seed"], cfg["omega"], cfg["Kmat"])
+    ref, _ = oracle.kuramoto_integrate(N, R, cfg["K"], cfg["D"], cfg["dt"], n, 0, oracle.DENSE, 0, cfg["seed"],
+                                       cfg["omega"].astype(np.float64), Kmat=cfg["Kmat"].astype(np.float64),
+                                       r_first=0, r_count=4)
+    err = _circ_err(ph.cpu().numpy()[:4], ref)
+    print(f"dense bf16x3 at N=4096, R=256, 200 steps: max phase error {err.max():.2e}")
+    assert err.max() <= 2e-4
+
+
+def test_dense_uniform_matrix_equals_meanfield(gpu):
+    """K_ij = K/N off the diagonal (zero diagonal) is the uniform model."""
+    N, R = 1024, 32
+    K = 2.5
+    Kmat = np.full((N, N), K / N, dtype=np.float32)
+    np.fill_diagonal(Kmat, 0.0)
+    omega = sde_inputs.kuramoto_omega(N, 1.0, 7)
+    a, _ = _run(gpu, N, R, K, 0.1, 0.01, 100, 2, 0, 3, omega, Kmat)
+    b, _ = _run(gpu, N, R, K, 0.1, 0.01, 100, 0, 0, 3, omega)
+    d = a.cpu().numpy().astype(np.float64) - b.cpu().numpy()
+    d = np.abs(np.mod(d + 0.5, 1.0) - 0.5) * 2 * np.pi
+    assert d.max() <= 2e-5
+
+
+@pytest.mark.parametrize("coupling,N", [(0, 65536), (1, 2048)])
+def test_identical_oscillator_threshold(gpu, coupling, N):
+    """omega = 0: stationary r solves r = I1(K r/D)/I0(K r/D) above K_c = 2D
+    (0.8315 at K/D = 4) and is O(N^-1/2) below it (K/D = 1)."""
+    D = 0.25
+    R = 2
+    n = 3000 if coupling == 1 else 6000
+    tol = 0.03 if N < 10000 else 0.02
+    omega = np.zeros(N, dtype=np.float32)
+    for KD, lo, hi in [(4.0, 0.8315 - tol, 0.8315 + tol), (1.0, 0.0, 0.08)]:
+        _, rs = _run(gpu, N, R, KD * D, D, 0.01, n, coupling, 0, 17, omega)
+        r_late = rs.cpu().numpy()[:, -10:].mean()
+        print(f"coupling {coupling}, K/D = {KD}: late r = {r_late:.4f}")
+        assert lo <= r_late <= hi
+
+
+@pytest.mark.parametrize("coupling", [0, 1, 3])
+def test_resume_bit_identical(gpu, coupling):
+    sde, ctx, dev = gpu
+    N, R = 1000, 32
+    omega = sde_inputs.kuramoto_omega(N, 1.0, 2)
+    Kmat = sde_inputs.dense_coupling(N, 3.0, 2) if coupling >= 2 else None
+    full, _ = _run(gpu, N, R, 3.0, 0.1, 0.01, 50, coupling, 0, 8, omega, Kmat, samples=False)
+    a, _ = _run(gpu, N, R, 3.0, 0.1, 0.01, 21, coupling, 0, 8, omega, Kmat, samples=False)
+    b, _ = _run(gpu, N, R, 3.0, 0.1, 0.01, 29, coupling, 0, 8, omega, Kmat, phi=a, step0=21, samples=False)
+    assert torch.equal(full, b)
+
+
+def test_deterministic_meanfield(gpu):
+    cfg = sde_inputs.kuramoto_uniform()
+    a, ra = _run(gpu, cfg["N"], cfg["R"], cfg["K"], cfg["D"], cfg["dt"], 300, 0, 0, 4, cfg["omega"])
+    b, rb = _run(gpu, cfg["N"], cfg["R"], cfg["K"], cfg["D"], cfg["dt"], 300, 0, 0, 4, cfg["omega"])
+    assert torch.equal(a, b) and torch.equal(ra, rb)
+
+
+def test_kuramoto_invalid_arguments(gpu):
+    sde, ctx, dev = gpu
+    N, R = 64, 2
+    ph = torch.zeros((R, N), dtype=torch.float32, device=dev)
+    om = torch.zeros(N, dtype=torch.float32, device=dev)
+    Km = torch.zeros((N, N), dtype=torch.float32, device=dev)
+    run = sde.make_run(1, sync=1)
+    bad = [(sde.sde_kuramoto_desc(0, R, 1.0, 0.1, 0.01, 10, 0, 0), None),
+           (sde.sde_kuramoto_desc(N, 0, 1.0, 0.1, 0.01, 10, 0, 0), None),
+           (sde.sde_kuramoto_desc(N, R, 1.0, 0.1, 0.0, 10, 0, 0), None),
+           (sde.sde_kuramoto_desc(N, R, 1.0, -0.1, 0.01, 10, 0, 0), None),
+           (sde.sde_kuramoto_desc(N, R, float("nan"), 0.1, 0.01, 10, 0, 0), None),
+           (sde.sde_kuramoto_desc(N, R, 1.0, 0.1, 0.01, 10, 3, 0), None),
+           (sde.sde_kuramoto_desc(N, R, 1.0, 0.1, 0.01, 10, 0, 0), Km),
+           (sde.sde_kuramoto_desc(N, R, 1.0, 0.1, 0.01, 10, 9, 0), None)]
+    for desc, K in bad:
+        with pytest.raises(sde.SDEError) as e:
+            sde.sde_kuramoto_integrate(ctx, desc, run, ph, om, K)
+        assert e.value.status == sde.SDE_ERR_INVALID
+    assert torch.count_nonzero(ph) == 0
