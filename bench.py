@@ -131,6 +131,7 @@ def bench_jj(args, sde, torch, dev):
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     sde.sde_check(ctx)
+    stats = sde.sde_get_stats(ctx)
     sde.sde_destroy(ctx)
     ms = [s.elapsed_time(e) for s, e in zip(starts, ends)]
     kernel_s = float(np.mean(ms)) / 1e3
@@ -152,7 +153,9 @@ def bench_jj(args, sde, torch, dev):
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FMA_LANES / 1e12,
                      "unit": "T FP32-FMA-equivalent lane-ops/s", "frac": achieved / PEAK_FMA_LANES,
                      "traffic": traffic, "ops_per_path_step": ops,
-                     "kernel": "jj_persistent_kernel<2, HEUN, inertial>"},
+                     "kernel": f"jj_persistent_kernel<{stats['jj_paths_per_lane']}, HEUN, inertial>"},
+        "launch": {"paths_per_lane": stats["jj_paths_per_lane"], "graph_replayed": stats["graph_replayed"],
+                   "work_items": stats["work_items"]},
         "fp32_tflops": jj_flops_per_path_step() * path_steps / kernel_s / 1e12,
         "kernel_ms": float(np.mean(ms)),
     }
@@ -172,6 +175,39 @@ def bench_jj(args, sde, torch, dev):
             out["parity"] = {"points": len(qs), "max_abs_diff_vmean": float(np.abs(g - o).max()),
                              "max_diff_over_3se_plus_1e-4": float(ratio.max()), "ok": bool(ratio.max() <= 1.0)}
     return out
+
+
+def bench_jj_batch(args, sde, torch, dev):
+    """The uneven batch: 2048 random points (a ~ U[2,6], omega ~ U[3,7],
+    f ~ U[0,0.5], log10 D ~ U[-4,-1], gamma ~ U[0.5,1.5]) with paths in
+    {256..8192} and steps in {5e4..4e5} (half transient), one persistent
+    launch.  Tail efficiency = the time the same path-steps would take at
+    the rate of the uniform scan kernel / the measured time."""
+    pts_l = sde_inputs.jj_batch()
+    pts = sde.make_points(pts_l)
+    work = sum(p["n_paths"] * p["n_steps"] for p in pts_l)
+    ps = torch.empty((len(pts_l), 2), dtype=torch.float64, device=dev)
+    ctx = sde.sde_create(0)
+    run = sde.make_run(sde_inputs.seed_of(5))
+    stream = torch.cuda.current_stream()
+    sde.sde_jj_integrate(ctx, pts, run, point_sums=ps)  # warm-up (tunes, records the graph)
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record(stream)
+    sde.sde_jj_integrate(ctx, pts, run, point_sums=ps)
+    e.record(stream)
+    torch.cuda.synchronize()
+    st = sde.sde_get_stats(ctx)
+    sde.sde_check(ctx)
+    sde.sde_destroy(ctx)
+    t = s.elapsed_time(e) / 1e3
+    ops = jj_ops_per_path_step()
+    return {"workload": "jj_batch", "points": len(pts_l), "path_steps": work, "seconds": t,
+            "path_steps_per_s": work / t, "paths_per_lane": st["jj_paths_per_lane"],
+            "work_items": st["work_items"], "graph_replayed": st["graph_replayed"],
+            "roofline": {"bound": "alu", "achieved": ops * work / t / 1e12, "peak": PEAK_FMA_LANES / 1e12,
+                         "unit": "T FP32-FMA-equivalent lane-ops/s", "frac": ops * work / t / PEAK_FMA_LANES,
+                         "traffic": None}}
 
 
 KURA = {
@@ -248,7 +284,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="jj_scan", choices=["jj_scan"] + sorted(KURA))
+    ap.add_argument("--workload", default="jj_scan", choices=["jj_scan", "jj_batch"] + sorted(KURA))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kuramoto", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -273,6 +309,12 @@ def main():
         if not args.no_kuramoto:
             out["kuramoto"] = [bench_kuramoto(w, args, sde, torch, dev, steps=s)
                                for w, s in [("kuramoto_mf", 20000), ("kuramoto_dense_bf16x3", 2000)]]
+            jb = bench_jj_batch(args, sde, torch, dev)
+            jb["tail_efficiency"] = jb["path_steps_per_s"] / (out["config"]["path_steps_per_step"] /
+                                                            (out["kernel_ms"] / 1e3))
+            out["jj_batch"] = jb
+    elif args.workload == "jj_batch":
+        out = bench_jj_batch(args, sde, torch, dev)
     else:
         out = bench_kuramoto(args.workload, args, sde, torch, dev, reps=args.steps)
     if args.calibrate_copy:

@@ -194,6 +194,36 @@ int sde_observables(sde_ctx* ctx, int kind, const void* dev_in /* [device] */,
                     const uint32_t* counts /* [host] */, uint32_t n_groups,
                     double* host_out /* [host] [n_groups][2] */, void* hip_stream);
 
+/* ---- launch layer: autotuner, graph cache, statistics --------------------- */
+enum {
+    SDE_OPT_AUTOTUNE = 1, /* 1 (default): on a tune-cache miss, time the candidate   */
+                          /* launch configurations on a short slice of the call and  */
+                          /* keep the fastest; 0: use the cached or default choice   */
+    SDE_OPT_GRAPHS = 2,   /* 1 (default): record each call's launch sequence once in */
+                          /* a HIP graph keyed by its arguments and replay it; 0:    */
+                          /* launch kernels directly                                 */
+    SDE_OPT_JJ_PPT = 3    /* Josephson-junction paths per lane: 0 (default) = tuned, */
+                          /* or 1, 2, 4 to force                                     */
+};
+/* Sets an option of the context.  SDE_ERR_INVALID for an unknown option or
+ * value. */
+int sde_set_option(sde_ctx* ctx, int option, int64_t value);
+/* Loads tuned launch choices from the JSON file `path` (created if missing)
+ * and saves new ones there after each tuning.  NULL: keep choices in memory
+ * only.  The environment variable SDE_TUNE_CACHE sets it at sde_create. */
+int sde_set_tune_cache(sde_ctx* ctx, const char* path);
+
+typedef struct {
+    int32_t graph_replayed;  /* the last call replayed a cached HIP graph             */
+    int32_t tuned;           /* the last call ran the autotuner                       */
+    int32_t jj_paths_per_lane;
+    int32_t graphs_cached;   /* HIP graphs held by the context                        */
+    double tune_ms;          /* time spent tuning in the last call                    */
+    uint64_t work_items;     /* work items (point, path chunk) of the last JJ call    */
+} sde_stats;
+/* Statistics of the last integration call on `ctx`. */
+int sde_get_stats(const sde_ctx* ctx, sde_stats* out);
+
 /* ---- test hooks ---------------------------------------------------------- */
 /* dev_out[k][0..3] = Philox4x32-10 words at counter (ctr0_first + k, a, b, tag)
  * for k < n_blocks (the raw integers the integrators consume). */

@@ -25,10 +25,12 @@ SDE_INIT_PHILOX, SDE_INIT_FROM_STATE = 0, 1
 SDE_MEANFIELD, SDE_TILED, SDE_DENSE_FP32, SDE_DENSE_BF16X3, SDE_DENSE_FP16X3 = 0, 1, 2, 3, 4
 SDE_TAG_NOISE, SDE_TAG_INIT = 0, 1
 SDE_OBS_MEAN_F32, SDE_OBS_MEAN_F64, SDE_OBS_MEANSQ_F32, SDE_OBS_ORDER = 0, 1, 2, 3
+SDE_OPT_AUTOTUNE, SDE_OPT_GRAPHS, SDE_OPT_JJ_PPT = 1, 2, 3
 
 EXPORTS = ["sde_create", "sde_destroy", "sde_strerror", "sde_last_error", "sde_check",
            "sde_jj_integrate", "sde_kuramoto_integrate", "sde_observables",
-           "sde_debug_philox", "sde_debug_gauss"]
+           "sde_debug_philox", "sde_debug_gauss", "sde_set_option", "sde_set_tune_cache",
+           "sde_get_stats"]
 
 
 class SDEError(RuntimeError):
@@ -48,6 +50,12 @@ class sde_run(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("step0", ctypes.c_uint64), ("scheme", ctypes.c_int32),
                 ("init", ctypes.c_int32), ("sample_every", ctypes.c_uint32),
                 ("sync", ctypes.c_int32)]
+
+
+class sde_stats(ctypes.Structure):
+    _fields_ = [("graph_replayed", ctypes.c_int32), ("tuned", ctypes.c_int32),
+                ("jj_paths_per_lane", ctypes.c_int32), ("graphs_cached", ctypes.c_int32),
+                ("tune_ms", ctypes.c_double), ("work_items", ctypes.c_uint64)]
 
 
 class sde_kuramoto_desc(ctypes.Structure):
@@ -92,6 +100,12 @@ def lib():
         L.sde_debug_philox.restype = i32
         L.sde_debug_gauss.argtypes = [vp, u64, u32, u32, u32, u64, u64, vp, vp]
         L.sde_debug_gauss.restype = i32
+        L.sde_set_option.argtypes = [vp, i32, ctypes.c_int64]
+        L.sde_set_option.restype = i32
+        L.sde_set_tune_cache.argtypes = [vp, ctypes.c_char_p]
+        L.sde_set_tune_cache.restype = i32
+        L.sde_get_stats.argtypes = [vp, ctypes.POINTER(sde_stats)]
+        L.sde_get_stats.restype = i32
         _lib = L
     return _lib
 
@@ -206,3 +220,18 @@ def sde_debug_philox(ctx, seed, tag, a, b, ctr0_first, n_blocks, dev_out, stream
 def sde_debug_gauss(ctx, seed, tag, a, b, n_first, count, dev_out, stream=None):
     return _check(ctx, lib().sde_debug_gauss(ctx, seed, tag, a, b, n_first, count,
                                              _ptr(dev_out), _stream(stream)))
+
+
+def sde_set_option(ctx, option, value):
+    return _check(ctx, lib().sde_set_option(ctx, option, value))
+
+
+def sde_set_tune_cache(ctx, path):
+    return _check(ctx, lib().sde_set_tune_cache(ctx, None if path is None else str(path).encode()))
+
+
+def sde_get_stats(ctx):
+    """dict of the last integration call's launch statistics."""
+    st = sde_stats()
+    _check(ctx, lib().sde_get_stats(ctx, ctypes.byref(st)))
+    return {k: getattr(st, k) for k, _ in sde_stats._fields_}

@@ -27,6 +27,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdlib>
 #include <map>
@@ -337,20 +338,176 @@ static bool finite_point(const sde_jj_point& p)
            std::isfinite(p.f) && std::isfinite(p.D);
 }
 
-int jj_paths_per_thread()
+// Work items of one paths-per-lane choice: chunk layout per point and the
+// queue (longest first), inertial points before overdamped ones.
+struct JJPlan {
+    std::vector<JJPointDev> pts;
+    std::vector<JJItem> items;
+    uint32_t n_inertial = 0;
+    uint32_t n_chunks = 0;
+};
+
+static void plan_items(std::vector<JJPointDev>& P, int ppt, JJPlan& out)
 {
-    const char* e = std::getenv("SDE_JJ_PPT");
-    if (e) {
-        int v = std::atoi(e);
-        if (v == 1 || v == 2 || v == 4) return v;
+    const uint32_t chunk_paths = (uint32_t)(kWave * ppt);
+    std::vector<JJItem> it_in, it_od;
+    uint32_t chunk_first = 0;
+    for (uint32_t q = 0; q < (uint32_t)P.size(); ++q) {
+        JJPointDev& d = P[q];
+        d.n_chunks = (d.n_paths + chunk_paths - 1) / chunk_paths;
+        d.chunk_first = chunk_first;
+        for (uint32_t c = 0; c < d.n_chunks; ++c) (d.inertial ? it_in : it_od).push_back(JJItem{q, c});
+        chunk_first += d.n_chunks;
     }
-    return 2;
+    auto longest_first = [&](const JJItem& x, const JJItem& y) { return P[x.point].n_steps > P[y.point].n_steps; };
+    std::stable_sort(it_in.begin(), it_in.end(), longest_first);
+    std::stable_sort(it_od.begin(), it_od.end(), longest_first);
+    out.pts = P;
+    out.n_inertial = (uint32_t)it_in.size();
+    out.items = std::move(it_in);
+    out.items.insert(out.items.end(), it_od.begin(), it_od.end());
+    out.n_chunks = chunk_first;
+}
+
+struct JJLaunch {
+    JJArgs A;
+    int ppt;
+    int scheme;
+    uint32_t n_inertial, n_items, n_pts;
+    uint32_t grid[2];
+    double* point_sums;
+};
+
+static int jj_grids(sde_ctx* ctx, JJLaunch& L)
+{
+    for (int kind = 0; kind < 2; ++kind) {
+        const uint32_t count = kind == 0 ? L.n_inertial : L.n_items - L.n_inertial;
+        L.grid[kind] = 0;
+        if (!count) continue;
+        JJKernel kern = kind == 0 ? pick_kernel<true>(L.ppt, L.scheme) : pick_kernel<false>(L.ppt, L.scheme);
+        int per_cu = 0;
+        SDE_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), 256, 0));
+        if (per_cu < 1) per_cu = 1;
+        const uint64_t want = ((uint64_t)count + 3) / 4;  // 4 waves per block, one item each at least
+        L.grid[kind] = (uint32_t)std::min<uint64_t>(want, (uint64_t)per_cu * ctx->n_cu);
+    }
+    return SDE_OK;
+}
+
+// The launch sequence of one call: reset the two queues, the persistent
+// kernel of each point kind, the per-point sums.
+static int jj_record(sde_ctx* ctx, const JJLaunch& L, hipStream_t s)
+{
+    int st = zero_counters(ctx, 0, 2, s);
+    if (st) return st;
+    const JJItem* all = L.A.items;
+    for (int kind = 0; kind < 2; ++kind) {
+        if (!L.grid[kind]) continue;
+        JJArgs A = L.A;
+        A.items = all + (kind == 0 ? 0 : L.n_inertial);
+        A.n_items = kind == 0 ? L.n_inertial : L.n_items - L.n_inertial;
+        A.queue = ctx->counters + kind;
+        JJKernel kern = kind == 0 ? pick_kernel<true>(L.ppt, L.scheme) : pick_kernel<false>(L.ppt, L.scheme);
+        hipLaunchKernelGGL(kern, dim3(L.grid[kind]), dim3(256), 0, s, A);
+        SDE_HIP(ctx, hipGetLastError());
+    }
+    if (L.point_sums) {
+        hipLaunchKernelGGL(jj_point_sums_kernel, dim3((L.n_pts + 255) / 256), dim3(256), 0, s, L.A.pts, L.n_pts,
+                           L.A.partials, L.point_sums);
+        SDE_HIP(ctx, hipGetLastError());
+    }
+    return SDE_OK;
+}
+
+static int jj_upload_plan(sde_ctx* ctx, const JJPlan& plan, hipStream_t stream, JJLaunch& L)
+{
+    int st;
+    if ((st = upload(ctx, kSlotJJPoints, 0, plan.pts.data(), plan.pts.size() * sizeof(JJPointDev), stream))) return st;
+    if ((st = upload(ctx, kSlotJJItems, 1, plan.items.data(), plan.items.size() * sizeof(JJItem), stream))) return st;
+    void* partials = nullptr;
+    if ((st = ensure_ws(ctx, kSlotJJPartials, (size_t)std::max(plan.n_chunks, 1u) * 2 * sizeof(double), &partials)))
+        return st;
+    if ((st = ensure_counters(ctx, 2))) return st;
+    L.A.pts = static_cast<const JJPointDev*>(ctx->ws[kSlotJJPoints].ptr);
+    L.A.items = static_cast<const JJItem*>(ctx->ws[kSlotJJItems].ptr);
+    L.A.partials = static_cast<double*>(partials);
+    L.n_inertial = plan.n_inertial;
+    L.n_items = (uint32_t)plan.items.size();
+    L.n_pts = (uint32_t)plan.pts.size();
+    return jj_grids(ctx, L);
+}
+
+static int ilog2u64(uint64_t x)
+{
+    int r = 0;
+    while (x > 1) {
+        x >>= 1;
+        ++r;
+    }
+    return r;
+}
+
+// Times the candidate paths-per-lane choices on a short slice of the call
+// (same points, at most 2048 steps, no per-path outputs) and returns the
+// fastest.  Nothing the caller passed is written.
+static int jj_tune(sde_ctx* ctx, const std::vector<JJPointDev>& P0, const JJLaunch& base, hipStream_t stream,
+                   int* best_ppt)
+{
+    std::vector<JJPointDev> P = P0;
+    uint64_t work = 0;
+    for (auto& d : P) {
+        d.n_steps = std::min<uint64_t>(d.n_steps, 2048);
+        work += (uint64_t)d.n_paths * d.n_steps;
+    }
+    if (work == 0) {
+        *best_ppt = 2;
+        return SDE_OK;
+    }
+    hipEvent_t e0, e1;
+    SDE_HIP(ctx, hipEventCreate(&e0));
+    SDE_HIP(ctx, hipEventCreate(&e1));
+    double best = 1e300;
+    int st = SDE_OK;
+    for (int ppt : {1, 2, 4}) {
+        JJPlan plan;
+        plan_items(P, ppt, plan);
+        JJLaunch L = base;
+        L.ppt = ppt;
+        L.point_sums = nullptr;
+        L.A.theta = nullptr;
+        L.A.winding = nullptr;
+        L.A.v = nullptr;
+        L.A.acc = nullptr;
+        L.A.init_from_state = 0;
+        L.A.flag = ctx->tune_flag;  // a trial run's NaN is not the caller's
+        if ((st = jj_upload_plan(ctx, plan, stream, L))) break;
+        float ms = 0.f;
+        for (int rep = 0; rep < 2; ++rep) {  // first launch loads the code object
+            if ((st = hipEventRecord(e0, stream) == hipSuccess ? SDE_OK : SDE_ERR_DEVICE)) break;
+            if ((st = jj_record(ctx, L, stream))) break;
+            if ((st = hipEventRecord(e1, stream) == hipSuccess ? SDE_OK : SDE_ERR_DEVICE)) break;
+            if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                st = SDE_ERR_DEVICE;
+                break;
+            }
+        }
+        if (st) break;
+        if (ms < best) {
+            best = ms;
+            *best_ppt = ppt;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st == SDE_ERR_DEVICE) return fail(ctx, st, "autotuner: HIP event or launch failed");
+    return st;
 }
 
 int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run,
                       float* theta, int32_t* winding, float* v, double* acc, double* point_sums,
                       hipStream_t stream)
 {
+    ctx->last = sde_stats{};
     if (!pts || !run || n_pts == 0) return fail(ctx, SDE_ERR_INVALID, "null points/run or n_pts = 0");
     if (run->scheme != SDE_HEUN && run->scheme != SDE_EULER)
         return fail(ctx, SDE_ERR_INVALID, "unknown scheme %d", run->scheme);
@@ -362,20 +519,18 @@ int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, con
         !aligned(point_sums, 8))
         return fail(ctx, SDE_ERR_INVALID, "misaligned device pointer");
     const uint32_t M = run->sample_every ? run->sample_every : 100u;
-    const int ppt = jj_paths_per_thread();
-    const uint32_t chunk_paths = (uint32_t)(kWave * ppt);
 
     std::vector<JJPointDev> P(n_pts);
-    std::vector<JJItem> items, items_od;  // inertial points, overdamped points
     std::map<uint32_t, uint32_t> lut_of;  // S -> offset
     std::vector<float> lut;
-    uint64_t path_first = 0;
-    uint32_t chunk_first = 0;
+    uint64_t path_first = 0, max_steps = 0;
+    bool any_inertial = false, any_overdamped = false;
     for (uint32_t q = 0; q < n_pts; ++q) {
         const sde_jj_point& p = pts[q];
         if (!finite_point(p)) return fail(ctx, SDE_ERR_INVALID, "point %u: non-finite parameter", q);
         if (p.n_paths == 0 || p.steps_per_period == 0)
             return fail(ctx, SDE_ERR_INVALID, "point %u: n_paths and steps_per_period must be > 0", q);
+        if (p.n_paths > (1u << 31)) return fail(ctx, SDE_ERR_INVALID, "point %u: more than 2^31 paths", q);
         if (!(p.omega > 0) || p.m < 0 || p.gamma < 0 || p.D < 0 || (p.m == 0 && !(p.gamma > 0)))
             return fail(ctx, SDE_ERR_INVALID, "point %u: need omega > 0, m >= 0, D >= 0, gamma >= 0 "
                         "(gamma > 0 when m = 0)", q);
@@ -394,6 +549,7 @@ int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, con
             const double sig = std::sqrt(2.0 * p.gamma * p.D * dt) / p.m;
             d.c2 = (float)(-2.0 * M_LN2 * sig * sig);
             d.sig_v = 0.f;
+            any_inertial = true;
         } else {
             const double s = std::sqrt(2.0 * p.D * dt / p.gamma);
             d.im = (float)(1.0 / p.gamma);
@@ -403,6 +559,7 @@ int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, con
             const double sig = s / (2.0 * M_PI);
             d.c2 = (float)(-2.0 * M_LN2 * sig * sig);
             d.sig_v = (float)(2.0 * M_PI / dt);
+            any_overdamped = true;
         }
         d.S = p.steps_per_period;
         auto it = lut_of.find(d.S);
@@ -420,64 +577,61 @@ int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, con
         const uint64_t end = run->step0 + p.n_steps;
         const uint64_t W = end > p.n_transient ? end - p.n_transient : 0;
         d.inv_W = W ? 1.0 / (double)W : 0.0;
-        d.n_chunks = (p.n_paths + chunk_paths - 1) / chunk_paths;
-        d.chunk_first = chunk_first;
-        for (uint32_t c = 0; c < d.n_chunks; ++c) (d.inertial ? items : items_od).push_back(JJItem{q, c});
-        chunk_first += d.n_chunks;
         path_first += p.n_paths;
+        max_steps = std::max<uint64_t>(max_steps, p.n_steps);
     }
-    // Longest items first, so that an uneven batch ends with short items.
-    auto longest_first = [&](const JJItem& x, const JJItem& y) { return P[x.point].n_steps > P[y.point].n_steps; };
-    std::stable_sort(items.begin(), items.end(), longest_first);
-    std::stable_sort(items_od.begin(), items_od.end(), longest_first);
-    const uint32_t n_inertial = (uint32_t)items.size();
-    items.insert(items.end(), items_od.begin(), items_od.end());
+    if (path_first / kWave > 0xffffffffull) return fail(ctx, SDE_ERR_INVALID, "too many paths in one call");
 
     int st;
-    if ((st = upload(ctx, kSlotJJPoints, 0, P.data(), P.size() * sizeof(JJPointDev), stream))) return st;
-    if ((st = upload(ctx, kSlotJJItems, 1, items.data(), items.size() * sizeof(JJItem), stream))) return st;
     if ((st = upload(ctx, kSlotJJLut, 2, lut.data(), lut.size() * sizeof(float), stream))) return st;
-    void* partials = nullptr;
-    if ((st = ensure_ws(ctx, kSlotJJPartials, (size_t)chunk_first * 2 * sizeof(double), &partials))) return st;
-    if ((st = zero_counters(ctx, 0, 2, stream))) return st;
+    JJLaunch L;
+    L.scheme = run->scheme;
+    L.point_sums = point_sums;
+    L.A.lut = static_cast<const float*>(ctx->ws[kSlotJJLut].ptr);
+    L.A.flag = ctx->flag;
+    L.A.theta = theta;
+    L.A.winding = winding;
+    L.A.v = v;
+    L.A.acc = acc;
+    L.A.step0 = run->step0;
+    L.A.key0 = (uint32_t)(run->seed & 0xffffffffu);
+    L.A.key1 = (uint32_t)(run->seed >> 32);
+    L.A.M = M;
+    L.A.init_from_state = run->init == SDE_INIT_FROM_STATE;
 
-    JJArgs A;
-    A.pts = static_cast<const JJPointDev*>(ctx->ws[kSlotJJPoints].ptr);
-    A.lut = static_cast<const float*>(ctx->ws[kSlotJJLut].ptr);
-    A.flag = ctx->flag;
-    A.theta = theta;
-    A.winding = winding;
-    A.v = v;
-    A.acc = acc;
-    A.partials = static_cast<double*>(partials);
-    A.step0 = run->step0;
-    A.key0 = (uint32_t)(run->seed & 0xffffffffu);
-    A.key1 = (uint32_t)(run->seed >> 32);
-    A.M = M;
-    A.init_from_state = run->init == SDE_INIT_FROM_STATE;
-    const JJItem* all_items = static_cast<const JJItem*>(ctx->ws[kSlotJJItems].ptr);
+    // paths per lane: forced, cached, or tuned on this call's shape class
+    int ppt = ctx->jj_ppt;
+    if (!ppt) {
+        char key[160];
+        snprintf(key, sizeof key, "jj|%s|scheme%d|kinds%d%d|paths2^%d|steps2^%d", ctx->arch.c_str(), run->scheme,
+                 (int)any_inertial, (int)any_overdamped, ilog2u64(path_first), ilog2u64(std::max<uint64_t>(max_steps, 1)));
+        if (!tune_lookup(ctx, key, &ppt)) {
+            ppt = 2;
+            if (ctx->autotune) {
+                const auto t0 = std::chrono::steady_clock::now();
+                if ((st = jj_tune(ctx, P, L, stream, &ppt))) return st;
+                ctx->last.tuned = 1;
+                ctx->last.tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                tune_store(ctx, key, ppt);
+            }
+        }
+    }
+    L.ppt = ppt;
+    JJPlan plan;
+    plan_items(P, ppt, plan);
+    if ((st = jj_upload_plan(ctx, plan, stream, L))) return st;
+    ctx->last.jj_paths_per_lane = ppt;
+    ctx->last.work_items = plan.items.size();
 
-    for (int kind = 0; kind < 2; ++kind) {  // 0: inertial points, 1: overdamped points
-        const uint32_t first = kind == 0 ? 0u : n_inertial;
-        const uint32_t count = kind == 0 ? n_inertial : (uint32_t)items.size() - n_inertial;
-        if (count == 0) continue;
-        A.items = all_items + first;
-        A.n_items = count;
-        A.queue = ctx->counters + kind;
-        JJKernel kern = kind == 0 ? pick_kernel<true>(ppt, run->scheme) : pick_kernel<false>(ppt, run->scheme);
-        int per_cu = 0;
-        SDE_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), 256, 0));
-        if (per_cu < 1) per_cu = 1;
-        const uint64_t want = ((uint64_t)count + 3) / 4;  // 4 waves per block, one item each at least
-        const uint32_t grid = (uint32_t)std::min<uint64_t>(want, (uint64_t)per_cu * ctx->n_cu);
-        hipLaunchKernelGGL(kern, dim3(grid), dim3(256), 0, stream, A);
-        SDE_HIP(ctx, hipGetLastError());
-    }
-    if (point_sums) {
-        hipLaunchKernelGGL(jj_point_sums_kernel, dim3((n_pts + 255) / 256), dim3(256), 0, stream, A.pts, n_pts,
-                           A.partials, point_sums);
-        SDE_HIP(ctx, hipGetLastError());
-    }
+    // everything baked into the recorded launches
+    char key[512];
+    snprintf(key, sizeof key, "jj|%p|%p|%p|%p|%p|%p|%p|%llu|%u|%u|%u|%d|%d|%d|%u|%u|%u|%u|%u", (void*)L.A.pts,
+             (void*)L.A.items, (void*)L.A.lut, (void*)theta, (void*)winding, (void*)v, (void*)acc,
+             (unsigned long long)run->step0, L.A.key0, L.A.key1, M, L.A.init_from_state, ppt, run->scheme,
+             L.n_inertial, L.n_items, L.n_pts, L.grid[0], L.grid[1]);
+    std::string k = key;
+    k += point_sums ? "|ps" + std::to_string((uintptr_t)point_sums) : "|ps0";
+    if ((st = run_recorded(ctx, k, stream, [&](hipStream_t s) { return jj_record(ctx, L, s); }))) return st;
     if (run->sync) return sync_and_check(ctx, stream);
     return SDE_OK;
 }

@@ -226,8 +226,9 @@ struct TiledArgs {
     float* dst;              // [R][N] output phases
     float* F1;               // [R][N] stage-1 drift (written by stage 1, read by stage 2)
     const float* omega;      // [N]
+    const uint64_t* nbase;   // device: absolute step of the current chunk's first step
+    uint32_t k;              // step within the chunk
     uint32_t N, R;
-    uint64_t n;              // absolute step index
     uint32_t key0, key1;
     float omega_scale, hdt2pi, kn, c2;
     int32_t stage;           // 1: predictor (or Euler step), 2: corrector
@@ -276,14 +277,15 @@ __global__ __launch_bounds__(kTileThreads) void kuramoto_tiled_kernel(TiledArgs 
             }
         }
     }
-    const uint32_t j = (uint32_t)A.n & 3u;
+    const uint64_t n = load_uniform(A.nbase) + A.k;
+    const uint32_t j = (uint32_t)n & 3u;
 #pragma unroll
     for (int k = 0; k < OPT; ++k) {
         if (idx[k] >= N) continue;
         const uint64_t gi = (uint64_t)r * N + idx[k];
         const float F = fmaf(A.kn, acc[k], A.omega[idx[k]]);
         float g[4];
-        gauss4_scaled(U4{(uint32_t)(A.n >> 2), idx[k], r, (uint32_t)SDE_TAG_NOISE}, A.key0, A.key1, A.c2, g);
+        gauss4_scaled(U4{(uint32_t)(n >> 2), idx[k], r, (uint32_t)SDE_TAG_NOISE}, A.key0, A.key1, A.c2, g);
         const float ns = j == 0 ? g[0] : j == 1 ? g[1] : j == 2 ? g[2] : g[3];
         const float th = A.base[gi];
         if (A.stage == 1) {
@@ -328,6 +330,49 @@ __global__ __launch_bounds__(256) void order_parameter_kernel(const float* theta
     }
 }
 
+// The same, at local step l = *nbase - step0, only when l is a multiple of
+// M (column l / M): lets one recorded chunk of steps sample where due.
+__global__ __launch_bounds__(256) void order_parameter_at_kernel(const float* theta, uint32_t N, double* out,
+                                                                 uint64_t stride, const uint64_t* nbase,
+                                                                 uint64_t step0, uint32_t M)
+{
+    const uint64_t l = load_uniform(nbase) - step0;
+    if (l % M) return;
+    __shared__ double lds[2 * 256 / kWave];
+    const uint32_t r = blockIdx.x;
+    double s = 0.0, c = 0.0;
+    for (uint32_t i = threadIdx.x; i < N; i += 256) {
+        const float t = theta[(uint64_t)r * N + i];
+        s += (double)sin_rev(t);
+        c += (double)cos_rev(t);
+    }
+    const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    s = wave_sum(s);
+    c = wave_sum(c);
+    if (lane == 0) {
+        lds[2 * wid] = s;
+        lds[2 * wid + 1] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double S = 0.0, C = 0.0;
+        for (int w = 0; w < 256 / kWave; ++w) {
+            S += lds[2 * w];
+            C += lds[2 * w + 1];
+        }
+        out[(uint64_t)r * stride + l / M] = std::sqrt(S * S + C * C) / (double)N;
+    }
+}
+
+__global__ void step_set_kernel(uint64_t* nbase, uint64_t v) { *nbase = v; }
+__global__ void step_advance_kernel(uint64_t* nbase, uint32_t by) { *nbase += by; }
+
+__global__ void copy_f32_kernel(float* dst, const float* src, uint64_t n)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
 // Initial phases theta = U(Philox(0, i, r, INIT).x0), one thread per oscillator.
 __global__ void kuramoto_init_kernel(float* theta, uint32_t N, uint32_t R, uint32_t key0, uint32_t key1)
 {
@@ -344,6 +389,35 @@ void launch_order_parameter(const float* theta, uint32_t N, uint32_t R, double* 
                             uint64_t col, hipStream_t stream)
 {
     hipLaunchKernelGGL(order_parameter_kernel, dim3(R), dim3(256), 0, stream, theta, N, out, stride, col);
+}
+
+void launch_order_parameter_at(const float* theta, uint32_t N, uint32_t R, double* out, uint64_t stride,
+                               const uint64_t* nbase, uint64_t step0, uint32_t M, hipStream_t stream)
+{
+    hipLaunchKernelGGL(order_parameter_at_kernel, dim3(R), dim3(256), 0, stream, theta, N, out, stride, nbase, step0,
+                       M);
+}
+
+void launch_step_set(uint64_t* nbase, uint64_t v, hipStream_t stream)
+{
+    hipLaunchKernelGGL(step_set_kernel, dim3(1), dim3(1), 0, stream, nbase, v);
+}
+
+void launch_step_advance(uint64_t* nbase, uint32_t by, hipStream_t stream)
+{
+    hipLaunchKernelGGL(step_advance_kernel, dim3(1), dim3(1), 0, stream, nbase, by);
+}
+
+uint32_t chunk_steps(uint32_t M, uint64_t n_steps, bool even)
+{
+    // largest divisor of M that is at most 128 (and even if required), so
+    // that every sampling step is a chunk start
+    uint32_t best = 0;
+    for (uint32_t c = 1; c <= 128 && c <= M; ++c)
+        if (M % c == 0 && (!even || c % 2 == 0)) best = c;
+    if (best == 0) best = even ? 2 : 1;
+    if ((uint64_t)best > n_steps && n_steps > 0) best = (uint32_t)n_steps;
+    return best;
 }
 
 void launch_kuramoto_init(float* theta, uint32_t N, uint32_t R, uint64_t seed, hipStream_t stream)
@@ -479,11 +553,14 @@ static int run_tiled(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* ru
     void* work = nullptr;
     int st = ensure_ws(ctx, kSlotKuraWork, (size_t)2 * NR * sizeof(float), &work);
     if (st) return st;
+    uint64_t* nbase = nullptr;
+    if ((st = step_counter(ctx, &nbase))) return st;
     float* tilde = static_cast<float*>(work);
     float* F1 = tilde + NR;
     const int opt = d->N >= 4096 ? 4 : 1;
     TiledArgs A;
     A.omega = omega;
+    A.nbase = nbase;
     A.N = d->N;
     A.R = d->R;
     A.key0 = (uint32_t)run->seed;
@@ -494,34 +571,48 @@ static int run_tiled(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* ru
     A.c2 = kc.c2;
     A.F1 = F1;
     A.euler = run->scheme == SDE_EULER;
-    for (uint64_t k = 0;; ++k) {
-        if (r_samples && k % M == 0) {
-            hipLaunchKernelGGL(order_parameter_kernel, dim3(d->R), dim3(256), 0, stream, phi, d->N, r_samples,
-                               n_samples, k / M);
-            SDE_HIP(ctx, hipGetLastError());
+    // `count` steps from the device step base, then advance it
+    auto record = [&](hipStream_t s, uint32_t count) -> int {
+        if (r_samples) launch_order_parameter_at(phi, d->N, d->R, r_samples, n_samples, nbase, run->step0, M, s);
+        for (uint32_t k = 0; k < count; ++k) {
+            A.k = k;
+            A.stage = 1;
+            A.src = phi;
+            A.base = phi;
+            A.dst = tilde;  // every lane reads all of src, so no step writes in place
+            int e = opt == 4 ? launch_tiled<4>(ctx, A, s) : launch_tiled<1>(ctx, A, s);
+            if (e) return e;
+            if (A.euler) {
+                hipLaunchKernelGGL(copy_f32_kernel, dim3((uint32_t)((NR + 255) / 256)), dim3(256), 0, s, phi, tilde, NR);
+                continue;
+            }
+            A.stage = 2;
+            A.src = tilde;
+            A.base = phi;
+            A.dst = phi;
+            e = opt == 4 ? launch_tiled<4>(ctx, A, s) : launch_tiled<1>(ctx, A, s);
+            if (e) return e;
         }
-        if (k == d->n_steps) break;
-        A.n = run->step0 + k;
-        A.stage = 1;
-        A.src = phi;
-        A.base = phi;
-        A.dst = A.euler ? phi : tilde;
-        // Euler reads and writes phi in place: every lane reads all of src
-        // before any lane writes, so stage 1 of Euler uses a separate buffer.
-        if (A.euler) A.dst = tilde;
-        st = opt == 4 ? launch_tiled<4>(ctx, A, stream) : launch_tiled<1>(ctx, A, stream);
-        if (st) return st;
-        if (A.euler) {
-            SDE_HIP(ctx, hipMemcpyAsync(phi, tilde, NR * sizeof(float), hipMemcpyDeviceToDevice, stream));
-            continue;
-        }
-        A.stage = 2;
-        A.src = tilde;
-        A.base = phi;
-        A.dst = phi;
-        st = opt == 4 ? launch_tiled<4>(ctx, A, stream) : launch_tiled<1>(ctx, A, stream);
-        if (st) return st;
-    }
+        launch_step_advance(nbase, count, s);
+        SDE_HIP(ctx, hipGetLastError());
+        return SDE_OK;
+    };
+    launch_step_set(nbase, run->step0, stream);
+    const uint32_t C = chunk_steps(M, d->n_steps, false);
+    char key[256];
+    snprintf(key, sizeof key, "tiled|%p|%p|%p|%p|%u|%u|%u|%u|%a|%a|%a|%a|%d|%llu|%u|%llu", (void*)phi, (void*)omega,
+             (void*)r_samples, (void*)work, d->N, d->R, A.key0, A.key1, A.omega_scale, A.hdt2pi, A.kn, A.c2, A.euler,
+             (unsigned long long)run->step0, M, (unsigned long long)n_samples);
+    const uint64_t full = d->n_steps / C, rem = d->n_steps % C;
+    for (uint64_t c = 0; c < full; ++c)
+        if ((st = run_recorded(ctx, std::string(key) + "|C" + std::to_string(C), stream,
+                               [&](hipStream_t s) { return record(s, C); })))
+            return st;
+    if (rem && (st = run_recorded(ctx, std::string(key) + "|C" + std::to_string(rem), stream,
+                                  [&](hipStream_t s) { return record(s, (uint32_t)rem); })))
+        return st;
+    if (r_samples) launch_order_parameter_at(phi, d->N, d->R, r_samples, n_samples, nbase, run->step0, M, stream);
+    SDE_HIP(ctx, hipGetLastError());
     return SDE_OK;
 }
 

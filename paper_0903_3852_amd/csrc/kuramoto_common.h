@@ -22,6 +22,13 @@ KuraConsts kuramoto_consts(const sde_kuramoto_desc* d);
 // Order parameter of every realization of theta [R][N] into out[r*stride + col].
 void launch_order_parameter(const float* theta, uint32_t N, uint32_t R, double* out, uint64_t stride,
                             uint64_t col, hipStream_t stream);
+// Order parameter at local step *nbase - step0 when it is a multiple of M.
+void launch_order_parameter_at(const float* theta, uint32_t N, uint32_t R, double* out, uint64_t stride,
+                               const uint64_t* nbase, uint64_t step0, uint32_t M, hipStream_t stream);
+void launch_step_set(uint64_t* nbase, uint64_t v, hipStream_t stream);
+void launch_step_advance(uint64_t* nbase, uint32_t by, hipStream_t stream);
+// Steps per recorded chunk: a divisor of M (at most 128; even if asked).
+uint32_t chunk_steps(uint32_t M, uint64_t n_steps, bool even);
 // theta = U(Philox(0, i, r, INIT).x0) for every oscillator.
 void launch_kuramoto_init(float* theta, uint32_t N, uint32_t R, uint64_t seed, hipStream_t stream);
 

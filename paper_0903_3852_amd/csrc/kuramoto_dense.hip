@@ -65,7 +65,8 @@ struct DenseArgs {
     const float* omega;    // [N]
     const float* scale;    // device: {scale, 1/scale}
     uint32_t N, R, Np, Rp, Mp;
-    uint64_t n;            // absolute step
+    const uint64_t* nbase; // device: absolute step of the current chunk's first step
+    uint32_t k;            // step within the chunk
     uint32_t key0, key1;
     float omega_scale, hdt2pi, c2;
     int32_t stage;         // 1 predictor (or Euler step), 2 corrector
@@ -93,9 +94,10 @@ __device__ __forceinline__ void dense_update(const DenseArgs& A, uint32_t i, uin
     const uint64_t gi = (uint64_t)r * A.N + i;
     const float ts = A.src[gi];
     const float F = fmaf(cos_rev(ts), S, fmaf(-sin_rev(ts), C, A.omega[i]));
+    const uint64_t n = load_uniform(A.nbase) + A.k;
     float g[4];
-    gauss4_scaled(U4{(uint32_t)(A.n >> 2), i, r, (uint32_t)SDE_TAG_NOISE}, A.key0, A.key1, A.c2, g);
-    const uint32_t j = (uint32_t)A.n & 3u;
+    gauss4_scaled(U4{(uint32_t)(n >> 2), i, r, (uint32_t)SDE_TAG_NOISE}, A.key0, A.key1, A.c2, g);
+    const uint32_t j = (uint32_t)n & 3u;
     const float ns = j == 0 ? g[0] : j == 1 ? g[1] : j == 2 ? g[2] : g[3];
     const float th = A.base[gi];
     float t;
@@ -425,49 +427,74 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
     A.F1 = F1;
     A.euler = run->scheme == SDE_EULER;
     const dim3 grid((Mp / kRowTile) * (Rp / kRealTile));
-    auto launch = [&]() -> int {
+    uint64_t* nbase = nullptr;
+    if ((st = step_counter(ctx, &nbase))) return st;
+    A.nbase = nbase;
+    auto launch = [&](hipStream_t s) -> int {
         if constexpr (sizeof(T) == 4)
-            hipLaunchKernelGGL(dense_fp32_kernel, grid, dim3(kDenseThreads), 0, stream, A);
+            hipLaunchKernelGGL(dense_fp32_kernel, grid, dim3(kDenseThreads), 0, s, A);
         else if constexpr (__is_same(T, __bf16))
-            hipLaunchKernelGGL((dense_mfma_kernel<__bf16, bf16x8>), grid, dim3(kDenseThreads), 0, stream, A);
+            hipLaunchKernelGGL((dense_mfma_kernel<__bf16, bf16x8>), grid, dim3(kDenseThreads), 0, s, A);
         else
-            hipLaunchKernelGGL((dense_mfma_kernel<_Float16, f16x8>), grid, dim3(kDenseThreads), 0, stream, A);
+            hipLaunchKernelGGL((dense_mfma_kernel<_Float16, f16x8>), grid, dim3(kDenseThreads), 0, s, A);
         SDE_HIP(ctx, hipGetLastError());
         return SDE_OK;
     };
-    for (uint64_t k = 0;; ++k) {
-        if (r_samples && k % M == 0) {
-            launch_order_parameter(phi, N, R, r_samples, n_samples, k / M, stream);
-            SDE_HIP(ctx, hipGetLastError());
+    // `count` steps from the device step base, then advance it.  The operand
+    // buffers alternate per stage; chunks hold an even number of stages so a
+    // recorded chunk always starts from the same buffer.
+    void* Bb_hi[2] = {Bcur_hi, Bnext_hi};
+    void* Bb_lo[2] = {Bcur_lo, Bnext_lo};
+    auto record = [&](hipStream_t s, uint32_t count) -> int {
+        if (r_samples) launch_order_parameter_at(phi, N, R, r_samples, n_samples, nbase, run->step0, M, s);
+        int cur = 0;
+        for (uint32_t k = 0; k < count; ++k) {
+            A.k = k;
+            // stage 1: drift at theta_n; Euler finishes the step in place
+            A.stage = 1;
+            A.Bhi = Bb_hi[cur];
+            A.Blo = Bb_lo[cur];
+            A.Bhi_next = Bb_hi[cur ^ 1];
+            A.Blo_next = Bb_lo[cur ^ 1];
+            A.src = phi;
+            A.base = phi;
+            A.dst = A.euler ? phi : tilde;
+            int e = launch(s);
+            if (e) return e;
+            cur ^= 1;
+            if (A.euler) continue;
+            // stage 2: drift at the predictor; corrector into phi
+            A.stage = 2;
+            A.Bhi = Bb_hi[cur];
+            A.Blo = Bb_lo[cur];
+            A.Bhi_next = Bb_hi[cur ^ 1];
+            A.Blo_next = Bb_lo[cur ^ 1];
+            A.src = tilde;
+            A.base = phi;
+            A.dst = phi;
+            if ((e = launch(s))) return e;
+            cur ^= 1;
         }
-        if (k == d->n_steps) break;
-        A.n = run->step0 + k;
-        // stage 1: drift at theta_n (operand Bcur); Euler finishes the step
-        A.stage = 1;
-        A.Bhi = Bcur_hi;
-        A.Blo = Bcur_lo;
-        A.Bhi_next = Bnext_hi;
-        A.Blo_next = Bnext_lo;
-        A.src = phi;
-        A.base = phi;
-        A.dst = A.euler ? phi : tilde;
-        if ((st = launch())) return st;
-        std::swap(Bcur_hi, Bnext_hi);
-        std::swap(Bcur_lo, Bnext_lo);
-        if (A.euler) continue;
-        // stage 2: drift at the predictor; corrector into phi
-        A.stage = 2;
-        A.Bhi = Bcur_hi;
-        A.Blo = Bcur_lo;
-        A.Bhi_next = Bnext_hi;
-        A.Blo_next = Bnext_lo;
-        A.src = tilde;
-        A.base = phi;
-        A.dst = phi;
-        if ((st = launch())) return st;
-        std::swap(Bcur_hi, Bnext_hi);
-        std::swap(Bcur_lo, Bnext_lo);
-    }
+        launch_step_advance(nbase, count, s);
+        SDE_HIP(ctx, hipGetLastError());
+        return SDE_OK;
+    };
+    launch_step_set(nbase, run->step0, stream);
+    const uint32_t C = chunk_steps(M, d->n_steps, A.euler != 0);
+    char key[320];
+    snprintf(key, sizeof key, "dense%d|%p|%p|%p|%p|%p|%p|%u|%u|%u|%u|%a|%a|%a|%d|%llu|%u|%llu", d->coupling,
+             (void*)phi, (void*)omega, (void*)r_samples, wa, wb, wk, N, R, A.key0, A.key1, A.omega_scale, A.hdt2pi,
+             A.c2, A.euler, (unsigned long long)run->step0, M, (unsigned long long)n_samples);
+    const uint64_t full = d->n_steps / C, rem = d->n_steps % C;
+    for (uint64_t c = 0; c < full; ++c)
+        if ((st = run_recorded(ctx, std::string(key) + "|C" + std::to_string(C), stream,
+                               [&](hipStream_t s) { return record(s, C); })))
+            return st;
+    if (rem && (st = run_recorded(ctx, std::string(key) + "|C" + std::to_string(rem), stream,
+                                  [&](hipStream_t s) { return record(s, (uint32_t)rem); })))
+        return st;
+    if (r_samples) launch_order_parameter_at(phi, N, R, r_samples, n_samples, nbase, run->step0, M, stream);
+    SDE_HIP(ctx, hipGetLastError());
     return SDE_OK;
 }
 

@@ -3,7 +3,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstdlib>
+#include <fstream>
 #include <new>
+#include <sstream>
 
 #include "sde_internal.h"
 
@@ -26,6 +29,7 @@ int ensure_ws(sde_ctx* ctx, int slot, size_t bytes, void** out)
             b.bytes = 0;
             ctx->uploaded[slot].clear();
         }
+        ++ctx->ws_generation;  // recorded graphs refer to the old address
         size_t cap = bytes < 4096 ? 4096 : bytes + bytes / 4;
         if (hipMalloc(&b.ptr, cap) != hipSuccess) {
             (void)hipGetLastError();
@@ -74,6 +78,7 @@ int ensure_counters(sde_ctx* ctx, size_t n)
         SDE_HIP(ctx, hipDeviceSynchronize());
         SDE_HIP(ctx, hipFree(ctx->counters));
         ctx->counters = nullptr;
+        ++ctx->ws_generation;
     }
     size_t cap = n < 1024 ? 1024 : n;
     if (hipMalloc(&ctx->counters, cap * sizeof(uint32_t)) != hipSuccess) {
@@ -109,6 +114,124 @@ int sync_and_check(sde_ctx* ctx, hipStream_t stream)
     return SDE_OK;
 }
 
+// ---------------------------------------------------------------- graphs --
+static void drop_graph(GraphEntry& g)
+{
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g.exec = nullptr;
+}
+
+int run_recorded(sde_ctx* ctx, const std::string& key, hipStream_t stream,
+                 const std::function<int(hipStream_t)>& record)
+{
+    ctx->last.graph_replayed = 0;
+    if (!ctx->use_graphs) return record(stream);
+    if (ctx->graphs_generation != ctx->ws_generation) {
+        // a workspace moved: every recorded graph may refer to freed memory
+        for (GraphEntry& g : ctx->graphs) drop_graph(g);
+        ctx->graphs.clear();
+        ctx->graphs_generation = ctx->ws_generation;
+    }
+    const std::string& full = key;
+    for (GraphEntry& g : ctx->graphs) {
+        if (g.key == full) {
+            g.last_use = ++ctx->graph_clock;
+            SDE_HIP(ctx, hipGraphLaunch(g.exec, stream));
+            ctx->last.graph_replayed = 1;
+            return SDE_OK;
+        }
+    }
+    if (!ctx->capture_stream) SDE_HIP(ctx, hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking));
+    SDE_HIP(ctx, hipStreamBeginCapture(ctx->capture_stream, hipStreamCaptureModeThreadLocal));
+    int st = record(ctx->capture_stream);
+    hipGraph_t graph = nullptr;
+    hipError_t e = hipStreamEndCapture(ctx->capture_stream, &graph);
+    if (st != SDE_OK) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return st;
+    }
+    if (e != hipSuccess) return fail(ctx, SDE_ERR_DEVICE, "graph capture failed: %s", hipGetErrorString(e));
+    hipGraphExec_t exec = nullptr;
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return fail(ctx, SDE_ERR_DEVICE, "graph instantiation failed: %s", hipGetErrorString(e));
+    // keep at most 32 graphs: drop the least recently used
+    if (ctx->graphs.size() >= 32) {
+        auto lru = std::min_element(ctx->graphs.begin(), ctx->graphs.end(),
+                                    [](const GraphEntry& a, const GraphEntry& b) { return a.last_use < b.last_use; });
+        drop_graph(*lru);
+        ctx->graphs.erase(lru);
+    }
+    GraphEntry g;
+    g.key = full;
+    g.exec = exec;
+    g.last_use = ++ctx->graph_clock;
+    ctx->graphs.push_back(g);
+    SDE_HIP(ctx, hipGraphLaunch(exec, stream));
+    return SDE_OK;
+}
+
+// ------------------------------------------------------------ tune cache --
+// The cache file is a flat JSON object {"key": integer, ...}.
+static void tune_load(sde_ctx* ctx)
+{
+    std::ifstream in(ctx->tune_path);
+    if (!in) return;
+    std::stringstream ss;
+    ss << in.rdbuf();
+    const std::string t = ss.str();
+    size_t p = 0;
+    while ((p = t.find('"', p)) != std::string::npos) {
+        const size_t q = t.find('"', p + 1);
+        if (q == std::string::npos) break;
+        const std::string key = t.substr(p + 1, q - p - 1);
+        const size_t c = t.find(':', q);
+        if (c == std::string::npos) break;
+        ctx->tune[key] = std::atoi(t.c_str() + c + 1);
+        p = t.find_first_of(",}", c);
+        if (p == std::string::npos) break;
+    }
+}
+
+static void tune_save(sde_ctx* ctx)
+{
+    if (ctx->tune_path.empty()) return;
+    const std::string tmp = ctx->tune_path + ".tmp";
+    {
+        std::ofstream out(tmp);
+        if (!out) return;
+        out << "{\n";
+        size_t i = 0;
+        for (const auto& kv : ctx->tune)
+            out << "  \"" << kv.first << "\": " << kv.second << (++i < ctx->tune.size() ? ",\n" : "\n");
+        out << "}\n";
+    }
+    (void)std::rename(tmp.c_str(), ctx->tune_path.c_str());
+}
+
+bool tune_lookup(sde_ctx* ctx, const std::string& key, int* value)
+{
+    auto it = ctx->tune.find(key);
+    if (it == ctx->tune.end()) return false;
+    *value = it->second;
+    return true;
+}
+
+void tune_store(sde_ctx* ctx, const std::string& key, int value)
+{
+    ctx->tune[key] = value;
+    tune_save(ctx);
+}
+
+int step_counter(sde_ctx* ctx, uint64_t** out)
+{
+    void* p = nullptr;
+    int st = ensure_ws(ctx, kSlotStep, 64, &p);
+    if (st) return st;
+    *out = static_cast<uint64_t*>(p);
+    return SDE_OK;
+}
+
 }  // namespace sde
 
 using namespace sde;
@@ -134,9 +257,13 @@ int sde_create(int hip_device, sde_ctx** out)
     ctx->n_cu = prop.multiProcessorCount;
     ctx->arch = prop.gcnArchName;
     if (hipMalloc(&ctx->flag, sizeof(int)) != hipSuccess || hipMemset(ctx->flag, 0, sizeof(int)) != hipSuccess ||
-        ensure_counters(ctx, 1024) != SDE_OK) {
+        hipMalloc(&ctx->tune_flag, sizeof(int)) != hipSuccess || ensure_counters(ctx, 1024) != SDE_OK) {
         sde_destroy(ctx);
         return SDE_ERR_NOMEM;
+    }
+    if (const char* tc = std::getenv("SDE_TUNE_CACHE")) {
+        ctx->tune_path = tc;
+        tune_load(ctx);
     }
     *out = ctx;
     return SDE_OK;
@@ -153,9 +280,49 @@ void sde_destroy(sde_ctx* ctx)
         if (s.host) (void)hipHostFree(s.host);
         if (s.done) (void)hipEventDestroy(s.done);
     }
+    for (auto& g : ctx->graphs) drop_graph(g);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     if (ctx->flag) (void)hipFree(ctx->flag);
+    if (ctx->tune_flag) (void)hipFree(ctx->tune_flag);
     if (ctx->counters) (void)hipFree(ctx->counters);
     delete ctx;
+}
+
+int sde_set_option(sde_ctx* ctx, int option, int64_t value)
+{
+    if (!ctx) return SDE_ERR_INVALID;
+    switch (option) {
+    case SDE_OPT_AUTOTUNE:
+        if (value != 0 && value != 1) break;
+        ctx->autotune = (int)value;
+        return SDE_OK;
+    case SDE_OPT_GRAPHS:
+        if (value != 0 && value != 1) break;
+        ctx->use_graphs = (int)value;
+        return SDE_OK;
+    case SDE_OPT_JJ_PPT:
+        if (value != 0 && value != 1 && value != 2 && value != 4) break;
+        ctx->jj_ppt = (int)value;
+        return SDE_OK;
+    default: break;
+    }
+    return fail(ctx, SDE_ERR_INVALID, "option %d: invalid value %lld", option, (long long)value);
+}
+
+int sde_set_tune_cache(sde_ctx* ctx, const char* path)
+{
+    if (!ctx) return SDE_ERR_INVALID;
+    ctx->tune_path = path ? path : "";
+    if (path) tune_load(ctx);
+    return SDE_OK;
+}
+
+int sde_get_stats(const sde_ctx* ctx, sde_stats* out)
+{
+    if (!ctx || !out) return SDE_ERR_INVALID;
+    *out = ctx->last;
+    out->graphs_cached = (int32_t)ctx->graphs.size();
+    return SDE_OK;
 }
 
 const char* sde_strerror(int status)

@@ -8,6 +8,8 @@
 #include <cstdint>
 #include <cstdio>
 #include <cstring>
+#include <functional>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -30,7 +32,11 @@ struct Staging {
     bool pending = false;
 };
 
-struct TuneEntry;
+struct GraphEntry {
+    std::string key;
+    hipGraphExec_t exec = nullptr;
+    uint64_t last_use = 0;
+};
 
 }  // namespace sde
 
@@ -41,11 +47,24 @@ struct sde_ctx {
     std::string arch;
     std::string last_error;
     int* flag = nullptr;          // device: nonzero once a state became NaN/Inf
+    int* tune_flag = nullptr;     // device: the same for autotuner trial runs (never reported)
     uint32_t* counters = nullptr; // device: work-queue counters and barrier words
     size_t n_counters = 0;
     sde::DevBuf ws[16];           // device workspaces, by slot (see sde::Slot)
     sde::Staging staging[4];
     std::vector<unsigned char> uploaded[16];  // host copy of what each slot holds
+    uint64_t ws_generation = 0;   // bumped whenever a workspace moves (invalidates graphs)
+    // launch layer
+    hipStream_t capture_stream = nullptr;
+    std::vector<sde::GraphEntry> graphs;
+    uint64_t graph_clock = 0;
+    uint64_t graphs_generation = 0;  // ws_generation the cached graphs were recorded at
+    int use_graphs = 1;
+    int autotune = 1;
+    int jj_ppt = 0;               // 0 = tuned
+    std::map<std::string, int> tune;
+    std::string tune_path;
+    sde_stats last{};
 };
 
 namespace sde {
@@ -62,6 +81,8 @@ enum Slot {
     kSlotDenseB = 8,
     kSlotDenseOut = 9,
     kSlotMisc = 10,
+    kSlotStep = 11,
+    kSlotTune = 12,
 };
 
 // Status helpers -----------------------------------------------------------
@@ -99,6 +120,19 @@ int ensure_counters(sde_ctx* ctx, size_t n);
 int sync_and_check(sde_ctx* ctx, hipStream_t stream);
 
 inline bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+// Records a launch sequence with `record(s)` on stream s.  With graphs on,
+// the sequence is captured once (on the context's private stream) into a
+// HIP graph stored under `key` (+ the workspace generation) and replayed on
+// `stream`; otherwise `record(stream)` launches directly.  `record` must
+// only enqueue kernels (no allocation, no synchronization, no memset).
+int run_recorded(sde_ctx* ctx, const std::string& key, hipStream_t stream,
+                 const std::function<int(hipStream_t)>& record);
+// Tune cache: look up / store an integer choice under `key`.
+bool tune_lookup(sde_ctx* ctx, const std::string& key, int* value);
+void tune_store(sde_ctx* ctx, const std::string& key, int value);
+// Small device-side counters of the step loops (one uint64 per use).
+int step_counter(sde_ctx* ctx, uint64_t** out);
 
 // Launchers implemented in the kernel translation units.
 int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run,
