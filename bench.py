@@ -210,6 +210,93 @@ def bench_jj_batch(args, sde, torch, dev):
                          "traffic": None}}
 
 
+SURR_CENTER = [4.0, 5.0, 0.25, -2.5, 1.0]   # features (a, omega, f, log10 D, gamma) -> [-1, 1]
+SURR_SCALE = [2.0, 2.0, 0.25, 1.5, 0.5]
+
+
+def _surr_points(sde, P, paths, steps):
+    return sde.make_points_np(m=1.0, gamma=P[:, 4], a=P[:, 0], omega=P[:, 1], f=P[:, 2], D=P[:, 3],
+                              n_paths=paths, steps_per_period=200, n_steps=steps, n_transient=steps // 2)
+
+
+def bench_surrogate(args, sde, torch, dev, n_train=100000, n_query=1000000, epochs=30):
+    """The learned <v> surrogate on the batch parameter distribution: labels
+    simulated by the integrator (512 paths x 1e5 steps, half transient,
+    dt = 2pi/omega/200), 5 members of 5-256-256-256-1 trained on the GPU,
+    error against 4096 held-out points simulated at 4096 paths, and a scan of
+    1e6 queries with fallback where the ensemble spread exceeds 0.02.  The
+    plain method simulates every query with the same 512 x 1e5 budget; its
+    time is measured on 1e4 queries and scaled linearly (the queries are
+    independent)."""
+    ctx = sde.sde_create(0)
+    stream = torch.cuda.current_stream()
+
+    def ev():
+        return torch.cuda.Event(enable_timing=True)
+
+    def simulate(P, paths, steps, seed):
+        pts = _surr_points(sde, P, paths, steps)
+        ps = torch.empty((len(P), 2), dtype=torch.float64, device=dev)
+        s, e = ev(), ev()
+        s.record(stream)
+        sde.sde_jj_integrate(ctx, pts, sde.make_run(seed), point_sums=ps)
+        e.record(stream)
+        torch.cuda.synchronize()
+        return ps.cpu().numpy()[:, 0] / paths, s.elapsed_time(e) / 1e3
+
+    seed = sde_inputs.seed_of(5)
+    Ptr = sde_inputs.jj_random_params(n_train, seed + 50)
+    ytr, t_labels = simulate(Ptr, 512, 100000, seed + 51)
+    Pho = sde_inputs.jj_random_params(4096, seed + 60)
+    yho, _ = simulate(Pho, 4096, 100000, seed + 61)
+
+    def feats(P):
+        X = P.astype(np.float64).copy()
+        X[:, 3] = np.log10(X[:, 3])
+        return torch.from_numpy(X.astype(np.float32)).to(dev)
+
+    sur = sde.sde_surrogate_create(ctx, [5, 256, 256, 256, 1], 5, seed + 70)
+    sde.sde_surrogate_set_scaling(sur, sde.make_scaling(SURR_CENTER, SURR_SCALE, float(ytr.mean()),
+                                                        float(ytr.std()), 0))
+    t0 = time.perf_counter()
+    curve = sde.sde_surrogate_train(sur, feats(Ptr), torch.from_numpy(ytr.astype(np.float32)).to(dev),
+                                    sde.make_train_opts(epochs, 1024, lr=1e-3, shuffle_seed=seed + 71))
+    t_train = time.perf_counter() - t0
+    # held-out error of the scan (prediction or fallback simulation)
+    qho = _surr_points(sde, Pho, 512, 100000)
+    vho = torch.empty(4096, dtype=torch.float64, device=dev)
+    uho = torch.empty(4096, dtype=torch.uint8, device=dev)
+    sde.sde_surrogate_scan(sur, qho, 0.02, sde.make_run(seed + 80), vho, uho)
+    err = np.abs(vho.cpu().numpy() - yho)
+    r2 = 1.0 - np.mean((vho.cpu().numpy() - yho) ** 2) / np.var(yho)
+    # the 1e6-query scan
+    Pq = sde_inputs.jj_random_params(n_query, seed + 90)
+    queries = _surr_points(sde, Pq, 512, 100000)
+    vq = torch.empty(n_query, dtype=torch.float64, device=dev)
+    uq = torch.empty(n_query, dtype=torch.uint8, device=dev)
+    sde.sde_surrogate_scan(sur, _surr_points(sde, Pq[:1000], 512, 100000), 0.02, sde.make_run(seed + 91),
+                           vq, uq)  # warm-up
+    t0 = time.perf_counter()
+    st = sde.sde_surrogate_scan(sur, queries, 0.02, sde.make_run(seed + 91), vq, uq)
+    t_scan = time.perf_counter() - t0
+    # the plain method on a 1e4-query subset, scaled to 1e6
+    _, t_plain_sub = simulate(Pq[:10000], 512, 100000, seed + 91)
+    t_plain = t_plain_sub * n_query / 10000
+    sde.sde_surrogate_destroy(sur)
+    sde.sde_destroy(ctx)
+    return {"workload": "jj_surrogate", "train_points": n_train, "label_budget": "512 paths x 1e5 steps",
+            "label_seconds": t_labels, "train_seconds": t_train, "epochs": epochs,
+            "loss_first_last": [float(curve[0]), float(curve[-1])],
+            "holdout": {"points": 4096, "paths": 4096, "mae": float(err.mean()),
+                        "p95": float(np.quantile(err, 0.95)), "max": float(err.max()), "r2": r2,
+                        "label_std": float(yho.std()), "mae_of_zero": float(np.abs(yho).mean()),
+                        "fallback": int(uho.cpu().numpy().sum())},
+            "scan": {"queries": n_query, "spread_max": 0.02, "fallback": int(st["n_fallback"]),
+                     "predict_ms": st["predict_ms"], "fallback_ms": st["fallback_ms"],
+                     "total_s": t_scan, "queries_per_s": n_query / t_scan},
+            "plain_simulation_s": t_plain, "speedup": t_plain / t_scan}
+
+
 KURA = {
     "kuramoto_mf": dict(cfg="uniform", coupling=0, scheme=0, steps=100000),
     "kuramoto_mf_em": dict(cfg="uniform", coupling=0, scheme=1, steps=100000),
@@ -284,7 +371,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="jj_scan", choices=["jj_scan", "jj_batch"] + sorted(KURA))
+    ap.add_argument("--workload", default="jj_scan",
+                    choices=["jj_scan", "jj_batch", "jj_surrogate"] + sorted(KURA))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kuramoto", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -313,8 +401,11 @@ def main():
             jb["tail_efficiency"] = jb["path_steps_per_s"] / (out["config"]["path_steps_per_step"] /
                                                             (out["kernel_ms"] / 1e3))
             out["jj_batch"] = jb
+            out["surrogate"] = bench_surrogate(args, sde, torch, dev)
     elif args.workload == "jj_batch":
         out = bench_jj_batch(args, sde, torch, dev)
+    elif args.workload == "jj_surrogate":
+        out = bench_surrogate(args, sde, torch, dev)
     else:
         out = bench_kuramoto(args.workload, args, sde, torch, dev, reps=args.steps)
     if args.calibrate_copy:

@@ -194,6 +194,84 @@ int sde_observables(sde_ctx* ctx, int kind, const void* dev_in /* [device] */,
                     const uint32_t* counts /* [host] */, uint32_t n_groups,
                     double* host_out /* [host] [n_groups][2] */, void* hip_stream);
 
+/* ---- learned surrogate for the mean velocity <v> ------------------------- */
+/*
+ * An ensemble of small fully connected networks maps the parameters of a
+ * Josephson-junction point to its time- and ensemble-averaged velocity <v>
+ * (the asymptotic velocity <<v>> of Sec. 5), trained on averages the
+ * integrator produces itself.  Member m (of n_members) has layers
+ *   h_l = GELU(W_l h_{l-1} + b_l), l < L,   y = W_L h_{L-1} + b_L,
+ * GELU(z) = z (1 + erf(z / sqrt 2)) / 2, all FP32.  Parameters of a member
+ * are packed W_1, b_1, W_2, b_2, ... row-major (W_l is [w_l][w_{l-1}]).
+ * Raw input features of a point are (a, omega, f, log10 D, gamma); they are
+ * normalized with the scaling below before entering the network.
+ * Calls on a surrogate are ordered on its context (one host thread).
+ */
+typedef struct sde_surrogate sde_surrogate;
+typedef struct {
+    float in_center[8];        /* x_i -> (x_i - in_center[i]) / in_scale[i]            */
+    float in_scale[8];
+    float out_mean, out_std;   /* network output y -> out_mean + out_std * y           */
+    int32_t target_over_omega; /* 1: the network predicts <v> / omega (feature 1)      */
+    int32_t reserved;          /* must be 0                                            */
+} sde_surrogate_scaling;
+typedef struct {
+    uint32_t epochs;           /* passes over the samples                              */
+    uint32_t batch;            /* minibatch size; a last partial batch is dropped      */
+    float lr, beta1, beta2, eps; /* Adam with bias correction                          */
+    uint64_t shuffle_seed;     /* each member sees its own permutation per epoch       */
+} sde_train_opts;
+typedef struct {
+    uint64_t n_queries, n_fallback;
+    double predict_ms;         /* ensemble inference (device time)                     */
+    double fallback_ms;        /* simulation of the uncertain points (device time)     */
+    double total_ms;           /* whole call, host wall clock                          */
+} sde_scan_stats;
+
+/* Creates a surrogate with layer widths widths[0..n_widths-1] (input width
+ * first, output width 1 last), n_members members, parameters drawn
+ * U(-1/sqrt(fan_in), 1/sqrt(fan_in)) from Philox(ctr = (k >> 2, member, 0,
+ * 5), key = seed) word k & 3 for packed parameter k; identity scaling. */
+int sde_surrogate_create(sde_ctx* ctx, const uint32_t* widths /* [host] */, uint32_t n_widths,
+                         uint32_t n_members, uint64_t seed, sde_surrogate** out);
+void sde_surrogate_destroy(sde_surrogate* s);
+/* Parameters per member. */
+uint64_t sde_surrogate_param_count(const sde_surrogate* s);
+/* Copy one member's packed parameters from / to host memory (synchronous);
+ * setting parameters also resets that member's Adam state. */
+int sde_surrogate_set_params(sde_surrogate* s, uint32_t member, const float* host, uint64_t n);
+int sde_surrogate_get_params(sde_surrogate* s, uint32_t member, float* host, uint64_t n);
+int sde_surrogate_set_scaling(sde_surrogate* s, const sde_surrogate_scaling* sc);
+int sde_surrogate_get_scaling(const sde_surrogate* s, sde_surrogate_scaling* sc);
+/* Trains every member on (X [device] [n][w_0] raw features, y [device] [n]
+ * targets <v>) with mean-squared error and Adam; loss_curve [host]
+ * [epochs] (or NULL) receives each epoch's mean minibatch loss of member 0
+ * (in normalized units).  Synchronizes. */
+int sde_surrogate_train(sde_surrogate* s, const float* X, const float* y, uint64_t n,
+                        const sde_train_opts* opts, float* loss_curve, void* hip_stream);
+/* Ensemble prediction for X [device] [n][w_0]: mean [device] [n] and
+ * spread [device] [n] (sample standard deviation over members, n - 1 in
+ * the denominator), both in units of <v>. */
+int sde_surrogate_predict(sde_surrogate* s, const float* X, uint64_t n, float* mean, float* spread,
+                          void* hip_stream);
+/* Test hook: mean-squared loss and its gradient (packed like the
+ * parameters, [host] or NULL) of one member on (X, y), computed with the
+ * training kernels at the member's current parameters.  Synchronizes. */
+int sde_surrogate_loss_grad(sde_surrogate* s, uint32_t member, const float* X, const float* y, uint64_t n,
+                            float* host_grad, double* host_loss, void* hip_stream);
+/* Scan: <v> for n query points [host] (their m must be 1).  The ensemble
+ * predicts every point; where its spread exceeds spread_max the point is
+ * integrated instead (sde_jj_integrate with its own n_paths, n_steps,
+ * n_transient and steps_per_period, and `fallback`'s seed and scheme).
+ * v_out [device] [n] receives the prediction or the simulated <v>;
+ * used_fallback [device] [n] (or NULL) 1 where simulated.  Synchronizes. */
+int sde_surrogate_scan(sde_surrogate* s, const sde_jj_point* queries, uint64_t n, float spread_max,
+                       const sde_run* fallback, double* v_out, uint8_t* used_fallback,
+                       sde_scan_stats* stats, void* hip_stream);
+/* Save (widths, members, scaling, parameters) to a binary file / load it. */
+int sde_surrogate_save(const sde_surrogate* s, const char* path);
+int sde_surrogate_load(sde_ctx* ctx, const char* path, sde_surrogate** out);
+
 /* ---- launch layer: autotuner, graph cache, statistics --------------------- */
 enum {
     SDE_OPT_AUTOTUNE = 1, /* 1 (default): on a tune-cache miss, time the candidate   */

@@ -30,7 +30,11 @@ SDE_OPT_AUTOTUNE, SDE_OPT_GRAPHS, SDE_OPT_JJ_PPT = 1, 2, 3
 EXPORTS = ["sde_create", "sde_destroy", "sde_strerror", "sde_last_error", "sde_check",
            "sde_jj_integrate", "sde_kuramoto_integrate", "sde_observables",
            "sde_debug_philox", "sde_debug_gauss", "sde_set_option", "sde_set_tune_cache",
-           "sde_get_stats"]
+           "sde_get_stats", "sde_surrogate_create", "sde_surrogate_destroy",
+           "sde_surrogate_param_count", "sde_surrogate_set_params", "sde_surrogate_get_params",
+           "sde_surrogate_set_scaling", "sde_surrogate_get_scaling", "sde_surrogate_train",
+           "sde_surrogate_predict", "sde_surrogate_loss_grad", "sde_surrogate_scan",
+           "sde_surrogate_save", "sde_surrogate_load"]
 
 
 class SDEError(RuntimeError):
@@ -56,6 +60,24 @@ class sde_stats(ctypes.Structure):
     _fields_ = [("graph_replayed", ctypes.c_int32), ("tuned", ctypes.c_int32),
                 ("jj_paths_per_lane", ctypes.c_int32), ("graphs_cached", ctypes.c_int32),
                 ("tune_ms", ctypes.c_double), ("work_items", ctypes.c_uint64)]
+
+
+class sde_surrogate_scaling(ctypes.Structure):
+    _fields_ = [("in_center", ctypes.c_float * 8), ("in_scale", ctypes.c_float * 8),
+                ("out_mean", ctypes.c_float), ("out_std", ctypes.c_float),
+                ("target_over_omega", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class sde_train_opts(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_uint32), ("batch", ctypes.c_uint32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
+                ("shuffle_seed", ctypes.c_uint64)]
+
+
+class sde_scan_stats(ctypes.Structure):
+    _fields_ = [("n_queries", ctypes.c_uint64), ("n_fallback", ctypes.c_uint64),
+                ("predict_ms", ctypes.c_double), ("fallback_ms", ctypes.c_double),
+                ("total_ms", ctypes.c_double)]
 
 
 class sde_kuramoto_desc(ctypes.Structure):
@@ -106,6 +128,34 @@ def lib():
         L.sde_set_tune_cache.restype = i32
         L.sde_get_stats.argtypes = [vp, ctypes.POINTER(sde_stats)]
         L.sde_get_stats.restype = i32
+        fp = ctypes.POINTER(ctypes.c_float)
+        L.sde_surrogate_create.argtypes = [vp, ctypes.POINTER(u32), u32, u32, u64, ctypes.POINTER(vp)]
+        L.sde_surrogate_create.restype = i32
+        L.sde_surrogate_destroy.argtypes = [vp]
+        L.sde_surrogate_destroy.restype = None
+        L.sde_surrogate_param_count.argtypes = [vp]
+        L.sde_surrogate_param_count.restype = u64
+        L.sde_surrogate_set_params.argtypes = [vp, u32, fp, u64]
+        L.sde_surrogate_set_params.restype = i32
+        L.sde_surrogate_get_params.argtypes = [vp, u32, fp, u64]
+        L.sde_surrogate_get_params.restype = i32
+        L.sde_surrogate_set_scaling.argtypes = [vp, ctypes.POINTER(sde_surrogate_scaling)]
+        L.sde_surrogate_set_scaling.restype = i32
+        L.sde_surrogate_get_scaling.argtypes = [vp, ctypes.POINTER(sde_surrogate_scaling)]
+        L.sde_surrogate_get_scaling.restype = i32
+        L.sde_surrogate_train.argtypes = [vp, vp, vp, u64, ctypes.POINTER(sde_train_opts), fp, vp]
+        L.sde_surrogate_train.restype = i32
+        L.sde_surrogate_predict.argtypes = [vp, vp, u64, vp, vp, vp]
+        L.sde_surrogate_predict.restype = i32
+        L.sde_surrogate_loss_grad.argtypes = [vp, u32, vp, vp, u64, fp, ctypes.POINTER(ctypes.c_double), vp]
+        L.sde_surrogate_loss_grad.restype = i32
+        L.sde_surrogate_scan.argtypes = [vp, ctypes.POINTER(sde_jj_point), u64, ctypes.c_float,
+                                         ctypes.POINTER(sde_run), vp, vp, ctypes.POINTER(sde_scan_stats), vp]
+        L.sde_surrogate_scan.restype = i32
+        L.sde_surrogate_save.argtypes = [vp, ctypes.c_char_p]
+        L.sde_surrogate_save.restype = i32
+        L.sde_surrogate_load.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(vp)]
+        L.sde_surrogate_load.restype = i32
         _lib = L
     return _lib
 
@@ -180,6 +230,23 @@ def make_points(params):
     return arr
 
 
+JJ_POINT_DTYPE = np.dtype([("m", "<f8"), ("gamma", "<f8"), ("a", "<f8"), ("omega", "<f8"),
+                           ("f", "<f8"), ("D", "<f8"), ("n_paths", "<u4"),
+                           ("steps_per_period", "<u4"), ("n_steps", "<u8"), ("n_transient", "<u8")])
+
+
+def make_points_np(**cols):
+    """Vectorized make_points: keyword arrays (or scalars) for every field
+    of sde_jj_point; returns a ctypes array viewing one numpy buffer."""
+    n = max(np.size(v) for v in cols.values())
+    arr = np.zeros(n, dtype=JJ_POINT_DTYPE)
+    for k in JJ_POINT_DTYPE.names:
+        arr[k] = cols[k]
+    out = (sde_jj_point * n).from_buffer(arr)
+    out._keep = arr
+    return out
+
+
 def make_run(seed, step0=0, scheme=SDE_HEUN, init=SDE_INIT_PHILOX, sample_every=0, sync=0):
     return sde_run(seed, step0, scheme, init, sample_every, sync)
 
@@ -235,3 +302,103 @@ def sde_get_stats(ctx):
     st = sde_stats()
     _check(ctx, lib().sde_get_stats(ctx, ctypes.byref(st)))
     return {k: getattr(st, k) for k, _ in sde_stats._fields_}
+
+
+# ---- surrogate ---------------------------------------------------------------
+# A surrogate handle is (ctx, pointer): errors are reported through its context.
+def sde_surrogate_create(ctx, widths, n_members, seed):
+    w = (ctypes.c_uint32 * len(widths))(*widths)
+    h = ctypes.c_void_p()
+    _check(ctx, lib().sde_surrogate_create(ctx, w, len(widths), n_members, seed, ctypes.byref(h)))
+    return (ctx, h.value)
+
+
+def sde_surrogate_destroy(s):
+    lib().sde_surrogate_destroy(s[1])
+
+
+def sde_surrogate_param_count(s):
+    return int(lib().sde_surrogate_param_count(s[1]))
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+def sde_surrogate_set_params(s, member, params):
+    p = np.ascontiguousarray(params, dtype=np.float32)
+    return _check(s[0], lib().sde_surrogate_set_params(s[1], member, _fptr(p), p.size))
+
+
+def sde_surrogate_get_params(s, member):
+    p = np.empty(sde_surrogate_param_count(s), dtype=np.float32)
+    _check(s[0], lib().sde_surrogate_get_params(s[1], member, _fptr(p), p.size))
+    return p
+
+
+def make_scaling(in_center, in_scale, out_mean=0.0, out_std=1.0, target_over_omega=0):
+    sc = sde_surrogate_scaling()
+    for i in range(8):
+        sc.in_center[i] = in_center[i] if i < len(in_center) else 0.0
+        sc.in_scale[i] = in_scale[i] if i < len(in_scale) else 1.0
+    sc.out_mean, sc.out_std, sc.target_over_omega, sc.reserved = out_mean, out_std, target_over_omega, 0
+    return sc
+
+
+def sde_surrogate_set_scaling(s, sc):
+    return _check(s[0], lib().sde_surrogate_set_scaling(s[1], ctypes.byref(sc)))
+
+
+def sde_surrogate_get_scaling(s):
+    sc = sde_surrogate_scaling()
+    _check(s[0], lib().sde_surrogate_get_scaling(s[1], ctypes.byref(sc)))
+    return sc
+
+
+def make_train_opts(epochs, batch, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, shuffle_seed=0):
+    return sde_train_opts(epochs, batch, lr, beta1, beta2, eps, shuffle_seed)
+
+
+def sde_surrogate_train(s, X, y, opts, stream=None, loss_curve=True):
+    """Returns the per-epoch loss curve (numpy) or None."""
+    n = X.shape[0]
+    curve = np.zeros(opts.epochs, dtype=np.float32) if loss_curve else None
+    _check(s[0], lib().sde_surrogate_train(s[1], _ptr(X), _ptr(y), n, ctypes.byref(opts),
+                                           _fptr(curve) if curve is not None else None,
+                                           _stream(stream)))
+    return curve
+
+
+def sde_surrogate_predict(s, X, mean, spread, stream=None):
+    return _check(s[0], lib().sde_surrogate_predict(s[1], _ptr(X), X.shape[0], _ptr(mean),
+                                                    _ptr(spread), _stream(stream)))
+
+
+def sde_surrogate_loss_grad(s, member, X, y, stream=None):
+    """(loss, packed gradient as float32 numpy)."""
+    g = np.empty(sde_surrogate_param_count(s), dtype=np.float32)
+    loss = ctypes.c_double()
+    _check(s[0], lib().sde_surrogate_loss_grad(s[1], member, _ptr(X), _ptr(y), X.shape[0], _fptr(g),
+                                               ctypes.byref(loss), _stream(stream)))
+    return loss.value, g
+
+
+def sde_surrogate_scan(s, queries, spread_max, fallback_run, v_out, used_fallback=None, stream=None):
+    """queries: list of dicts or ctypes array; returns the scan statistics dict."""
+    if not isinstance(queries, ctypes.Array):
+        queries = make_points(queries)
+    st = sde_scan_stats()
+    _check(s[0], lib().sde_surrogate_scan(s[1], queries, len(queries), spread_max,
+                                          ctypes.byref(fallback_run), _ptr(v_out), _ptr(used_fallback),
+                                          ctypes.byref(st), _stream(stream)))
+    return {k: getattr(st, k) for k, _ in sde_scan_stats._fields_}
+
+
+def sde_surrogate_save(s, path):
+    return _check(s[0], lib().sde_surrogate_save(s[1], str(path).encode()))
+
+
+def sde_surrogate_load(ctx, path):
+    h = ctypes.c_void_p()
+    _check(ctx, lib().sde_surrogate_load(ctx, str(path).encode(), ctypes.byref(h)))
+    return (ctx, h.value)

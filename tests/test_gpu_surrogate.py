@@ -1,0 +1,242 @@
+"""GPU checks of the learned <v> surrogate through the C ABI: the network's
+hand-written forward/backward/Adam kernels against the FP64 oracle MLP, the
+fused ensemble inference, and the scan's fallback to the integrator.
+
+Tolerances: gradients and predictions are FP32 against FP64, compared as
+relative error of the whole vector (Euclidean norm) <= 1e-4; one Adam step
+(which moves each parameter by about lr * sign(g)) agrees to 1e-3 of lr
+except where the FP32 and FP64 gradients straddle zero.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import oracle.mlp as om
+import sde_inputs
+
+pytestmark = pytest.mark.gpu
+
+WIDTHS = [5, 256, 256, 256, 1]
+
+
+def _np_params(seed, widths=WIDTHS):
+    rng = np.random.default_rng(seed)
+    ps = []
+    for (o, i), _ in om.param_shapes(widths):
+        bound = 1.0 / np.sqrt(i)
+        ps.append((rng.uniform(-bound, bound, (o, i)), rng.uniform(-bound, bound, o)))
+    return ps
+
+
+def _f32(ps):
+    return [(W.astype(np.float32).astype(np.float64), b.astype(np.float32).astype(np.float64)) for W, b in ps]
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b)
+
+
+@pytest.fixture()
+def surrogate(gpu):
+    sde, ctx, dev = gpu
+    s = sde.sde_surrogate_create(ctx, WIDTHS, 5, 1234)
+    yield sde, s, dev
+    sde.sde_surrogate_destroy(s)
+
+
+def test_parameter_count_and_init_stream(surrogate):
+    """U(+-1/sqrt(fan_in)) from Philox(ctr = (k >> 2, member, 0, 5)), word k & 3."""
+    sde, s, dev = surrogate
+    P = sde.sde_surrogate_param_count(s)
+    assert P == om.n_params(WIDTHS) == 133377
+    for member in (0, 3):
+        got = sde.sde_surrogate_get_params(s, member)
+        idx = np.concatenate([np.arange(0, 40), np.arange(1275, 1300), np.arange(P - 260, P)])
+        bounds = np.concatenate([np.full(w * i + w, 1 / np.sqrt(i)) for (w, i), _ in om.param_shapes(WIDTHS)])
+        for k in idx:
+            w = oracle.philox(1234, [k >> 2, member, 0, 5])[k & 3]
+            u = (w >> 8) / 2**24
+            assert got[k] == np.float32(np.float32(bounds[k]) * (2 * np.float32(u) - 1)), k
+
+
+def test_loss_and_gradient_match_oracle(surrogate):
+    sde, s, dev = surrogate
+    ps = _f32(_np_params(1))
+    sde.sde_surrogate_set_params(s, 2, om.pack(ps))
+    rng = np.random.default_rng(2)
+    X = rng.uniform(-1, 1, (300, 5)).astype(np.float32)
+    y = rng.standard_normal(300).astype(np.float32)
+    loss, g = sde.sde_surrogate_loss_grad(s, 2, torch.from_numpy(X).to(dev), torch.from_numpy(y).to(dev))
+    ref_loss, ref_g = om.loss_and_grad(ps, X.astype(np.float64), y.astype(np.float64))
+    ref = om.pack(ref_g)
+    print(f"loss {loss:.8f} vs {ref_loss:.8f}; gradient relative error {_rel(g, ref):.2e}")
+    assert abs(loss - ref_loss) <= 1e-5 * abs(ref_loss)
+    assert _rel(g, ref) <= 1e-4
+    # per layer, so a wrong block cannot hide in the norm
+    off = 0
+    for (o, i), _ in om.param_shapes(WIDTHS):
+        for size in (o * i, o):
+            assert _rel(g[off:off + size], ref[off:off + size]) <= 1e-4
+            off += size
+
+
+def test_one_adam_step_matches_oracle(surrogate):
+    sde, s, dev = surrogate
+    widths = WIDTHS
+    ps = _f32(_np_params(3))
+    for m in range(5):
+        sde.sde_surrogate_set_params(s, m, om.pack(ps))
+    rng = np.random.default_rng(4)
+    X = rng.uniform(-1, 1, (512, 5)).astype(np.float32)
+    y = rng.standard_normal(512).astype(np.float32)
+    opts = sde.make_train_opts(1, 512, lr=1e-3)
+    sde.sde_surrogate_train(s, torch.from_numpy(X).to(dev), torch.from_numpy(y).to(dev), opts)
+    _, grads = om.loss_and_grad(ps, X.astype(np.float64), y.astype(np.float64))
+    new = om.adam_step(ps, grads, om.zeros_like(ps), om.zeros_like(ps), 1, lr=1e-3)
+    ref_step = om.pack(new) - om.pack(ps)
+    g = om.pack(grads)
+    for m in range(5):
+        got_step = sde.sde_surrogate_get_params(s, m).astype(np.float64) - om.pack(ps)
+        assert np.all(np.abs(got_step) <= 1e-3 * (1 + 1e-5) + 1e-7)
+        clear = np.abs(g) > 1e-6   # away from a sign change of the gradient
+        assert clear.mean() > 0.8
+        assert np.max(np.abs(got_step - ref_step)[clear]) <= 1e-6
+
+
+def test_ensemble_prediction_matches_oracle(surrogate):
+    sde, s, dev = surrogate
+    members = [_f32(_np_params(10 + m)) for m in range(5)]
+    for m, ps in enumerate(members):
+        sde.sde_surrogate_set_params(s, m, om.pack(ps))
+    center, scale = [4.0, 5.0, 0.25, -2.5, 1.0], [2.0, 2.0, 0.25, 1.5, 0.5]
+    sde.sde_surrogate_set_scaling(s, sde.make_scaling(center, scale, 0.3, 1.7, 1))
+    P = sde_inputs.jj_random_params(1000, 5).astype(np.float32)
+    P[:, 3] = np.log10(P[:, 3])
+    Xt = torch.from_numpy(P).to(dev)
+    mean = torch.empty(1000, dtype=torch.float32, device=dev)
+    spread = torch.empty(1000, dtype=torch.float32, device=dev)
+    sde.sde_surrogate_predict(s, Xt, mean, spread)
+    torch.cuda.synchronize()
+    Xn = (P.astype(np.float64) - center) / scale
+    outs = np.stack([(0.3 + 1.7 * om.forward(ps, Xn)[0]) * P[:, 1] for ps in members])
+    assert _rel(mean.cpu().numpy(), outs.mean(axis=0)) <= 1e-4
+    assert _rel(spread.cpu().numpy(), outs.std(axis=0, ddof=1)) <= 1e-4
+
+
+def test_training_reduces_loss(surrogate):
+    """A smooth target of the five features is learned by every member."""
+    sde, s, dev = surrogate
+    rng = np.random.default_rng(6)
+    X = rng.uniform(-1, 1, (16384, 5)).astype(np.float32)
+    y = (np.sin(2 * X[:, 0]) + X[:, 1] * X[:, 2] - 0.5 * X[:, 3] ** 2 + 0.1 * X[:, 4]).astype(np.float32)
+    curve = sde.sde_surrogate_train(s, torch.from_numpy(X).to(dev), torch.from_numpy(y).to(dev),
+                                    sde.make_train_opts(30, 256, lr=1e-3, shuffle_seed=3))
+    print("loss curve:", curve[[0, 9, 19, 29]])
+    assert curve[-1] < 0.02 * curve[0]
+    Xt = torch.from_numpy(X[:2000]).to(dev)
+    mean = torch.empty(2000, dtype=torch.float32, device=dev)
+    spread = torch.empty(2000, dtype=torch.float32, device=dev)
+    sde.sde_surrogate_predict(s, Xt, mean, spread)
+    err = np.abs(mean.cpu().numpy() - y[:2000])
+    print(f"fit MAE {err.mean():.4f}, mean spread {spread.cpu().numpy().mean():.4f}")
+    assert err.mean() < 0.05
+
+
+def test_save_load_roundtrip(surrogate, tmp_path):
+    sde, s, dev = surrogate
+    sde.sde_surrogate_set_scaling(s, sde.make_scaling([1, 2, 3, 4, 5], [2, 2, 2, 2, 2], 0.5, 2.0, 0))
+    path = tmp_path / "sur.bin"
+    sde.sde_surrogate_save(s, path)
+    t = sde.sde_surrogate_load(s[0], path)
+    try:
+        for m in range(5):
+            assert np.array_equal(sde.sde_surrogate_get_params(s, m), sde.sde_surrogate_get_params(t, m))
+        assert sde.sde_surrogate_get_scaling(t).out_std == 2.0
+    finally:
+        sde.sde_surrogate_destroy(t)
+
+
+def test_scan_falls_back_where_members_disagree(surrogate):
+    """Untrained members disagree strongly: with a threshold between the
+    smallest and largest spreads, exactly the points above it are simulated,
+    and their <v> equals a direct integration of those points."""
+    sde, s, dev = surrogate
+    ctx = s[0]
+    pts = sde_inputs.jj_batch(n_points=300, seed=9, path_range=(64, 200), step_range=(400, 1200))
+    P = np.array([[p["a"], p["omega"], p["f"], np.log10(p["D"]), p["gamma"]] for p in pts], dtype=np.float32)
+    mean = torch.empty(len(pts), dtype=torch.float32, device=dev)
+    spread = torch.empty(len(pts), dtype=torch.float32, device=dev)
+    sde.sde_surrogate_predict(s, torch.from_numpy(P).to(dev), mean, spread)
+    sp = spread.cpu().numpy()
+    thr = float(np.quantile(sp, 0.8))
+    v = torch.empty(len(pts), dtype=torch.float64, device=dev)
+    used = torch.empty(len(pts), dtype=torch.uint8, device=dev)
+    run = sde.make_run(77)
+    st = sde.sde_surrogate_scan(s, pts, thr, run, v, used)
+    used_np = used.cpu().numpy().astype(bool)
+    assert np.array_equal(used_np, sp > np.float32(thr))
+    assert st["n_fallback"] == used_np.sum() > 0
+    vg = v.cpu().numpy()
+    np.testing.assert_array_equal(vg[~used_np], mean.cpu().numpy()[~used_np].astype(np.float64))
+    sub = [pts[i] for i in np.nonzero(used_np)[0]]
+    ps = torch.empty((len(sub), 2), dtype=torch.float64, device=dev)
+    sde.sde_jj_integrate(ctx, sub, sde.make_run(77, sync=1), point_sums=ps)
+    direct = ps.cpu().numpy()[:, 0] / np.array([p["n_paths"] for p in sub])
+    np.testing.assert_allclose(vg[used_np], direct, rtol=0, atol=0)
+
+
+def test_surrogate_gain_over_plain_simulation(gpu):
+    """What the trained network buys: on the batch parameter distribution a
+    surrogate trained on 8192 simulated points answers 2e5 queries (with
+    fallback to simulation above a spread of 0.02) far faster than simulating
+    every query with the label budget, within 1e-2 of held-out simulations."""
+    import time
+    sde, ctx, dev = gpu
+    seed = 4242
+    P = sde_inputs.jj_random_params(8192, seed)
+
+    def pts(P, paths):
+        return sde.make_points_np(m=1.0, gamma=P[:, 4], a=P[:, 0], omega=P[:, 1], f=P[:, 2], D=P[:, 3],
+                                  n_paths=paths, steps_per_period=200, n_steps=20000, n_transient=10000)
+
+    def simulate(P, paths, s):
+        ps = torch.empty((len(P), 2), dtype=torch.float64, device=dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sde.sde_jj_integrate(ctx, pts(P, paths), sde.make_run(s, sync=1), point_sums=ps)
+        return ps.cpu().numpy()[:, 0] / paths, time.perf_counter() - t0
+
+    y, _ = simulate(P, 256, seed + 1)
+    Pho = sde_inputs.jj_random_params(512, seed + 2)
+    yho, _ = simulate(Pho, 2048, seed + 3)
+
+    def feats(P):
+        X = P.copy()
+        X[:, 3] = np.log10(X[:, 3])
+        return torch.from_numpy(X.astype(np.float32)).to(dev)
+
+    s = sde.sde_surrogate_create(ctx, WIDTHS, 5, seed + 4)
+    try:
+        sde.sde_surrogate_set_scaling(s, sde.make_scaling([4, 5, 0.25, -2.5, 1], [2, 2, 0.25, 1.5, 0.5],
+                                                          float(y.mean()), float(y.std()), 0))
+        curve = sde.sde_surrogate_train(s, feats(P), torch.from_numpy(y.astype(np.float32)).to(dev),
+                                        sde.make_train_opts(10, 512, shuffle_seed=seed + 5))
+        assert curve[-1] < curve[0]
+        vho = torch.empty(512, dtype=torch.float64, device=dev)
+        sde.sde_surrogate_scan(s, pts(Pho, 256), 0.02, sde.make_run(seed + 6), vho)
+        mae = np.abs(vho.cpu().numpy() - yho).mean()
+        Pq = sde_inputs.jj_random_params(200000, seed + 7)
+        vq = torch.empty(200000, dtype=torch.float64, device=dev)
+        uq = torch.empty(200000, dtype=torch.uint8, device=dev)
+        t0 = time.perf_counter()
+        st = sde.sde_surrogate_scan(s, pts(Pq, 256), 0.02, sde.make_run(seed + 8), vq, uq)
+        t_scan = time.perf_counter() - t0
+        _, t_sub = simulate(Pq[:4000], 256, seed + 8)
+        speedup = t_sub * 50 / t_scan
+        print(f"held-out MAE {mae:.2e} (labels std {yho.std():.2e}), fallback {st['n_fallback']} of 200000, "
+              f"scan {t_scan * 1e3:.1f} ms vs plain {t_sub * 50:.2f} s: speedup {speedup:.0f}x")
+        assert mae <= 1e-2
+        assert speedup >= 10
+    finally:
+        sde.sde_surrogate_destroy(s)
