@@ -378,6 +378,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--model-steps", type=int, default=200000,
                     help="Heun steps per path (the workload uses 2e5; smaller only for profiling)")
+    ap.add_argument("--kura-steps", type=int, default=None,
+                    help="steps of a kuramoto_* workload (default: its own; fewer only for profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -407,7 +409,7 @@ def main():
     elif args.workload == "jj_surrogate":
         out = bench_surrogate(args, sde, torch, dev)
     else:
-        out = bench_kuramoto(args.workload, args, sde, torch, dev, reps=args.steps)
+        out = bench_kuramoto(args.workload, args, sde, torch, dev, steps=args.kura_steps, reps=args.steps)
     if args.calibrate_copy:
         x = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         y = torch.empty_like(x)

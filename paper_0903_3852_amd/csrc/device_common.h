@@ -86,6 +86,19 @@ __device__ __forceinline__ void gauss4_scaled(U4 c, uint32_t k0, uint32_t k1, fl
     box_muller_scaled(x.z, x.w, c2, g[2], g[3]);
 }
 
+// sigma * Gaussian j (0..3) of block c alone, by the same operations that
+// gauss4_scaled applies for that output (pair j / 2, cosine for even j).
+// j should be wave-uniform.
+__device__ __forceinline__ float gauss1_scaled(U4 c, uint32_t k0, uint32_t k1, float c2, uint32_t j)
+{
+    const U4 x = philox4x32_10(c, k0, k1);
+    const uint32_t w1 = j < 2 ? x.x : x.z, w2 = j < 2 ? x.y : x.w;
+    const float u1 = (float)((w1 >> 8) + 1u) * 0x1p-24f;
+    const float u2 = (float)(w2 >> 8) * 0x1p-24f;
+    const float rho = __builtin_amdgcn_sqrtf(c2 * __builtin_amdgcn_logf(u1));
+    return rho * ((j & 1u) ? __builtin_amdgcn_sinf(u2) : __builtin_amdgcn_cosf(u2));
+}
+
 // Load of wave-uniform read-only data through the constant address space,
 // so that it becomes a scalar (SMEM) load into SGPRs.
 template <typename T>

@@ -284,9 +284,7 @@ __global__ __launch_bounds__(kTileThreads) void kuramoto_tiled_kernel(TiledArgs 
         if (idx[k] >= N) continue;
         const uint64_t gi = (uint64_t)r * N + idx[k];
         const float F = fmaf(A.kn, acc[k], A.omega[idx[k]]);
-        float g[4];
-        gauss4_scaled(U4{(uint32_t)(n >> 2), idx[k], r, (uint32_t)SDE_TAG_NOISE}, A.key0, A.key1, A.c2, g);
-        const float ns = j == 0 ? g[0] : j == 1 ? g[1] : j == 2 ? g[2] : g[3];
+        const float ns = gauss1_scaled(U4{(uint32_t)(n >> 2), idx[k], r, (uint32_t)SDE_TAG_NOISE}, A.key0, A.key1, A.c2, j);
         const float th = A.base[gi];
         if (A.stage == 1) {
             const float t = fmaf(A.omega_scale, F, th) + ns;

@@ -19,13 +19,18 @@
 //    exact power of two so its largest entry lies in [1, 2): the fp16 lo
 //    parts then stay normal, and the scaling is undone exactly afterwards.
 //
-// Layouts (all in the context's workspace):
-//   Khi, Klo : [Mp][Np] row-major 16-bit (rows padded to 128, columns to 32)
-//   K32      : [Mp][Np] row-major FP32 (FP32 variant)
-//   B        : [2 Rp][Np] column-major (a column is contiguous over j):
-//              column (r / 32) * 64 + (r % 32) holds sin(2 pi theta_rj),
-//              32 columns later cos; Rp = R rounded up to 32.  Two buffers
-//              alternate between the stages.
+// Layouts (all in the context's workspace).  Rows of K are padded to Mp (a
+// multiple of 128), the k extent to Np (N rounded up to 32), realizations to
+// Rp (a multiple of 32); the sin/cos operand B has 2 Rp columns, column
+// (r / 32) * 64 + (r % 32) holding sin(2 pi theta_rj) and the column 32
+// later cos.  Two B buffers alternate between the stages.
+//   16-bit variants: K (hi and lo) and B in the fragment-packed layout of
+//                    frag_off, so every MFMA operand is one contiguous 1 KB
+//                    load (a row-major tile puts the 16 rows of a fragment
+//                    8 KB apart, and the L1 then serves the load one lane at
+//                    a time);
+//   FP32 variant:    K [Mp][ld] row-major, B [2 Rp][ld] column-major, ld = Np
+//                    padded to an odd multiple of 128 bytes (dense_pitch).
 // A workgroup owns 128 rows x 32 realizations (64 columns), so every lane
 // holds S and C of the same (i, r) in its accumulators.  Workgroups are
 // dealt to XCDs so that each XCD sweeps a contiguous band of rows over all
@@ -52,19 +57,17 @@ constexpr uint32_t kRealTile = 32;
 constexpr uint32_t kKStep = 32;
 
 struct DenseArgs {
-    const void* Ahi;       // [Mp][Np] 16-bit split of the scaled K, or FP32 K (A32)
-    const void* Alo;
-    const void* Bhi;       // [2Rp][Np] current sin/cos operand (16-bit split or FP32)
-    const void* Blo;
-    void* Bhi_next;        // operand for the next product
-    void* Blo_next;
+    const void* K;         // scaled K: packed 16-bit hi/lo, or FP32 [Mp][ld]
+    const void* B;         // current sin/cos operand (same layout family)
+    void* Bnext;           // operand for the next product
     const float* src;      // [R][N] phases the drift is evaluated at
     const float* base;     // [R][N] phases at the start of the step
     float* dst;            // [R][N] output phases
-    float* F1;             // [R][N] stage-1 drift
+    float* F1;             // [R][N] the predictor's carry for the corrector (dense_stage)
     const float* omega;    // [N]
     const float* scale;    // device: {scale, 1/scale}
-    uint32_t N, R, Np, Rp, Mp;
+    uint32_t N, R, Np, Rp, Mp;  // Np: k extent of the product (N rounded up to 32)
+    uint32_t ld;           // FP32 variant: row pitch (elements) of K and of the operand columns
     const uint64_t* nbase; // device: absolute step of the current chunk's first step
     uint32_t k;            // step within the chunk
     uint32_t key0, key1;
@@ -78,48 +81,77 @@ __device__ __forceinline__ uint32_t bcol(uint32_t r, uint32_t kind)
     return (r / kRealTile) * (2 * kRealTile) + kind * kRealTile + (r % kRealTile);
 }
 
+// Fragment-packed 16-bit layout of a matrix with 32-aligned k extent Np
+// (KB = Np / 32 blocks of k): the operand of one 16x16x32 MFMA -- 16 rows (A)
+// or columns (B) by 32 k -- is one contiguous 1 KB block laid out as the 64
+// lanes hold it (lane = row % 16 + 16 * (k % 32 / 8), 8 consecutive k per
+// lane), its lo part in the next 1 KB, and consecutive k blocks of the same
+// 16 rows follow each other.  A wave's fragment load is then one fully used,
+// contiguous 1 KB request, and a row tile's k sweep is a sequential stream.
+__device__ __forceinline__ uint64_t frag_off(uint32_t row, uint32_t k, uint32_t KB)
+{
+    return ((((uint64_t)(row >> 4) * KB + (k >> 5)) * 2) * 64 + ((row & 15u) + 16u * ((k >> 3) & 3u))) * 8 + (k & 7u);
+}
+constexpr uint32_t kFragLo = 512;  // elements from a hi fragment to its lo part
+
+// x -> hi = round16(x) at p[idx], lo = round16(x - hi) at p[idx + kFragLo].
 template <typename T>
-__device__ __forceinline__ void store_split(void* hi, void* lo, uint64_t idx, float x)
+__device__ __forceinline__ void store_split(T* p, uint64_t idx, float x)
 {
     const T h = (T)x;
-    static_cast<T*>(hi)[idx] = h;
-    static_cast<T*>(lo)[idx] = (T)(x - (float)h);
+    p[idx] = h;
+    p[idx + kFragLo] = (T)(x - (float)h);
 }
 
-// The stage update of oscillator i of realization r given S = sum_j K_ij
-// sin phi_j and C = sum_j K_ij cos phi_j; also writes the next operand.
-template <typename T>
-__device__ __forceinline__ void dense_update(const DenseArgs& A, uint32_t i, uint32_t r, float S, float C)
+// The stage update of oscillator i of realization r at absolute step n,
+// given S = sum_j K_ij sin phi_j, C = sum_j K_ij cos phi_j, the phase ts the
+// drift F is evaluated at, the phase th at the start of the step and omega_i.
+// Both Heun stages of a step add the same noise (Alg. 2), so the predictor
+// leaves the corrector everything it needs from stage 1 in one number,
+// carry = (dt / 2) F_1 / 2 pi + noise, and the corrector draws no noise:
+//   predictor  t = th + dt F_1 / 2 pi + noise           (Euler: the step)
+//   corrector  t = th + (dt / 2) F_2 / 2 pi + carry
+// Returns the new phase; `carry` is written by the predictor, read by the
+// corrector.
+__device__ __forceinline__ float dense_stage(const DenseArgs& A, uint64_t n, uint32_t i, uint32_t r, float S, float C,
+                                             float ts, float th, float om, float& carry)
 {
-    const uint64_t gi = (uint64_t)r * A.N + i;
-    const float ts = A.src[gi];
-    const float F = fmaf(cos_rev(ts), S, fmaf(-sin_rev(ts), C, A.omega[i]));
-    const uint64_t n = load_uniform(A.nbase) + A.k;
-    float g[4];
-    gauss4_scaled(U4{(uint32_t)(n >> 2), i, r, (uint32_t)SDE_TAG_NOISE}, A.key0, A.key1, A.c2, g);
-    const uint32_t j = (uint32_t)n & 3u;
-    const float ns = j == 0 ? g[0] : j == 1 ? g[1] : j == 2 ? g[2] : g[3];
-    const float th = A.base[gi];
+    const float F = fmaf(cos_rev(ts), S, fmaf(-sin_rev(ts), C, om));
     float t;
     if (A.stage == 1) {
+        const float ns = gauss1_scaled(U4{(uint32_t)(n >> 2), i, r, (uint32_t)SDE_TAG_NOISE}, A.key0, A.key1, A.c2,
+                                       (uint32_t)n & 3u);
         t = fmaf(A.omega_scale, F, th) + ns;
         if (A.euler)
             t -= floorf(t);
         else
-            A.F1[gi] = F;
+            carry = fmaf(A.hdt2pi, F, ns);
     } else {
-        t = fmaf(A.hdt2pi, A.F1[gi] + F, th) + ns;
+        t = fmaf(A.hdt2pi, F, th) + carry;
         t -= floorf(t);
     }
+    return t;
+}
+
+// dense_stage with its loads and stores for one oscillator.
+__device__ __forceinline__ float dense_phase(const DenseArgs& A, uint32_t i, uint32_t r, float S, float C)
+{
+    const uint64_t gi = (uint64_t)r * A.N + i;
+    const uint64_t n = load_uniform(A.nbase) + A.k;
+    float carry = A.stage == 1 ? 0.f : A.F1[gi];
+    const float t = dense_stage(A, n, i, r, S, C, A.src[gi], A.base[gi], A.omega[i], carry);
+    if (A.stage == 1 && !A.euler) A.F1[gi] = carry;
     A.dst[gi] = t;
-    const uint64_t cs = (uint64_t)bcol(r, 0) * A.Np + i, cc = (uint64_t)bcol(r, 1) * A.Np + i;
-    if constexpr (sizeof(T) == 4) {
-        static_cast<float*>(A.Bhi_next)[cs] = sin_rev(t);
-        static_cast<float*>(A.Bhi_next)[cc] = cos_rev(t);
-    } else {
-        store_split<T>(A.Bhi_next, A.Blo_next, cs, sin_rev(t));
-        store_split<T>(A.Bhi_next, A.Blo_next, cc, cos_rev(t));
-    }
+    return t;
+}
+
+// FP32 variant: dense_phase, then the oscillator's entries of the next operand.
+__device__ __forceinline__ void dense_update_f32(const DenseArgs& A, uint32_t i, uint32_t r, float S, float C)
+{
+    const float t = dense_phase(A, i, r, S, C);
+    float* B = static_cast<float*>(A.Bnext);
+    B[(uint64_t)bcol(r, 0) * A.ld + i] = sin_rev(t);
+    B[(uint64_t)bcol(r, 1) * A.ld + i] = cos_rev(t);
 }
 
 // workgroup -> (row tile, realization tile); XCD-aware when the row tiles
@@ -146,84 +178,195 @@ __device__ __forceinline__ f32x4 mfma16(V a, V b, f32x4 c)
         return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
 }
 
+// Stage update of a 128-row x 32-realization tile whose S and C sit in LDS
+// as tS[realization][row], tC[realization][row] (already unscaled).
+//  1. Lane t takes the oscillators t, t + 256, ... of the tile in row-fastest
+//     order, so a wave's phase loads and stores cover 64 consecutive
+//     oscillators of one realization (256 contiguous bytes; with 8 rows per
+//     lane the lanes sit 32 bytes apart and the L1 serves them one by one).
+//     All of a lane's loads come before its first store: dst may be src (the
+//     in-place Euler step), so the compiler could not move a load above a
+//     store.  sin and cos of the new phase replace S and C in the tile.
+//  2. The tile goes out as the next operand in 16-byte rows: a wave writes one
+//     whole 1 KB packed fragment (hi) and its lo part per pass.
 template <typename T, typename V>
-__global__ __launch_bounds__(kDenseThreads) void dense_mfma_kernel(DenseArgs A)
+__device__ __forceinline__ void dense_tile_update(const DenseArgs& A, uint32_t mt, uint32_t nt,
+                                                  float (*tS)[kRowTile + 1], float (*tC)[kRowTile + 1])
 {
+    constexpr uint32_t kPer = kRowTile * kRealTile / kDenseThreads;  // oscillators per lane
+    static_assert(kRowTile % kWave == 0 && kDenseThreads % kRowTile == 0, "a wave stays in one realization");
+    const uint32_t KB = A.Np / kKStep;
+    const uint64_t n = load_uniform(A.nbase) + A.k;
+    const bool corrector = A.stage != 1;
+    float ts[kPer], th[kPer], cy[kPer], om[kPer];
+#pragma unroll
+    for (uint32_t e = 0; e < kPer; ++e) {
+        const uint32_t idx = threadIdx.x + e * kDenseThreads;
+        const uint32_t r = nt * kRealTile + idx / kRowTile, i = mt * kRowTile + idx % kRowTile;
+        const bool ok = r < A.R && i < A.N;
+        const uint64_t gi = ok ? (uint64_t)r * A.N + i : 0;
+        ts[e] = ok ? A.src[gi] : 0.f;
+        cy[e] = ok && corrector ? A.F1[gi] : 0.f;
+        om[e] = ok ? A.omega[i] : 0.f;
+    }
+    if (A.src == A.base) {  // stage 1: the drift is evaluated at the step's start
+#pragma unroll
+        for (uint32_t e = 0; e < kPer; ++e) th[e] = ts[e];
+    } else {
+#pragma unroll
+        for (uint32_t e = 0; e < kPer; ++e) {
+            const uint32_t idx = threadIdx.x + e * kDenseThreads;
+            const uint32_t r = nt * kRealTile + idx / kRowTile, i = mt * kRowTile + idx % kRowTile;
+            th[e] = r < A.R && i < A.N ? A.base[(uint64_t)r * A.N + i] : 0.f;
+        }
+    }
+#pragma unroll
+    for (uint32_t e = 0; e < kPer; ++e) {
+        const uint32_t idx = threadIdx.x + e * kDenseThreads;
+        const uint32_t rl = idx / kRowTile, il = idx % kRowTile;
+        const uint32_t r = nt * kRealTile + rl, i = mt * kRowTile + il;
+        float sv = 0.f, cv = 0.f;  // rows k >= N of the operand stay zero
+        if (r < A.R && i < A.N) {
+            const uint64_t gi = (uint64_t)r * A.N + i;
+            const float t = dense_stage(A, n, i, r, tS[rl][il], tC[rl][il], ts[e], th[e], om[e], cy[e]);
+            if (!corrector && !A.euler) A.F1[gi] = cy[e];
+            A.dst[gi] = t;
+            sv = sin_rev(t);
+            cv = cos_rev(t);
+        }
+        tS[rl][il] = sv;
+        tC[rl][il] = cv;
+    }
+    __syncthreads();
+    // pass j: lane -> (column c % 16, 8-row group within the 32-row block) of
+    // fragment (column block, k block) = ((u >> 6) & 3, u >> 8)
+    T* B = static_cast<T*>(A.Bnext);
+#pragma unroll
+    for (uint32_t j = 0; j < 2 * kRealTile * kRowTile / 8 / kDenseThreads; ++j) {
+        const uint32_t u = threadIdx.x + j * kDenseThreads;
+        const uint32_t cb = (u >> 6) & 3u, kind = cb >> 1;
+        const uint32_t rl = (cb & 1u) * 16 + (u & 15u), il0 = (u >> 8) * kKStep + ((u >> 4) & 3u) * 8;
+        const uint32_t r = nt * kRealTile + rl, i0 = mt * kRowTile + il0;
+        if (r >= A.R || i0 >= A.N) continue;
+        const float* src = kind ? &tC[rl][il0] : &tS[rl][il0];
+        V hi, lo;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            hi[e] = (T)src[e];
+            lo[e] = (T)(src[e] - (float)hi[e]);
+        }
+        const uint64_t o = frag_off(bcol(r, kind), i0, KB);
+        *reinterpret_cast<V*>(B + o) = hi;
+        *reinterpret_cast<V*>(B + o + kFragLo) = lo;
+    }
+}
+
+// Split-precision product and stage update of one 128-row x 32-realization
+// tile.  The output (N x 2R = 4096 x 512 at the benchmark size) is too small
+// to give each SIMD a large tile of its own, so the k loop is split instead:
+// every wave of the workgroup computes the whole 128 x 64 tile over every
+// fourth 32-k block.  Per block a wave loads 16 K and 8 B fragments (24 KB,
+// prefetched one block ahead) for 96 MFMAs, and no fragment is loaded twice
+// within the CU: 64 B per clock per CU at the MFMA rate, half of what a 2 x 2
+// grid of 64 x 32 wave tiles needs (there the L1 bounds the loop).  The four
+// partial tiles are summed through LDS in a fixed order, then the stage
+// update runs on the sum.
+constexpr uint32_t kSplitK = 4;
+
+template <typename T, typename V>
+__global__ __launch_bounds__(kDenseThreads, 1) void dense_mfma_kernel(DenseArgs A)
+{
+    // partials of waves 1..3: [wave - 1][32 accumulator quads][64 lanes] x 4
+    // floats (96 KB), and the summed tile transposed to [realization][row]
+    __shared__ f32x4 red[kSplitK - 1][32][kWave];
+    __shared__ float tS[kRealTile][kRowTile + 1], tC[kRealTile][kRowTile + 1];
     uint32_t mt, nt;
     tile_of(blockIdx.x, A.Mp / kRowTile, A.Rp / kRealTile, mt, nt);
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
-    const uint32_t wr = wave >> 1, wc = wave & 1u;
-    const uint32_t row0 = mt * kRowTile + wr * 64;      // 4 sub-tiles of 16 rows
-    const uint32_t csin = nt * 2 * kRealTile + wc * 16 + (lane & 15u);
-    const uint32_t ccos = csin + kRealTile;
-    const uint32_t kofs = 8 * (lane >> 4);
-    const T* Ahi = static_cast<const T*>(A.Ahi);
-    const T* Alo = static_cast<const T*>(A.Alo);
-    const T* Bhi = static_cast<const T*>(A.Bhi);
-    const T* Blo = static_cast<const T*>(A.Blo);
-    const uint64_t Np = A.Np;
-    const T* pa_hi = Ahi + (uint64_t)(row0 + (lane & 15u)) * Np + kofs;
-    const T* pa_lo = Alo + (uint64_t)(row0 + (lane & 15u)) * Np + kofs;
-    const T* pbs_hi = Bhi + (uint64_t)csin * Np + kofs;
-    const T* pbs_lo = Blo + (uint64_t)csin * Np + kofs;
-    const T* pbc_hi = Bhi + (uint64_t)ccos * Np + kofs;
-    const T* pbc_lo = Blo + (uint64_t)ccos * Np + kofs;
+    const uint32_t KB = A.Np / kKStep;
+    const uint64_t frag = 2 * 64 * 8;              // elements per k block (hi + lo)
+    const uint64_t stream = (uint64_t)KB * frag;  // elements per 16-row block
+    const T* pa = static_cast<const T*>(A.K) + (uint64_t)(mt * 8) * stream + lane * 8;
+    const T* pb = static_cast<const T*>(A.B) + (uint64_t)(nt * 4) * stream + lane * 8;
 
-    f32x4 accS[4], accC[4];
+    f32x4 acc[8][4];  // [16-row block][column block: sin 0-15, sin 16-31, cos 0-15, cos 16-31]
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
-        accS[m] = f32x4{0.f, 0.f, 0.f, 0.f};
-        accC[m] = f32x4{0.f, 0.f, 0.f, 0.f};
-    }
-    V ah[4], al[4], bsh, bsl, bch, bcl;
-    auto load = [&](uint32_t k0) {
+    for (int m = 0; m < 8; ++m)
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            ah[m] = *reinterpret_cast<const V*>(pa_hi + (uint64_t)m * 16 * Np + k0);
-            al[m] = *reinterpret_cast<const V*>(pa_lo + (uint64_t)m * 16 * Np + k0);
+        for (int n = 0; n < 4; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    V ah[8], al[8], bh[4], bl[4];
+    auto load = [&](uint64_t o) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            ah[m] = *reinterpret_cast<const V*>(pa + m * stream + o);
+            al[m] = *reinterpret_cast<const V*>(pa + m * stream + o + kFragLo);
         }
-        bsh = *reinterpret_cast<const V*>(pbs_hi + k0);
-        bsl = *reinterpret_cast<const V*>(pbs_lo + k0);
-        bch = *reinterpret_cast<const V*>(pbc_hi + k0);
-        bcl = *reinterpret_cast<const V*>(pbc_lo + k0);
-    };
-    load(0);
-    for (uint32_t k0 = 0; k0 < A.Np; k0 += kKStep) {
-        V cah[4], cal[4];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
+        for (int n = 0; n < 4; ++n) {
+            bh[n] = *reinterpret_cast<const V*>(pb + n * stream + o);
+            bl[n] = *reinterpret_cast<const V*>(pb + n * stream + o + kFragLo);
+        }
+    };
+    uint32_t kb = wave;
+    if (kb < KB) load((uint64_t)kb * frag);
+    for (; kb < KB; kb += kSplitK) {
+        V cah[8], cal[8], cbh[4], cbl[4];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
             cah[m] = ah[m];
             cal[m] = al[m];
         }
-        const V cbsh = bsh, cbsl = bsl, cbch = bch, cbcl = bcl;
-        if (k0 + kKStep < A.Np) load(k0 + kKStep);  // prefetch the next k step
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            accS[m] = mfma16<T, V>(cah[m], cbsh, accS[m]);
-            accC[m] = mfma16<T, V>(cah[m], cbch, accC[m]);
+        for (int n = 0; n < 4; ++n) {
+            cbh[n] = bh[n];
+            cbl[n] = bl[n];
         }
+        if (kb + kSplitK < KB) load((uint64_t)(kb + kSplitK) * frag);  // prefetch this wave's next block
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            accS[m] = mfma16<T, V>(cah[m], cbsl, accS[m]);
-            accC[m] = mfma16<T, V>(cah[m], cbcl, accC[m]);
-        }
+        for (int m = 0; m < 8; ++m)
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            accS[m] = mfma16<T, V>(cal[m], cbsh, accS[m]);
-            accC[m] = mfma16<T, V>(cal[m], cbch, accC[m]);
-        }
+            for (int n = 0; n < 4; ++n) acc[m][n] = mfma16<T, V>(cah[m], cbh[n], acc[m][n]);
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = mfma16<T, V>(cah[m], cbl[n], acc[m][n]);
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = mfma16<T, V>(cal[m], cbh[n], acc[m][n]);
     }
+    // Partial tiles: waves 1..3 into red; wave 0 writes its own, unscaled by
+    // the exact power of two, straight into the transposed tile; then all
+    // lanes add ((p1 + p2) + p3) into it -- a fixed order.
     const float inv = A.scale[1];
-    const uint32_t r = nt * kRealTile + wc * 16 + (lane & 15u);
-    if (r >= A.R) return;
+    if (wave > 0) {
 #pragma unroll
-    for (int m = 0; m < 4; ++m) {
+        for (int m = 0; m < 8; ++m)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const uint32_t i = row0 + m * 16 + 4 * (lane >> 4) + q;
-            if (i < A.N) dense_update<T>(A, i, r, accS[m][q] * inv, accC[m][q] * inv);
-        }
+            for (int n = 0; n < 4; ++n) red[wave - 1][m * 4 + n][lane] = acc[m][n];
+    } else {
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                float(*t)[kRowTile + 1] = (n >> 1) ? tC : tS;
+                const uint32_t rl = (n & 1) * 16 + (lane & 15u);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) t[rl][m * 16 + 4 * (lane >> 4) + q] = acc[m][n][q] * inv;
+            }
     }
+    __syncthreads();
+    for (uint32_t p = threadIdx.x; p < 32 * kWave; p += kDenseThreads) {
+        const uint32_t quad = p / kWave, l = p % kWave;
+        const f32x4 sum = (red[0][quad][l] + red[1][quad][l]) + red[2][quad][l];
+        const uint32_t m = quad / 4, n = quad % 4;
+        float(*t)[kRowTile + 1] = (n >> 1) ? tC : tS;
+        const uint32_t rl = (n & 1) * 16 + (l & 15u);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) t[rl][m * 16 + 4 * (l >> 4) + q] += sum[q] * inv;
+    }
+    __syncthreads();
+    dense_tile_update<T, V>(A, mt, nt, tS, tC);
 }
 
 // ------------------------------------------------------------ FP32 SIMT ---
@@ -238,9 +381,9 @@ __global__ __launch_bounds__(kDenseThreads) void dense_fp32_kernel(DenseArgs A)
     uint32_t mt, nt;
     tile_of(blockIdx.x, A.Mp / kRowTile, A.Rp / kRealTile, mt, nt);
     const uint32_t tx = threadIdx.x & 15u, ty = threadIdx.x >> 4;  // 16 x 16
-    const float* K32 = static_cast<const float*>(A.Ahi);
-    const float* B32 = static_cast<const float*>(A.Bhi);
-    const uint64_t Np = A.Np;
+    const float* K32 = static_cast<const float*>(A.K);
+    const float* B32 = static_cast<const float*>(A.B);
+    const uint64_t ld = A.ld;
     float accS[8][2], accC[8][2];
 #pragma unroll
     for (int a = 0; a < 8; ++a)
@@ -250,9 +393,9 @@ __global__ __launch_bounds__(kDenseThreads) void dense_fp32_kernel(DenseArgs A)
     // B tile 64 cols x 16 = 256 float4 (1 per lane)
     const uint32_t arow = threadIdx.x >> 2, akq = (threadIdx.x & 3u) * 4;
     const uint32_t bcolv = threadIdx.x >> 2, bkq = (threadIdx.x & 3u) * 4;
-    const float* pa0 = K32 + (uint64_t)(mt * kRowTile + arow) * Np + akq;
-    const float* pa1 = pa0 + 64 * Np;
-    const float* pb = B32 + (uint64_t)(nt * 2 * kRealTile + bcolv) * Np + bkq;
+    const float* pa0 = K32 + (uint64_t)(mt * kRowTile + arow) * ld + akq;
+    const float* pa1 = pa0 + 64 * ld;
+    const float* pb = B32 + (uint64_t)(nt * 2 * kRealTile + bcolv) * ld + bkq;
     for (uint32_t k0 = 0; k0 < A.Np; k0 += kF32K) {
         const float4 a0 = *reinterpret_cast<const float4*>(pa0 + k0);
         const float4 a1 = *reinterpret_cast<const float4*>(pa1 + k0);
@@ -294,7 +437,7 @@ __global__ __launch_bounds__(kDenseThreads) void dense_fp32_kernel(DenseArgs A)
 #pragma unroll
         for (int q = 0; q < 8; ++q) {
             const uint32_t i = mt * kRowTile + ty * 8 + q;
-            if (i < A.N) dense_update<float>(A, i, r, accS[q][b], accC[q][b]);
+            if (i < A.N) dense_update_f32(A, i, r, accS[q][b], accC[q][b]);
         }
     }
 }
@@ -322,46 +465,56 @@ __global__ void dense_scale_kernel(const uint32_t* maxbits, float* scale, int un
     scale[1] = 1.f / s;
 }
 
-// K -> padded [Mp][Np] scaled copy: 16-bit hi/lo split, or FP32.
+// K -> scaled, padded copy over Mp rows x ld columns (zero outside N x N):
+// FP32 row-major with pitch ld, or the packed 16-bit hi/lo split (ld = Np).
 template <typename T>
-__global__ void dense_split_kernel(const float* K, uint32_t N, uint32_t Np, uint32_t Mp, const float* scale,
-                                   void* hi, void* lo)
+__global__ void dense_split_kernel(const float* K, uint32_t N, uint32_t ld, uint32_t Mp, const float* scale, void* out)
 {
     const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= (uint64_t)Mp * Np) return;
-    const uint32_t i = (uint32_t)(g / Np), j = (uint32_t)(g % Np);
+    if (g >= (uint64_t)Mp * ld) return;
+    const uint32_t i = (uint32_t)(g / ld), j = (uint32_t)(g % ld);
     const float x = (i < N && j < N) ? K[(uint64_t)i * N + j] * scale[0] : 0.f;
     if constexpr (sizeof(T) == 4)
-        static_cast<float*>(hi)[g] = x;
+        static_cast<float*>(out)[g] = x;
     else
-        store_split<T>(hi, lo, g, x);
+        store_split<T>(static_cast<T*>(out), frag_off(i, j, ld / kKStep), x);
 }
 
-// theta [R][N] -> sin/cos operand [2Rp][Np] (zero in the padding).
+// theta [R][N] -> sin/cos operand over 2 Rp columns x ld rows of k (zero in
+// the padding): FP32 columns of pitch ld, or packed 16-bit hi/lo (ld = Np).
 template <typename T>
-__global__ void dense_operand_kernel(const float* theta, uint32_t N, uint32_t R, uint32_t Np, uint32_t Rp, void* hi,
-                                     void* lo)
+__global__ void dense_operand_kernel(const float* theta, uint32_t N, uint32_t R, uint32_t ld, uint32_t Rp, void* out)
 {
     const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= (uint64_t)Rp * Np) return;
-    const uint32_t r = (uint32_t)(g / Np), j = (uint32_t)(g % Np);
+    if (g >= (uint64_t)Rp * ld) return;
+    const uint32_t r = (uint32_t)(g / ld), j = (uint32_t)(g % ld);
     float s = 0.f, c = 0.f;
     if (r < R && j < N) {
         const float t = theta[(uint64_t)r * N + j];
         s = sin_rev(t);
         c = cos_rev(t);
     }
-    const uint64_t cs = (uint64_t)bcol(r, 0) * Np + j, cc = (uint64_t)bcol(r, 1) * Np + j;
     if constexpr (sizeof(T) == 4) {
-        static_cast<float*>(hi)[cs] = s;
-        static_cast<float*>(hi)[cc] = c;
+        static_cast<float*>(out)[(uint64_t)bcol(r, 0) * ld + j] = s;
+        static_cast<float*>(out)[(uint64_t)bcol(r, 1) * ld + j] = c;
     } else {
-        store_split<T>(hi, lo, cs, s);
-        store_split<T>(hi, lo, cc, c);
+        T* B = static_cast<T*>(out);
+        store_split<T>(B, frag_off(bcol(r, 0), j, ld / kKStep), s);
+        store_split<T>(B, frag_off(bcol(r, 1), j, ld / kKStep), c);
     }
 }
 
 // ------------------------------------------------------------------ host --
+// FP32 row pitch: Np rounded up to an odd multiple of 128 bytes, so that the
+// same k slice of consecutive rows does not fall on one L2 channel (a
+// power-of-two pitch, e.g. 16 KB at N = 4096, maps them all to one).
+static uint32_t dense_pitch(uint32_t Np)
+{
+    constexpr uint32_t unit = 128 / sizeof(float);
+    uint32_t ld = (Np + unit - 1) / unit * unit;
+    if ((ld / unit) % 2 == 0) ld += unit;
+    return ld;
+}
 
 template <typename T>
 static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, float* phi,
@@ -374,24 +527,19 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
     const uint32_t Mp = (N + kRowTile - 1) / kRowTile * kRowTile;
     const uint32_t Rp = (R + kRealTile - 1) / kRealTile * kRealTile;
     const uint64_t NR = (uint64_t)N * R;
-    const size_t esz = sizeof(T);
-    const bool split = esz == 2;
-    const size_t a_bytes = (size_t)Mp * Np * esz;
-    const size_t b_bytes = (size_t)2 * Rp * Np * esz;
+    const bool split = sizeof(T) == 2;
+    const uint32_t ld = split ? Np : dense_pitch(Np);
+    // bytes of the K copy and of one operand buffer (hi and lo for the split)
+    const size_t a_bytes = (size_t)Mp * ld * sizeof(T) * (split ? 2 : 1);
+    const size_t b_bytes = (size_t)2 * Rp * ld * sizeof(T) * (split ? 2 : 1);
     void *wa = nullptr, *wb = nullptr, *wk = nullptr;
     int st;
-    if ((st = ensure_ws(ctx, kSlotDenseA, a_bytes * (split ? 2 : 1), &wa))) return st;
-    if ((st = ensure_ws(ctx, kSlotDenseB, b_bytes * (split ? 4 : 2) + 64, &wb))) return st;
+    if ((st = ensure_ws(ctx, kSlotDenseA, a_bytes, &wa))) return st;
+    if ((st = ensure_ws(ctx, kSlotDenseB, 2 * b_bytes + 64, &wb))) return st;
     if ((st = ensure_ws(ctx, kSlotKuraWork, (size_t)2 * NR * sizeof(float), &wk))) return st;
-    char* A0 = static_cast<char*>(wa);
     char* B0 = static_cast<char*>(wb);
-    void* Ahi = A0;
-    void* Alo = split ? A0 + a_bytes : nullptr;
-    void* Bcur_hi = B0;
-    void* Bcur_lo = split ? B0 + b_bytes : nullptr;
-    void* Bnext_hi = B0 + b_bytes * (split ? 2 : 1);
-    void* Bnext_lo = split ? B0 + b_bytes * 3 : nullptr;
-    float* scale = reinterpret_cast<float*>(B0 + b_bytes * (split ? 4 : 2));
+    void* Bbuf[2] = {B0, B0 + b_bytes};
+    float* scale = reinterpret_cast<float*>(B0 + 2 * b_bytes);
     uint32_t* maxbits = reinterpret_cast<uint32_t*>(scale + 2);
     float* tilde = static_cast<float*>(wk);
     float* F1 = tilde + NR;
@@ -400,23 +548,23 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
     hipLaunchKernelGGL(dense_zero_kernel, dim3(1), dim3(1), 0, stream, maxbits);
     if (split) hipLaunchKernelGGL(dense_maxabs_kernel, dim3(1024), dim3(256), 0, stream, K, (uint64_t)N * N, maxbits);
     hipLaunchKernelGGL(dense_scale_kernel, dim3(1), dim3(1), 0, stream, maxbits, scale, split ? 0 : 1);
-    hipLaunchKernelGGL(dense_split_kernel<T>, dim3((uint32_t)(((uint64_t)Mp * Np + 255) / 256)), dim3(256), 0, stream,
-                       K, N, Np, Mp, scale, Ahi, Alo);
+    hipLaunchKernelGGL(dense_split_kernel<T>, dim3((uint32_t)(((uint64_t)Mp * ld + 255) / 256)), dim3(256), 0, stream,
+                       K, N, ld, Mp, scale, wa);
     // both operand buffers get their zero padding (rows j >= N, columns of
     // realizations r >= R) here; the epilogues only ever write the live part
     for (int b = 0; b < 2; ++b)
-        hipLaunchKernelGGL(dense_operand_kernel<T>, dim3((uint32_t)(((uint64_t)Rp * Np + 255) / 256)), dim3(256), 0,
-                           stream, phi, N, R, Np, Rp, b ? Bnext_hi : Bcur_hi, b ? Bnext_lo : Bcur_lo);
+        hipLaunchKernelGGL(dense_operand_kernel<T>, dim3((uint32_t)(((uint64_t)Rp * ld + 255) / 256)), dim3(256), 0,
+                           stream, phi, N, R, ld, Rp, Bbuf[b]);
     SDE_HIP(ctx, hipGetLastError());
 
     DenseArgs A;
-    A.Ahi = Ahi;
-    A.Alo = Alo;
+    A.K = wa;
     A.omega = omega;
     A.scale = scale;
     A.N = N;
     A.R = R;
     A.Np = Np;
+    A.ld = ld;
     A.Rp = Rp;
     A.Mp = Mp;
     A.key0 = (uint32_t)run->seed;
@@ -443,8 +591,6 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
     // `count` steps from the device step base, then advance it.  The operand
     // buffers alternate per stage; chunks hold an even number of stages so a
     // recorded chunk always starts from the same buffer.
-    void* Bb_hi[2] = {Bcur_hi, Bnext_hi};
-    void* Bb_lo[2] = {Bcur_lo, Bnext_lo};
     auto record = [&](hipStream_t s, uint32_t count) -> int {
         if (r_samples) launch_order_parameter_at(phi, N, R, r_samples, n_samples, nbase, run->step0, M, s);
         int cur = 0;
@@ -452,10 +598,8 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
             A.k = k;
             // stage 1: drift at theta_n; Euler finishes the step in place
             A.stage = 1;
-            A.Bhi = Bb_hi[cur];
-            A.Blo = Bb_lo[cur];
-            A.Bhi_next = Bb_hi[cur ^ 1];
-            A.Blo_next = Bb_lo[cur ^ 1];
+            A.B = Bbuf[cur];
+            A.Bnext = Bbuf[cur ^ 1];
             A.src = phi;
             A.base = phi;
             A.dst = A.euler ? phi : tilde;
@@ -465,10 +609,8 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
             if (A.euler) continue;
             // stage 2: drift at the predictor; corrector into phi
             A.stage = 2;
-            A.Bhi = Bb_hi[cur];
-            A.Blo = Bb_lo[cur];
-            A.Bhi_next = Bb_hi[cur ^ 1];
-            A.Blo_next = Bb_lo[cur ^ 1];
+            A.B = Bbuf[cur];
+            A.Bnext = Bbuf[cur ^ 1];
             A.src = tilde;
             A.base = phi;
             A.dst = phi;
