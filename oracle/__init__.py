@@ -41,7 +41,8 @@ class JJPoint(ctypes.Structure):
     _fields_ = [("m", ctypes.c_double), ("gamma", ctypes.c_double), ("a", ctypes.c_double),
                 ("omega", ctypes.c_double), ("f", ctypes.c_double), ("D", ctypes.c_double),
                 ("n_paths", ctypes.c_uint32), ("steps_per_period", ctypes.c_uint32),
-                ("n_steps", ctypes.c_uint64), ("n_transient", ctypes.c_uint64)]
+                ("n_steps", ctypes.c_uint64), ("n_transient", ctypes.c_uint64),
+                ("potential", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 def lib():
@@ -111,13 +112,19 @@ def gauss_array(seed, tag, a, b, n_first, count):
     return out
 
 
+POT_SIN, POT_SIN2PI = 0, 1
+
+
 def make_points(params):
     """params: list of dicts with keys m, gamma, a, omega, f, D, n_paths,
-    steps_per_period, n_steps, n_transient."""
+    steps_per_period, n_steps, n_transient and optionally potential
+    (POT_SIN, the default, or POT_SIN2PI)."""
     arr = (JJPoint * len(params))()
     for i, p in enumerate(params):
         for k, _ in JJPoint._fields_:
-            setattr(arr[i], k, p[k])
+            if k == "reserved":
+                continue
+            setattr(arr[i], k, p.get(k, POT_SIN) if k == "potential" else p[k])
     return arr
 
 

@@ -155,14 +155,21 @@ static int thread_count(int n_threads)
 }
 
 /* ------------------------------------------------------------------------ */
-/* Josephson junction, Eq. 1 with m x'' + gamma x' = -sin x + a cos(w t) + f  */
-/* + sqrt(2 gamma D) xi(t).  State (phi, v); noise acts on v only.           */
-/* m = 0: gamma x' = -sin x + a cos(w t) + f + sqrt(2 gamma D) xi(t).        */
+/* Eq. 1: m x'' + gamma x' = -V'(x) + a cos(w t) + f + sqrt(2 gamma D) xi(t) */
+/* with -V'(x) = -sin x (Josephson form, x = phi in radians) or, for the     */
+/* paper's V(x) = sin(2 pi x), -V'(x) = -2 pi cos(2 pi x) (x in periods).    */
+/* State (x, v); noise acts on v only.                                       */
+/* m = 0: gamma x' = -V'(x) + a cos(w t) + f + sqrt(2 gamma D) xi(t).        */
 /* ------------------------------------------------------------------------ */
+static double jj_potential_force(const oracle_jj_point* P, double x)
+{
+    return P->potential == ORC_POT_SIN2PI ? -2.0 * PI * cos(2.0 * PI * x) : -sin(x);
+}
+
 static void jj_drift(const void* ctx, double t, const double* x, double* F)
 {
     const oracle_jj_point* P = (const oracle_jj_point*)ctx;
-    double force = -sin(x[0]) + P->a * cos(P->omega * t) + P->f;
+    double force = jj_potential_force(P, x[0]) + P->a * cos(P->omega * t) + P->f;
     if (P->m > 0.0) {
         F[0] = x[1];
         F[1] = (force - P->gamma * x[1]) / P->m;
@@ -179,6 +186,7 @@ static int jj_point_valid(const oracle_jj_point* P)
         !isfinite(P->D) || !isfinite(P->omega))
         return 0;
     if (P->n_paths == 0 || P->steps_per_period == 0) return 0;
+    if (P->potential != ORC_POT_SIN && P->potential != ORC_POT_SIN2PI) return 0;
     return 1;
 }
 
@@ -217,7 +225,9 @@ int oracle_jj_integrate(const oracle_jj_point* pts, uint32_t n_pts, const uint32
             if (!init_from_state) {
                 uint32_t ctr[4] = {0u, (uint32_t)p, qid, ORC_TAG_INIT}, r[4];
                 oracle_philox(seed, ctr, r);
-                phi[gi] = 2.0 * PI * u_closed0(r[0]);
+                /* one potential period times U: 2 pi (radians) or 1 (periods) */
+                const double period = P->potential == ORC_POT_SIN2PI ? 1.0 : 2.0 * PI;
+                phi[gi] = period * u_closed0(r[0]);
                 v[gi] = -2.0 + 4.0 * u_closed0(r[1]);
                 acc[gi] = 0.0;
             }

@@ -62,12 +62,21 @@ void oracle_philox_stream(uint64_t seed, uint32_t tag, uint32_t a, uint32_t b,
 void oracle_gauss_stream(uint64_t seed, uint32_t tag, uint32_t a, uint32_t b,
                          uint64_t n_first, uint64_t count, double* out);
 
-/* ---- Josephson junction (Eq. 1 with the -sin(phi) potential force) ------- */
+/* ---- Josephson junction / Brownian particle in a tilted washboard (Eq. 1) -
+ * Two potentials:
+ *   ORC_POT_SIN    m phi'' + gamma phi' = -sin phi + a cos wt + f + noise
+ *                  (the Josephson-junction form; coordinate phi in radians)
+ *   ORC_POT_SIN2PI m x'' + gamma x' = -V'(x) + a cos wt + f + noise with the
+ *                  paper's V(x) = sin(2 pi x) (Sec. 2; x in potential periods)
+ * noise = sqrt(2 gamma D) xi(t) in both. */
+enum { ORC_POT_SIN = 0, ORC_POT_SIN2PI = 1 };
 
 typedef struct {
     double m, gamma, a, omega, f, D;   /* m = 0 selects the overdamped limit */
     uint32_t n_paths, steps_per_period; /* dt = 2 pi / (omega * steps_per_period) */
     uint64_t n_steps, n_transient;      /* n_transient is an absolute step index */
+    int32_t potential;                  /* ORC_POT_* */
+    int32_t reserved;
 } oracle_jj_point;
 
 /*
@@ -75,9 +84,12 @@ typedef struct {
  * pts[q].n_steps steps with stochastic Heun (Alg. 2 applied to (phi, v)) or
  * Euler-Maruyama.  Paths of all points are laid out one after another.
  *
- *   phi, v, acc : [total paths] in/out.  phi in radians, NOT wrapped.
- *                 If init_from_state is 0 they are overwritten with the
- *                 Philox INIT draw: phi = 2 pi U(x0), v = -2 + 4 U(x1), acc = 0.
+ *   phi, v, acc : [total paths] in/out.  phi is the point's coordinate,
+ *                 NOT wrapped: radians (ORC_POT_SIN) or periods
+ *                 (ORC_POT_SIN2PI); v its time derivative.  If
+ *                 init_from_state is 0 they are overwritten with the
+ *                 Philox INIT draw: one period times U(x0) (phi = 2 pi U or
+ *                 x = U), v = -2 + 4 U(x1), acc = 0.
  *   point_sums  : [n_pts][2] out: sum_p vbar_p and sum_p vbar_p^2 where
  *                 vbar_p = acc_p / W and W = number of window steps
  *                 (absolute step n with n >= n_transient) up to step0+n_steps.
@@ -87,8 +99,9 @@ typedef struct {
  *                 counters of point q (default q), so that a subset of a
  *                 larger batch draws the same random numbers as in the batch.
  * Returns 0, or -1 on invalid arguments.
- * Parity: pinned by the equilibrium (Boltzmann) moments, the overdamped
- * washboard velocity and the deterministic order-2 convergence.
+ * Parity: pinned, for both potentials, by the equilibrium (Boltzmann)
+ * moments, the overdamped washboard velocity and the deterministic order-2
+ * convergence.
  */
 int oracle_jj_integrate(const oracle_jj_point* pts, uint32_t n_pts, const uint32_t* point_ids,
                         uint64_t seed, uint64_t step0, int scheme, int init_from_state,

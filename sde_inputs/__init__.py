@@ -33,11 +33,24 @@ def seed_of(k):
     return SEED_BASE + k
 
 
+POT_SIN, POT_SIN2PI = 0, 1  # -sin(phi) force (Josephson form); V(x) = sin(2 pi x)
+
+
 def jj_point(m=1.0, gamma=0.9, a=4.2, omega=4.9, f=0.1, D=1e-3, n_paths=4096,
-             steps_per_period=400, n_steps=10000, n_transient=0):
+             steps_per_period=400, n_steps=10000, n_transient=0, potential=POT_SIN):
     return dict(m=float(m), gamma=float(gamma), a=float(a), omega=float(omega), f=float(f),
                 D=float(D), n_paths=int(n_paths), steps_per_period=int(steps_per_period),
-                n_steps=int(n_steps), n_transient=int(n_transient))
+                n_steps=int(n_steps), n_transient=int(n_transient), potential=int(potential))
+
+
+def jj_fig2(n_paths=1 << 19, periods=2000):
+    """The ensemble of the paper's precision study (Fig. 2): V(x) = sin(2 pi x),
+    a = 4.2, gamma = 0.9, omega = 4.9, D = 0.001, f = 0.1, dt = 0.01 of the
+    drive period, t in (0, 2000 periods); the position histogram at the end
+    has 200 bins of one potential period."""
+    return [jj_point(m=1.0, gamma=0.9, a=4.2, omega=4.9, f=0.1, D=1e-3, n_paths=n_paths,
+                     steps_per_period=100, n_steps=100 * periods, n_transient=0,
+                     potential=POT_SIN2PI)]
 
 
 def jj_single(n_paths=4096, n_steps=10000):

@@ -167,6 +167,94 @@ def test_jj_euler_order_one(orc):
     assert np.all(np.abs(slopes - 1) < 0.2), (errs, slopes)
 
 
+# ---- the paper's own potential V(x) = sin(2 pi x), x in periods (Sec. 2) ----
+P2 = sde_inputs.POT_SIN2PI
+
+
+@pytest.mark.parametrize("D", [0.5, 1.0])
+def test_jj_sin2pi_boltzmann_equilibrium(orc, D):
+    """a = f = 0: stationary density exp(-(v^2/2 + sin 2 pi x)/D), so
+    <v^2> = D, <sin 2 pi x> = -I1(1/D)/I0(1/D) and <cos 2 pi x> = 0.  A wrong
+    sign of the force flips the sin moment; a missing 2 pi factor changes it
+    to the moment of a potential 2 pi times shallower."""
+    n_paths = 16384
+    pt = _jj(m=1.0, gamma=1.0, a=0.0, omega=2 * np.pi, f=0.0, D=D, n_paths=n_paths,
+             steps_per_period=400, n_steps=12000, n_transient=0, potential=P2)
+    res = orc.jj_integrate([pt], seed=78)
+    v, x = res["v"], res["phi"]
+    assert abs((v ** 2).mean() - D) < 4 * D * np.sqrt(2.0 / n_paths) + 4e-3
+    s_, c_ = np.sin(2 * np.pi * x), np.cos(2 * np.pi * x)
+    expect = -special.i1(1 / D) / special.i0(1 / D)
+    assert abs(s_.mean() - expect) < 4 * s_.std() / np.sqrt(n_paths) + 2e-3
+    assert abs(c_.mean()) < 4 * c_.std() / np.sqrt(n_paths) + 2e-3
+    wrong = -special.i1(1 / (2 * np.pi * D)) / special.i0(1 / (2 * np.pi * D))
+    assert abs(s_.mean() - wrong) > 0.1
+
+
+@pytest.mark.parametrize("f,gamma", [(7.5, 0.8), (9.0, 1.3), (5.0, 1.0)])
+def test_jj_sin2pi_overdamped_washboard_velocity(orc, f, gamma):
+    """m = 0, D = 0, a = 0: gamma x' = f - 2 pi cos 2 pi x runs with
+    v = 1 / int_0^1 gamma dx / (f - 2 pi cos 2 pi x) = sqrt(f^2 - 4 pi^2)/gamma
+    above f = 2 pi and is locked (v = 0) below."""
+    n_steps, S = 200_000, 400
+    pt = _jj(m=0.0, gamma=gamma, a=0.0, omega=2 * np.pi, f=f, D=0.0, n_paths=4,
+             steps_per_period=S, n_steps=n_steps, n_transient=1000, potential=P2)
+    res = orc.jj_integrate([pt], seed=1)
+    vbar = res["point_sums"][0, 0] / 4
+    T = (n_steps - 1000) * (1.0 / S)
+    exact = np.sqrt(f * f - 4 * np.pi ** 2) / gamma if f > 2 * np.pi else 0.0
+    assert abs(vbar - exact) < 1.0 / T + 1e-3 * max(exact, 1.0)
+
+
+def _sin2pi_rhs(t, y, p):
+    x, v = y
+    return [v, (-2 * np.pi * np.cos(2 * np.pi * x) - p["gamma"] * v + p["a"] * np.cos(p["omega"] * t)
+                + p["f"]) / p["m"]]
+
+
+def test_jj_sin2pi_deterministic_order_two(orc):
+    """D = 0 with the paper's drive (a = 4.2, omega = 4.9, gamma = 0.9,
+    f = 0.1): Heun's global error against a high-order solution falls as dt^2."""
+    p = dict(m=1.0, gamma=0.9, a=4.2, omega=4.9, f=0.1)
+    T_end = 2 * 2 * np.pi / 4.9
+    y0 = [0.3, -0.7]
+    ref = integrate.solve_ivp(_sin2pi_rhs, (0, T_end), y0, args=(p,), method="DOP853",
+                              rtol=1e-13, atol=1e-13).y[:, -1]
+    errs = []
+    for S in (100, 200, 400, 800):
+        pt = _jj(D=0.0, n_paths=1, steps_per_period=S, n_steps=2 * S, potential=P2, **p)
+        res = orc.jj_integrate([pt], seed=0, state=(np.array([y0[0]]), np.array([y0[1]]),
+                                                    np.zeros(1)))
+        errs.append(np.hypot(res["phi"][0] - ref[0], res["v"][0] - ref[1]))
+    slopes = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert np.all(np.abs(slopes - 2) < 0.2), (errs, slopes)
+    assert errs[-1] < 1e-3
+
+
+def test_jj_sin2pi_initial_conditions(orc):
+    """x0 = U(x0) in periods (no 2 pi), v0 = -2 + 4 U(x1)."""
+    import oracle.philox_ref as pref
+    pt = sde_inputs.jj_point(n_paths=6, n_steps=0, potential=P2)
+    res = orc.jj_integrate([pt], seed=4)
+    for p in range(6):
+        w = pref.block(4, 1, p, 0, 0)
+        assert res["phi"][p] == (w[0] >> 8) / 2**24
+        assert res["v"][p] == -2 + 4 * ((w[1] >> 8) / 2**24)
+
+
+def test_jj_potentials_mix_in_one_call(orc):
+    """Each point follows its own potential; a batch equals the points run
+    alone (same point ids)."""
+    pts = [sde_inputs.jj_point(n_paths=5, n_steps=50, potential=k) for k in (0, 1, 0)]
+    both = orc.jj_integrate(pts, seed=6)
+    off = 0
+    for q, pt in enumerate(pts):
+        alone = orc.jj_integrate([pt], seed=6, point_ids=[q])
+        np.testing.assert_array_equal(both["phi"][off:off + 5], alone["phi"])
+        off += 5
+    assert not np.allclose(both["phi"][:5], both["phi"][5:10])
+
+
 def test_jj_resume_is_bit_identical(orc):
     pts = sde_inputs.jj_single(n_paths=64, n_steps=300)
     full = orc.jj_integrate(pts, seed=5)
