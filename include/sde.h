@@ -66,6 +66,13 @@ enum {
 };
 /* Philox counter word 3 of each random stream */
 enum { SDE_TAG_NOISE = 0, SDE_TAG_INIT = 1 };
+/* potential of a Josephson-junction / washboard point (Eq. 1) */
+enum {
+    SDE_POTENTIAL_SIN = 0,    /* force -sin(phi), coordinate phi in radians: the        */
+                              /* Josephson-junction (Stewart-McCumber) form             */
+    SDE_POTENTIAL_SIN2PI = 1  /* the paper's V(x) = sin(2 pi x) (Sec. 2): force         */
+                              /* -2 pi cos(2 pi x), coordinate x in potential periods   */
+};
 
 typedef struct sde_ctx sde_ctx;
 
@@ -98,13 +105,16 @@ typedef struct {
 
 /* ---- Josephson junction (Eq. 1, Alg. 1, Alg. 2) -------------------------- */
 typedef struct {
-    double m, gamma, a, omega, f, D; /* Eq. 1; m = 0 selects the overdamped limit    */
-                                     /* gamma phi' = -sin phi + a cos wt + f + noise */
+    double m, gamma, a, omega, f, D; /* Eq. 1: m x'' + gamma x' = -V'(x) + a cos wt  */
+                                     /* + f + sqrt(2 gamma D) xi(t); m = 0 selects   */
+                                     /* the overdamped limit gamma x' = ...          */
     uint32_t n_paths;                /* independent paths of this point              */
     uint32_t steps_per_period;       /* S: dt = 2 pi / (omega S); the drive phase    */
                                      /* is kept as the step index mod S (Sec. 5)     */
     uint64_t n_steps;                /* steps of this call                           */
     uint64_t n_transient;            /* absolute step index where averaging begins   */
+    int32_t potential;               /* SDE_POTENTIAL_* (0, a zeroed struct: -sin)   */
+    int32_t reserved;                /* must be 0                                    */
 } sde_jj_point;
 
 /*
@@ -114,11 +124,13 @@ typedef struct {
  *
  * Path p of point q (0 <= p < pts[q].n_paths) lives at index
  * off(q) + p of the per-path arrays, off(q) = sum of n_paths of points < q.
- *   theta   [device] float,   per path, phase in revolutions in [0, 1):
- *                             phi = 2 pi (theta + winding)
- *   winding [device] int32,   per path, whole revolutions
- *   v       [device] float,   per path, velocity phi' (m = 0: the step's
- *                             mean velocity (phi_{n+1} - phi_n)/dt)
+ * The coordinate is kept in units of the potential's period L (2 pi for
+ * phi, 1 for x) as theta + winding:
+ *   theta   [device] float,   per path, fraction of a period in [0, 1):
+ *                             phi = 2 pi (theta + winding), x = theta + winding
+ *   winding [device] int32,   per path, whole periods
+ *   v       [device] float,   per path, velocity phi' or x' (m = 0: the
+ *                             step's mean velocity (change over the step)/dt)
  *   acc     [device] double,  per path, sum of v after each window step
  *                             (absolute step n >= n_transient)
  * Each may be NULL (state not kept) unless run->init is
@@ -131,9 +143,12 @@ typedef struct {
  *                             step0 + n_steps (0 if none: sums are 0).
  * The noise of path p of point q at absolute step n is component n & 3 of
  * the Box-Muller Gaussians of Philox(ctr = (n >> 2, p, q, SDE_TAG_NOISE)).
+ * Points of different potentials and of m > 0 / m = 0 mix freely in one
+ * call (one persistent launch per kind present).
  * Errors: SDE_ERR_INVALID for n_pts = 0, n_paths = 0, steps_per_period = 0,
  * omega <= 0, gamma < 0 (or 0 with m = 0), m < 0, D < 0, non-finite
- * parameters, misaligned pointers, FROM_STATE with a NULL state array.
+ * parameters, an unknown potential, reserved != 0, misaligned pointers,
+ * FROM_STATE with a NULL state array.
  */
 int sde_jj_integrate(sde_ctx* ctx, const sde_jj_point* pts /* [host] */, uint32_t n_pts,
                      const sde_run* run, float* theta, int32_t* winding, float* v, double* acc,
@@ -193,6 +208,23 @@ enum {
 int sde_observables(sde_ctx* ctx, int kind, const void* dev_in /* [device] */,
                     const uint32_t* counts /* [host] */, uint32_t n_groups,
                     double* host_out /* [host] [n_groups][2] */, void* hip_stream);
+
+/*
+ * Coarse-grained position histogram with one bin per potential period (the
+ * distributions of Fig. 2 and Sec. 5): with x = theta + winding in periods
+ * and theta in [0, 1), the bin [x0 + b, x0 + b + 1) holds exactly the paths
+ * with winding == x0 + b.  Counts the n device entries of `winding` into
+ *   counts[0]            winding <  x0
+ *   counts[1 + b]        winding == x0 + b,  0 <= b < n_bins
+ *   counts[n_bins + 1]   winding >= x0 + n_bins
+ * counts: [device] uint64 [n_bins + 2], overwritten (zeroed by a kernel, so
+ * the call can be recorded in a HIP graph).  Integer counts: bitwise
+ * reproducible.  Asynchronous on `hip_stream`.  Errors: SDE_ERR_INVALID for
+ * NULL counts, NULL winding with n > 0, n_bins = 0 or n_bins > 2^24, a
+ * misaligned pointer.
+ */
+int sde_position_histogram(sde_ctx* ctx, const int32_t* winding /* [device] */, uint64_t n, int64_t x0,
+                           uint32_t n_bins, uint64_t* counts /* [device] */, void* hip_stream);
 
 /* ---- learned surrogate for the mean velocity <v> ------------------------- */
 /*

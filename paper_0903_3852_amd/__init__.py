@@ -24,11 +24,12 @@ SDE_HEUN, SDE_EULER = 0, 1
 SDE_INIT_PHILOX, SDE_INIT_FROM_STATE = 0, 1
 SDE_MEANFIELD, SDE_TILED, SDE_DENSE_FP32, SDE_DENSE_BF16X3, SDE_DENSE_FP16X3 = 0, 1, 2, 3, 4
 SDE_TAG_NOISE, SDE_TAG_INIT = 0, 1
+SDE_POTENTIAL_SIN, SDE_POTENTIAL_SIN2PI = 0, 1
 SDE_OBS_MEAN_F32, SDE_OBS_MEAN_F64, SDE_OBS_MEANSQ_F32, SDE_OBS_ORDER = 0, 1, 2, 3
 SDE_OPT_AUTOTUNE, SDE_OPT_GRAPHS, SDE_OPT_JJ_PPT = 1, 2, 3
 
 EXPORTS = ["sde_create", "sde_destroy", "sde_strerror", "sde_last_error", "sde_check",
-           "sde_jj_integrate", "sde_kuramoto_integrate", "sde_observables",
+           "sde_jj_integrate", "sde_kuramoto_integrate", "sde_observables", "sde_position_histogram",
            "sde_debug_philox", "sde_debug_gauss", "sde_set_option", "sde_set_tune_cache",
            "sde_get_stats", "sde_surrogate_create", "sde_surrogate_destroy",
            "sde_surrogate_param_count", "sde_surrogate_set_params", "sde_surrogate_get_params",
@@ -47,7 +48,8 @@ class sde_jj_point(ctypes.Structure):
     _fields_ = [("m", ctypes.c_double), ("gamma", ctypes.c_double), ("a", ctypes.c_double),
                 ("omega", ctypes.c_double), ("f", ctypes.c_double), ("D", ctypes.c_double),
                 ("n_paths", ctypes.c_uint32), ("steps_per_period", ctypes.c_uint32),
-                ("n_steps", ctypes.c_uint64), ("n_transient", ctypes.c_uint64)]
+                ("n_steps", ctypes.c_uint64), ("n_transient", ctypes.c_uint64),
+                ("potential", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class sde_run(ctypes.Structure):
@@ -118,6 +120,8 @@ def lib():
         L.sde_observables.argtypes = [vp, i32, vp, ctypes.POINTER(u32), u32,
                                       ctypes.POINTER(ctypes.c_double), vp]
         L.sde_observables.restype = i32
+        L.sde_position_histogram.argtypes = [vp, vp, u64, ctypes.c_int64, u32, vp, vp]
+        L.sde_position_histogram.restype = i32
         L.sde_debug_philox.argtypes = [vp, u64, u32, u32, u32, u64, u64, vp, vp]
         L.sde_debug_philox.restype = i32
         L.sde_debug_gauss.argtypes = [vp, u64, u32, u32, u32, u64, u64, vp, vp]
@@ -222,25 +226,32 @@ def sde_check(ctx):
 
 def make_points(params):
     """list of dicts (m, gamma, a, omega, f, D, n_paths, steps_per_period,
-    n_steps, n_transient) -> ctypes array of sde_jj_point."""
+    n_steps, n_transient, optionally potential) -> ctypes array of
+    sde_jj_point."""
     arr = (sde_jj_point * len(params))()
     for i, p in enumerate(params):
         for k, _ in sde_jj_point._fields_:
-            setattr(arr[i], k, p[k])
+            if k == "reserved":
+                continue
+            setattr(arr[i], k, p.get(k, SDE_POTENTIAL_SIN) if k == "potential" else p[k])
     return arr
 
 
 JJ_POINT_DTYPE = np.dtype([("m", "<f8"), ("gamma", "<f8"), ("a", "<f8"), ("omega", "<f8"),
                            ("f", "<f8"), ("D", "<f8"), ("n_paths", "<u4"),
-                           ("steps_per_period", "<u4"), ("n_steps", "<u8"), ("n_transient", "<u8")])
+                           ("steps_per_period", "<u4"), ("n_steps", "<u8"), ("n_transient", "<u8"),
+                           ("potential", "<i4"), ("reserved", "<i4")])
 
 
 def make_points_np(**cols):
     """Vectorized make_points: keyword arrays (or scalars) for every field
-    of sde_jj_point; returns a ctypes array viewing one numpy buffer."""
+    of sde_jj_point (potential optional, default SDE_POTENTIAL_SIN); returns
+    a ctypes array viewing one numpy buffer."""
     n = max(np.size(v) for v in cols.values())
     arr = np.zeros(n, dtype=JJ_POINT_DTYPE)
     for k in JJ_POINT_DTYPE.names:
+        if k == "reserved" or (k == "potential" and k not in cols):
+            continue
         arr[k] = cols[k]
     out = (sde_jj_point * n).from_buffer(arr)
     out._keep = arr
@@ -277,6 +288,13 @@ def sde_observables(ctx, kind, dev_in, counts, stream=None):
                                       out.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                       _stream(stream)))
     return out
+
+
+def sde_position_histogram(ctx, winding, x0, n_bins, counts, stream=None):
+    """Histogram of a device int32 winding array into device uint64
+    counts[n_bins + 2] (underflow, bins x0 .. x0 + n_bins - 1, overflow)."""
+    return _check(ctx, lib().sde_position_histogram(ctx, _ptr(winding), int(winding.numel()), int(x0),
+                                                    int(n_bins), _ptr(counts), _stream(stream)))
 
 
 def sde_debug_philox(ctx, seed, tag, a, b, ctr0_first, n_blocks, dev_out, stream=None):

@@ -1,6 +1,13 @@
-// jj.hip -- ensemble integration of the driven, damped, noisy Josephson
-// junction (Eq. 1 with the -sin(phi) potential force) over many independent
-// paths and parameter points, stochastic Heun (Alg. 2) or Euler-Maruyama.
+// jj.hip -- ensemble integration of the driven, damped, noisy Brownian
+// particle of Eq. 1 over many independent paths and parameter points,
+// stochastic Heun (Alg. 2) or Euler-Maruyama.  Per point, either potential:
+//   SDE_POTENTIAL_SIN     m phi'' + gamma phi' = -sin phi + a cos wt + f + noise
+//                         (Josephson-junction form, phi in radians)
+//   SDE_POTENTIAL_SIN2PI  m x'' + gamma x' = -2 pi cos(2 pi x) + a cos wt + f
+//                         + noise: the paper's V(x) = sin(2 pi x), x in periods
+// The state is the coordinate in units of its period (theta + winding), so
+// the two differ only in the trigonometric function of the force and in
+// per-point constants.
 //
 // Design (gfx950):
 //  * One persistent launch.  Every wavefront pops work items (point, path
@@ -38,11 +45,14 @@
 namespace sde {
 
 struct JJPointDev {
-    float dt, hdt, dt2pi, hdt2pi;  // dt, dt/2, dt/(2 pi), dt/(4 pi)
-    float gim, im, a_im, f_im;     // gamma/m, 1/m, a/m, f/m (overdamped: 1/gamma for m)
+    float dt, hdt, dtp, hdtp;      // dt, dt/2, dt/L, dt/(2L) with L the coordinate's period
+                                   // (2 pi for phi, 1 for x): theta' = v / L
+    float gim, kv, a_im, f_im;     // gamma/m, (force amplitude)/m, a/m, f/m with force
+                                   // amplitude 1 (sin phi) or 2 pi (2 pi cos 2 pi x);
+                                   // overdamped: 1/gamma for 1/m
     float c2, sig_v;               // c2 = -2 ln2 sigma^2 with sigma the noise increment per
-                                   // Gaussian: on v (inertial) or on theta in revolutions
-                                   // (overdamped); sig_v = 2 pi / dt turns the latter into
+                                   // Gaussian: on v (inertial) or on theta in periods
+                                   // (overdamped); sig_v = L / dt turns the latter into
                                    // a velocity
     uint32_t S, lut_off, n_paths, inertial;
     uint64_t path_first, n_steps, n_transient;
@@ -75,36 +85,44 @@ struct JJArgs {
 // One step n -> n + 1 of the PPT paths held by this lane.  e0, e1 are the
 // uniform drive terms (a cos(w t) + f)/m at t_n and t_{n+1} (the second
 // drift evaluation of Alg. 2 is taken at t + dt), ns the noise increments.
-template <int PPT, int SCHEME, bool INERTIAL, bool ACC>
+// The potential's shape at theta (in periods): sin(2 pi theta) for the
+// -sin phi force, cos(2 pi theta) for -V'(x) = -2 pi cos(2 pi x).
+template <bool COSF>
+__device__ __forceinline__ float jj_shape(float theta)
+{
+    return COSF ? cos_rev(theta) : sin_rev(theta);
+}
+
+template <int PPT, int SCHEME, bool INERTIAL, bool COSF, bool ACC>
 __device__ __forceinline__ void jj_step(const JJPointDev& P, float e0, float e1, const float (&ns)[PPT],
                                         float (&th)[PPT], float (&vv)[PPT], float (&af)[PPT])
 {
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         if (INERTIAL) {
-            // X = (phi, v), F = (v, (-sin phi - gamma v + a cos wt + f)/m), noise on v
-            const float F1 = fmaf(-P.im, sin_rev(th[k]), fmaf(-P.gim, vv[k], e0));
+            // X = (coordinate, v), F = (v, (force - gamma v + a cos wt + f)/m), noise on v
+            const float F1 = fmaf(-P.kv, jj_shape<COSF>(th[k]), fmaf(-P.gim, vv[k], e0));
             if (SCHEME == SDE_HEUN) {
                 const float vt = fmaf(P.dt, F1, vv[k]) + ns[k];
-                const float tt = fmaf(P.dt2pi, vv[k], th[k]);
-                const float F2 = fmaf(-P.im, sin_rev(tt), fmaf(-P.gim, vt, e1));
-                th[k] = fmaf(P.hdt2pi, vv[k] + vt, th[k]);
+                const float tt = fmaf(P.dtp, vv[k], th[k]);
+                const float F2 = fmaf(-P.kv, jj_shape<COSF>(tt), fmaf(-P.gim, vt, e1));
+                th[k] = fmaf(P.hdtp, vv[k] + vt, th[k]);
                 vv[k] = fmaf(P.hdt, F1 + F2, vv[k]) + ns[k];
             } else {
-                th[k] = fmaf(P.dt2pi, vv[k], th[k]);
+                th[k] = fmaf(P.dtp, vv[k], th[k]);
                 vv[k] = fmaf(P.dt, F1, vv[k]) + ns[k];
             }
         } else {
-            // overdamped: phi' = (-sin phi + a cos wt + f)/gamma + noise on phi;
-            // v reports the step's mean velocity (phi_{n+1} - phi_n)/dt
-            const float F1 = fmaf(-P.im, sin_rev(th[k]), e0);
+            // overdamped: coordinate' = (force + a cos wt + f)/gamma + noise on
+            // the coordinate; v reports the step's mean velocity (change / dt)
+            const float F1 = fmaf(-P.kv, jj_shape<COSF>(th[k]), e0);
             if (SCHEME == SDE_HEUN) {
-                const float tt = fmaf(P.dt2pi, F1, th[k]) + ns[k];
-                const float F2 = fmaf(-P.im, sin_rev(tt), e1);
-                th[k] = fmaf(P.hdt2pi, F1 + F2, th[k]) + ns[k];
+                const float tt = fmaf(P.dtp, F1, th[k]) + ns[k];
+                const float F2 = fmaf(-P.kv, jj_shape<COSF>(tt), e1);
+                th[k] = fmaf(P.hdtp, F1 + F2, th[k]) + ns[k];
                 vv[k] = fmaf(0.5f, F1 + F2, P.sig_v * ns[k]);
             } else {
-                th[k] = fmaf(P.dt2pi, F1, th[k]) + ns[k];
+                th[k] = fmaf(P.dtp, F1, th[k]) + ns[k];
                 vv[k] = fmaf(P.sig_v, ns[k], F1);
             }
         }
@@ -112,7 +130,7 @@ __device__ __forceinline__ void jj_step(const JJPointDev& P, float e0, float e1,
     }
 }
 
-template <int PPT, int SCHEME, bool INERTIAL>
+template <int PPT, int SCHEME, bool INERTIAL, bool COSF>
 __device__ __forceinline__ void jj_item(const JJArgs& A, uint32_t q, uint32_t chunk)
 {
     const JJPointDev P = load_uniform(A.pts + q);
@@ -179,7 +197,7 @@ __device__ __forceinline__ void jj_item(const JJArgs& A, uint32_t q, uint32_t ch
                     float ns[PPT];
 #pragma unroll
                     for (int k = 0; k < PPT; ++k) ns[k] = g[k][j];
-                    jj_step<PPT, SCHEME, INERTIAL, true>(P, e[j], e[j + 1], ns, th, vv, af);
+                    jj_step<PPT, SCHEME, INERTIAL, COSF, true>(P, e[j], e[j + 1], ns, th, vv, af);
                     fold_tick();
                 }
             } else if (n + 4 <= P.n_transient) {
@@ -188,7 +206,7 @@ __device__ __forceinline__ void jj_item(const JJArgs& A, uint32_t q, uint32_t ch
                     float ns[PPT];
 #pragma unroll
                     for (int k = 0; k < PPT; ++k) ns[k] = g[k][j];
-                    jj_step<PPT, SCHEME, INERTIAL, false>(P, e[j], e[j + 1], ns, th, vv, af);
+                    jj_step<PPT, SCHEME, INERTIAL, COSF, false>(P, e[j], e[j + 1], ns, th, vv, af);
                     fold_tick();
                 }
             } else {
@@ -198,9 +216,9 @@ __device__ __forceinline__ void jj_item(const JJArgs& A, uint32_t q, uint32_t ch
 #pragma unroll
                     for (int k = 0; k < PPT; ++k) ns[k] = g[k][j];
                     if (n + j >= P.n_transient)
-                        jj_step<PPT, SCHEME, INERTIAL, true>(P, e[j], e[j + 1], ns, th, vv, af);
+                        jj_step<PPT, SCHEME, INERTIAL, COSF, true>(P, e[j], e[j + 1], ns, th, vv, af);
                     else
-                        jj_step<PPT, SCHEME, INERTIAL, false>(P, e[j], e[j + 1], ns, th, vv, af);
+                        jj_step<PPT, SCHEME, INERTIAL, COSF, false>(P, e[j], e[j + 1], ns, th, vv, af);
                     fold_tick();
                 }
             }
@@ -217,9 +235,9 @@ __device__ __forceinline__ void jj_item(const JJArgs& A, uint32_t q, uint32_t ch
                 const float ea = fmaf(P.a_im, load_uniform(lut + kk), P.f_im);
                 const float eb = fmaf(P.a_im, load_uniform(lut + kk + 1), P.f_im);
                 if (n >= P.n_transient)
-                    jj_step<PPT, SCHEME, INERTIAL, true>(P, ea, eb, ns, th, vv, af);
+                    jj_step<PPT, SCHEME, INERTIAL, COSF, true>(P, ea, eb, ns, th, vv, af);
                 else
-                    jj_step<PPT, SCHEME, INERTIAL, false>(P, ea, eb, ns, th, vv, af);
+                    jj_step<PPT, SCHEME, INERTIAL, COSF, false>(P, ea, eb, ns, th, vv, af);
                 fold_tick();
                 ++n;
                 kk = (kk + 1 == P.S) ? 0u : kk + 1;
@@ -260,7 +278,7 @@ __device__ __forceinline__ void jj_item(const JJArgs& A, uint32_t q, uint32_t ch
     if (__ballot(bad) != 0 && lane == 0) atomicOr(A.flag, 1);
 }
 
-template <int PPT, int SCHEME, bool INERTIAL>
+template <int PPT, int SCHEME, bool INERTIAL, bool COSF>
 __global__ __launch_bounds__(256) void jj_persistent_kernel(JJArgs A)
 {
     const uint32_t lane = threadIdx.x & (kWave - 1);
@@ -270,7 +288,7 @@ __global__ __launch_bounds__(256) void jj_persistent_kernel(JJArgs A)
         item = uniform_u32(__shfl(item, 0, kWave));
         if (item >= A.n_items) break;
         const JJItem it = load_uniform(A.items + item);
-        jj_item<PPT, SCHEME, INERTIAL>(A, it.point, it.chunk);
+        jj_item<PPT, SCHEME, INERTIAL, COSF>(A, it.point, it.chunk);
     }
 }
 
@@ -319,17 +337,31 @@ __global__ void gauss_dump_kernel(uint32_t k0, uint32_t k1, uint32_t tag, uint32
 
 using JJKernel = void (*)(JJArgs);
 
-template <bool INERTIAL>
-static JJKernel pick_kernel(int ppt, int scheme)
+template <bool INERTIAL, bool COSF>
+static JJKernel pick_kernel_t(int ppt, int scheme)
 {
     if (scheme == SDE_HEUN) {
-        if (ppt == 1) return jj_persistent_kernel<1, SDE_HEUN, INERTIAL>;
-        if (ppt == 4) return jj_persistent_kernel<4, SDE_HEUN, INERTIAL>;
-        return jj_persistent_kernel<2, SDE_HEUN, INERTIAL>;
+        if (ppt == 1) return jj_persistent_kernel<1, SDE_HEUN, INERTIAL, COSF>;
+        if (ppt == 4) return jj_persistent_kernel<4, SDE_HEUN, INERTIAL, COSF>;
+        return jj_persistent_kernel<2, SDE_HEUN, INERTIAL, COSF>;
     }
-    if (ppt == 1) return jj_persistent_kernel<1, SDE_EULER, INERTIAL>;
-    if (ppt == 4) return jj_persistent_kernel<4, SDE_EULER, INERTIAL>;
-    return jj_persistent_kernel<2, SDE_EULER, INERTIAL>;
+    if (ppt == 1) return jj_persistent_kernel<1, SDE_EULER, INERTIAL, COSF>;
+    if (ppt == 4) return jj_persistent_kernel<4, SDE_EULER, INERTIAL, COSF>;
+    return jj_persistent_kernel<2, SDE_EULER, INERTIAL, COSF>;
+}
+
+// Point kinds, one persistent launch each: bit 0 = overdamped, bit 1 = the
+// sin(2 pi x) potential.
+constexpr int kJJKinds = 4;
+
+static JJKernel pick_kernel(int kind, int ppt, int scheme)
+{
+    switch (kind) {
+    case 0: return pick_kernel_t<true, false>(ppt, scheme);
+    case 1: return pick_kernel_t<false, false>(ppt, scheme);
+    case 2: return pick_kernel_t<true, true>(ppt, scheme);
+    default: return pick_kernel_t<false, true>(ppt, scheme);
+    }
 }
 
 static bool finite_point(const sde_jj_point& p)
@@ -339,33 +371,35 @@ static bool finite_point(const sde_jj_point& p)
 }
 
 // Work items of one paths-per-lane choice: chunk layout per point and the
-// queue (longest first), inertial points before overdamped ones.
+// queue of each point kind (longest first within a kind).
 struct JJPlan {
     std::vector<JJPointDev> pts;
     std::vector<JJItem> items;
-    uint32_t n_inertial = 0;
+    uint32_t kind_begin[kJJKinds + 1] = {};  // items of kind k: [kind_begin[k], kind_begin[k + 1])
     uint32_t n_chunks = 0;
 };
 
-static void plan_items(std::vector<JJPointDev>& P, int ppt, JJPlan& out)
+static void plan_items(std::vector<JJPointDev>& P, const std::vector<int>& kinds, int ppt, JJPlan& out)
 {
     const uint32_t chunk_paths = (uint32_t)(kWave * ppt);
-    std::vector<JJItem> it_in, it_od;
+    std::vector<JJItem> it[kJJKinds];
     uint32_t chunk_first = 0;
     for (uint32_t q = 0; q < (uint32_t)P.size(); ++q) {
         JJPointDev& d = P[q];
         d.n_chunks = (d.n_paths + chunk_paths - 1) / chunk_paths;
         d.chunk_first = chunk_first;
-        for (uint32_t c = 0; c < d.n_chunks; ++c) (d.inertial ? it_in : it_od).push_back(JJItem{q, c});
+        for (uint32_t c = 0; c < d.n_chunks; ++c) it[kinds[q]].push_back(JJItem{q, c});
         chunk_first += d.n_chunks;
     }
     auto longest_first = [&](const JJItem& x, const JJItem& y) { return P[x.point].n_steps > P[y.point].n_steps; };
-    std::stable_sort(it_in.begin(), it_in.end(), longest_first);
-    std::stable_sort(it_od.begin(), it_od.end(), longest_first);
     out.pts = P;
-    out.n_inertial = (uint32_t)it_in.size();
-    out.items = std::move(it_in);
-    out.items.insert(out.items.end(), it_od.begin(), it_od.end());
+    out.items.clear();
+    for (int k = 0; k < kJJKinds; ++k) {
+        std::stable_sort(it[k].begin(), it[k].end(), longest_first);
+        out.kind_begin[k] = (uint32_t)out.items.size();
+        out.items.insert(out.items.end(), it[k].begin(), it[k].end());
+    }
+    out.kind_begin[kJJKinds] = (uint32_t)out.items.size();
     out.n_chunks = chunk_first;
 }
 
@@ -373,18 +407,19 @@ struct JJLaunch {
     JJArgs A;
     int ppt;
     int scheme;
-    uint32_t n_inertial, n_items, n_pts;
-    uint32_t grid[2];
+    uint32_t kind_begin[kJJKinds + 1];
+    uint32_t n_items, n_pts;
+    uint32_t grid[kJJKinds];
     double* point_sums;
 };
 
 static int jj_grids(sde_ctx* ctx, JJLaunch& L)
 {
-    for (int kind = 0; kind < 2; ++kind) {
-        const uint32_t count = kind == 0 ? L.n_inertial : L.n_items - L.n_inertial;
+    for (int kind = 0; kind < kJJKinds; ++kind) {
+        const uint32_t count = L.kind_begin[kind + 1] - L.kind_begin[kind];
         L.grid[kind] = 0;
         if (!count) continue;
-        JJKernel kern = kind == 0 ? pick_kernel<true>(L.ppt, L.scheme) : pick_kernel<false>(L.ppt, L.scheme);
+        JJKernel kern = pick_kernel(kind, L.ppt, L.scheme);
         int per_cu = 0;
         SDE_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), 256, 0));
         if (per_cu < 1) per_cu = 1;
@@ -394,20 +429,20 @@ static int jj_grids(sde_ctx* ctx, JJLaunch& L)
     return SDE_OK;
 }
 
-// The launch sequence of one call: reset the two queues, the persistent
-// kernel of each point kind, the per-point sums.
+// The launch sequence of one call: reset the queues, the persistent kernel
+// of each point kind present, the per-point sums.
 static int jj_record(sde_ctx* ctx, const JJLaunch& L, hipStream_t s)
 {
-    int st = zero_counters(ctx, 0, 2, s);
+    int st = zero_counters(ctx, 0, kJJKinds, s);
     if (st) return st;
     const JJItem* all = L.A.items;
-    for (int kind = 0; kind < 2; ++kind) {
+    for (int kind = 0; kind < kJJKinds; ++kind) {
         if (!L.grid[kind]) continue;
         JJArgs A = L.A;
-        A.items = all + (kind == 0 ? 0 : L.n_inertial);
-        A.n_items = kind == 0 ? L.n_inertial : L.n_items - L.n_inertial;
+        A.items = all + L.kind_begin[kind];
+        A.n_items = L.kind_begin[kind + 1] - L.kind_begin[kind];
         A.queue = ctx->counters + kind;
-        JJKernel kern = kind == 0 ? pick_kernel<true>(L.ppt, L.scheme) : pick_kernel<false>(L.ppt, L.scheme);
+        JJKernel kern = pick_kernel(kind, L.ppt, L.scheme);
         hipLaunchKernelGGL(kern, dim3(L.grid[kind]), dim3(256), 0, s, A);
         SDE_HIP(ctx, hipGetLastError());
     }
@@ -427,11 +462,11 @@ static int jj_upload_plan(sde_ctx* ctx, const JJPlan& plan, hipStream_t stream, 
     void* partials = nullptr;
     if ((st = ensure_ws(ctx, kSlotJJPartials, (size_t)std::max(plan.n_chunks, 1u) * 2 * sizeof(double), &partials)))
         return st;
-    if ((st = ensure_counters(ctx, 2))) return st;
+    if ((st = ensure_counters(ctx, kJJKinds))) return st;
     L.A.pts = static_cast<const JJPointDev*>(ctx->ws[kSlotJJPoints].ptr);
     L.A.items = static_cast<const JJItem*>(ctx->ws[kSlotJJItems].ptr);
     L.A.partials = static_cast<double*>(partials);
-    L.n_inertial = plan.n_inertial;
+    std::copy(plan.kind_begin, plan.kind_begin + kJJKinds + 1, L.kind_begin);
     L.n_items = (uint32_t)plan.items.size();
     L.n_pts = (uint32_t)plan.pts.size();
     return jj_grids(ctx, L);
@@ -450,8 +485,8 @@ static int ilog2u64(uint64_t x)
 // Times the candidate paths-per-lane choices on a short slice of the call
 // (same points, at most 2048 steps, no per-path outputs) and returns the
 // fastest.  Nothing the caller passed is written.
-static int jj_tune(sde_ctx* ctx, const std::vector<JJPointDev>& P0, const JJLaunch& base, hipStream_t stream,
-                   int* best_ppt)
+static int jj_tune(sde_ctx* ctx, const std::vector<JJPointDev>& P0, const std::vector<int>& kinds,
+                   const JJLaunch& base, hipStream_t stream, int* best_ppt)
 {
     std::vector<JJPointDev> P = P0;
     uint64_t work = 0;
@@ -470,7 +505,7 @@ static int jj_tune(sde_ctx* ctx, const std::vector<JJPointDev>& P0, const JJLaun
     int st = SDE_OK;
     for (int ppt : {1, 2, 4}) {
         JJPlan plan;
-        plan_items(P, ppt, plan);
+        plan_items(P, kinds, ppt, plan);
         JJLaunch L = base;
         L.ppt = ppt;
         L.point_sums = nullptr;
@@ -521,10 +556,11 @@ int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, con
     const uint32_t M = run->sample_every ? run->sample_every : 100u;
 
     std::vector<JJPointDev> P(n_pts);
+    std::vector<int> kinds(n_pts);
     std::map<uint32_t, uint32_t> lut_of;  // S -> offset
     std::vector<float> lut;
     uint64_t path_first = 0, max_steps = 0;
-    bool any_inertial = false, any_overdamped = false;
+    unsigned kinds_present = 0;
     for (uint32_t q = 0; q < n_pts; ++q) {
         const sde_jj_point& p = pts[q];
         if (!finite_point(p)) return fail(ctx, SDE_ERR_INVALID, "point %u: non-finite parameter", q);
@@ -534,33 +570,39 @@ int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, con
         if (!(p.omega > 0) || p.m < 0 || p.gamma < 0 || p.D < 0 || (p.m == 0 && !(p.gamma > 0)))
             return fail(ctx, SDE_ERR_INVALID, "point %u: need omega > 0, m >= 0, D >= 0, gamma >= 0 "
                         "(gamma > 0 when m = 0)", q);
+        if (p.potential != SDE_POTENTIAL_SIN && p.potential != SDE_POTENTIAL_SIN2PI)
+            return fail(ctx, SDE_ERR_INVALID, "point %u: unknown potential %d", q, p.potential);
+        if (p.reserved != 0) return fail(ctx, SDE_ERR_INVALID, "point %u: reserved must be 0", q);
+        const bool sin2pi = p.potential == SDE_POTENTIAL_SIN2PI;
+        const double L = sin2pi ? 1.0 : 2.0 * M_PI;   // period of the coordinate
+        const double amp = sin2pi ? 2.0 * M_PI : 1.0;  // amplitude of the potential force
         const double dt = 2.0 * M_PI / (p.omega * (double)p.steps_per_period);
         JJPointDev& d = P[q];
         d.dt = (float)dt;
         d.hdt = (float)(0.5 * dt);
-        d.dt2pi = (float)(dt / (2.0 * M_PI));
-        d.hdt2pi = (float)(dt / (4.0 * M_PI));
+        d.dtp = (float)(dt / L);
+        d.hdtp = (float)(0.5 * dt / L);
         d.inertial = p.m > 0 ? 1u : 0u;
         if (d.inertial) {
-            d.im = (float)(1.0 / p.m);
+            d.kv = (float)(amp / p.m);
             d.gim = (float)(p.gamma / p.m);
             d.a_im = (float)(p.a / p.m);
             d.f_im = (float)(p.f / p.m);
             const double sig = std::sqrt(2.0 * p.gamma * p.D * dt) / p.m;
             d.c2 = (float)(-2.0 * M_LN2 * sig * sig);
             d.sig_v = 0.f;
-            any_inertial = true;
         } else {
             const double s = std::sqrt(2.0 * p.D * dt / p.gamma);
-            d.im = (float)(1.0 / p.gamma);
+            d.kv = (float)(amp / p.gamma);
             d.gim = 0.f;
             d.a_im = (float)(p.a / p.gamma);
             d.f_im = (float)(p.f / p.gamma);
-            const double sig = s / (2.0 * M_PI);
+            const double sig = s / L;
             d.c2 = (float)(-2.0 * M_LN2 * sig * sig);
-            d.sig_v = (float)(2.0 * M_PI / dt);
-            any_overdamped = true;
+            d.sig_v = (float)(L / dt);
         }
+        kinds[q] = (d.inertial ? 0 : 1) + (sin2pi ? 2 : 0);
+        kinds_present |= 1u << kinds[q];
         d.S = p.steps_per_period;
         auto it = lut_of.find(d.S);
         if (it == lut_of.end()) {
@@ -603,13 +645,13 @@ int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, con
     int ppt = ctx->jj_ppt;
     if (!ppt) {
         char key[160];
-        snprintf(key, sizeof key, "jj|%s|scheme%d|kinds%d%d|paths2^%d|steps2^%d", ctx->arch.c_str(), run->scheme,
-                 (int)any_inertial, (int)any_overdamped, ilog2u64(path_first), ilog2u64(std::max<uint64_t>(max_steps, 1)));
+        snprintf(key, sizeof key, "jj|%s|scheme%d|kinds%x|paths2^%d|steps2^%d", ctx->arch.c_str(), run->scheme,
+                 kinds_present, ilog2u64(path_first), ilog2u64(std::max<uint64_t>(max_steps, 1)));
         if (!tune_lookup(ctx, key, &ppt)) {
             ppt = 2;
             if (ctx->autotune) {
                 const auto t0 = std::chrono::steady_clock::now();
-                if ((st = jj_tune(ctx, P, L, stream, &ppt))) return st;
+                if ((st = jj_tune(ctx, P, kinds, L, stream, &ppt))) return st;
                 ctx->last.tuned = 1;
                 ctx->last.tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
                 tune_store(ctx, key, ppt);
@@ -618,18 +660,20 @@ int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, con
     }
     L.ppt = ppt;
     JJPlan plan;
-    plan_items(P, ppt, plan);
+    plan_items(P, kinds, ppt, plan);
     if ((st = jj_upload_plan(ctx, plan, stream, L))) return st;
     ctx->last.jj_paths_per_lane = ppt;
     ctx->last.work_items = plan.items.size();
 
     // everything baked into the recorded launches
     char key[512];
-    snprintf(key, sizeof key, "jj|%p|%p|%p|%p|%p|%p|%p|%llu|%u|%u|%u|%d|%d|%d|%u|%u|%u|%u|%u", (void*)L.A.pts,
+    snprintf(key, sizeof key, "jj|%p|%p|%p|%p|%p|%p|%p|%llu|%u|%u|%u|%d|%d|%d|%u|%u", (void*)L.A.pts,
              (void*)L.A.items, (void*)L.A.lut, (void*)theta, (void*)winding, (void*)v, (void*)acc,
              (unsigned long long)run->step0, L.A.key0, L.A.key1, M, L.A.init_from_state, ppt, run->scheme,
-             L.n_inertial, L.n_items, L.n_pts, L.grid[0], L.grid[1]);
+             L.n_items, L.n_pts);
     std::string k = key;
+    for (int kind = 0; kind < kJJKinds; ++kind)
+        k += "|" + std::to_string(L.kind_begin[kind + 1]) + "/" + std::to_string(L.grid[kind]);
     k += point_sums ? "|ps" + std::to_string((uintptr_t)point_sums) : "|ps0";
     if ((st = run_recorded(ctx, k, stream, [&](hipStream_t s) { return jj_record(ctx, L, s); }))) return st;
     if (run->sync) return sync_and_check(ctx, stream);

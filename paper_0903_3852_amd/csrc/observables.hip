@@ -81,6 +81,61 @@ __global__ __launch_bounds__(kObsThreads) void obs_kernel(int kind, const void* 
     }
 }
 
+// ---- coarse-grained position histogram (one bin per potential period) ----
+// With x = theta + winding and theta in [0, 1), the bin of x is its winding
+// count, so the histogram is an integer histogram of `winding`.  Each
+// workgroup counts its grid-stride share in LDS (32-bit; the grid keeps a
+// workgroup's share below 2^31) and adds its bins to the 64-bit totals;
+// more bins than fit in LDS go straight to global 64-bit atomics.  Integer
+// sums: the result does not depend on the order.
+constexpr uint32_t kHistLds = 8192;
+
+__global__ void hist_zero_kernel(uint64_t* counts, uint32_t n)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) counts[i] = 0ull;
+}
+
+__global__ __launch_bounds__(256) void hist_kernel(const int32_t* w, uint64_t n, int64_t x0, uint32_t nb,
+                                                   uint64_t* counts)
+{
+    __shared__ uint32_t h[kHistLds];
+    const bool lds = nb + 2 <= kHistLds;
+    if (lds)
+        for (uint32_t i = threadIdx.x; i < nb + 2; i += blockDim.x) h[i] = 0u;
+    __syncthreads();
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+        const int64_t d = (int64_t)w[i] - x0;
+        const uint32_t b = d < 0 ? 0u : d >= (int64_t)nb ? nb + 1 : (uint32_t)d + 1;
+        if (lds)
+            atomicAdd(&h[b], 1u);
+        else
+            atomicAdd(reinterpret_cast<unsigned long long*>(counts + b), 1ull);
+    }
+    __syncthreads();
+    if (lds)
+        for (uint32_t i = threadIdx.x; i < nb + 2; i += blockDim.x)
+            if (h[i]) atomicAdd(reinterpret_cast<unsigned long long*>(counts + i), (unsigned long long)h[i]);
+}
+
+int histogram_impl(sde_ctx* ctx, const int32_t* winding, uint64_t n, int64_t x0, uint32_t n_bins, uint64_t* counts,
+                   hipStream_t stream)
+{
+    if ((!winding && n) || !counts) return fail(ctx, SDE_ERR_INVALID, "null winding or counts");
+    if (n_bins == 0 || n_bins > (1u << 24)) return fail(ctx, SDE_ERR_INVALID, "n_bins must be in [1, 2^24]");
+    if (!aligned(winding, 4) || !aligned(counts, 8)) return fail(ctx, SDE_ERR_INVALID, "misaligned pointer");
+    const uint32_t nc = n_bins + 2;
+    hipLaunchKernelGGL(hist_zero_kernel, dim3((nc + 255) / 256), dim3(256), 0, stream, counts, nc);
+    if (n) {
+        uint64_t grid = std::min<uint64_t>((n + 255) / 256, (uint64_t)ctx->n_cu * 4);
+        grid = std::max<uint64_t>(grid, (n >> 31) + 1);  // at most 2^31 paths per workgroup
+        hipLaunchKernelGGL(hist_kernel, dim3((uint32_t)grid), dim3(256), 0, stream, winding, n, x0, n_bins, counts);
+    }
+    SDE_HIP(ctx, hipGetLastError());
+    return SDE_OK;
+}
+
 int observables_impl(sde_ctx* ctx, int kind, const void* in, const uint32_t* counts, uint32_t n_groups,
                      double* host_out, hipStream_t stream)
 {

@@ -389,6 +389,14 @@ int sde_observables(sde_ctx* ctx, int kind, const void* dev_in, const uint32_t* 
     }
 }
 
+int sde_position_histogram(sde_ctx* ctx, const int32_t* winding, uint64_t n, int64_t x0, uint32_t n_bins,
+                           uint64_t* counts, void* hip_stream)
+{
+    if (!ctx) return SDE_ERR_INVALID;
+    ctx->last_error.clear();
+    return histogram_impl(ctx, winding, n, x0, n_bins, counts, static_cast<hipStream_t>(hip_stream));
+}
+
 int sde_debug_philox(sde_ctx* ctx, uint64_t seed, uint32_t tag, uint32_t a, uint32_t b,
                      uint64_t ctr0_first, uint64_t n_blocks, uint32_t* dev_out, void* hip_stream)
 {

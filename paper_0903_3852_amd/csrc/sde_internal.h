@@ -144,6 +144,8 @@ int debug_gauss_impl(sde_ctx* ctx, uint64_t seed, uint32_t tag, uint32_t a, uint
                      uint64_t n0, uint64_t n, float* out, hipStream_t stream);
 int observables_impl(sde_ctx* ctx, int kind, const void* in, const uint32_t* counts,
                      uint32_t n_groups, double* host_out, hipStream_t stream);
+int histogram_impl(sde_ctx* ctx, const int32_t* winding, uint64_t n, int64_t x0, uint32_t n_bins, uint64_t* counts,
+                   hipStream_t stream);
 int kuramoto_impl(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, float* phi,
                   const float* omega, const float* K, double* r_samples, hipStream_t stream);
 

@@ -31,12 +31,38 @@ def test_library_exports_every_declared_symbol():
     assert set(sde.EXPORTS) <= set(_declared())
 
 
-def test_struct_layouts_match_header():
+def test_struct_layouts_match_header(tmp_path):
+    """Every field offset and struct size of the binding's ctypes mirrors
+    equals what a C compiler makes of include/sde.h."""
     import ctypes
+    import shutil
+    import subprocess
     import paper_0903_3852_amd as sde
-    assert ctypes.sizeof(sde.sde_jj_point) == 6 * 8 + 2 * 4 + 2 * 8
-    assert ctypes.sizeof(sde.sde_run) == 8 + 8 + 4 * 4
-    assert ctypes.sizeof(sde.sde_kuramoto_desc) == 4 + 4 + 3 * 8 + 8 + 4 + 4
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = [sde.sde_jj_point, sde.sde_run, sde.sde_kuramoto_desc, sde.sde_stats,
+               sde.sde_surrogate_scaling, sde.sde_train_opts, sde.sde_scan_stats]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "sde.h"', "int main(void) {"]
+    for st in structs:
+        n = st.__name__
+        lines.append(f'printf("{n} %zu\\n", sizeof({n}));')
+        for f, _ in st._fields_:
+            lines.append(f'printf("{n}.{f} %zu\\n", offsetof({n}, {f}));')
+    lines.append("return 0; }")
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines))
+    exe = tmp_path / "layout"
+    subprocess.check_call([cc, "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    got = dict(l.split() for l in subprocess.check_output([str(exe)], text=True).splitlines())
+    for st in structs:
+        n = st.__name__
+        assert int(got[n]) == ctypes.sizeof(st), n
+        for f, _ in st._fields_:
+            assert int(got[f"{n}.{f}"]) == getattr(st, f).offset, (n, f)
+    assert sde.JJ_POINT_DTYPE.itemsize == ctypes.sizeof(sde.sde_jj_point)
+    for f, _ in sde.sde_jj_point._fields_:
+        assert sde.JJ_POINT_DTYPE.fields[f][1] == getattr(sde.sde_jj_point, f).offset, f
 
 
 def test_status_strings():

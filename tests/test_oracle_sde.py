@@ -231,6 +231,24 @@ def test_jj_sin2pi_deterministic_order_two(orc):
     assert errs[-1] < 1e-3
 
 
+def test_jj_sin2pi_absolute_negative_mobility(orc):
+    """The Fig. 2 parameters (a = 4.2, gamma = 0.9, omega = 4.9, D = 0.001)
+    lie in the anomalous-response regime the paper names (Sec. 2): a small
+    bias f = +0.1 drives a negative mean velocity, f = -0.1 a positive one,
+    each more than 5 standard errors from zero (512 paths, 100 periods of
+    transient, 300 averaged).  Only the sign is pinned; the magnitude still
+    drifts over the paper's 2000 periods."""
+    out = {}
+    for f in (0.1, -0.1):
+        pt = _jj(m=1.0, gamma=0.9, a=4.2, omega=4.9, f=f, D=1e-3, n_paths=512, steps_per_period=100,
+                 n_steps=100 * 400, n_transient=100 * 100, potential=P2)
+        r = orc.jj_integrate([pt], seed=11)
+        vb = r["acc"] / (pt["n_steps"] - pt["n_transient"])
+        out[f] = (vb.mean(), vb.std(ddof=1) / np.sqrt(vb.size))
+    assert out[0.1][0] < -5 * out[0.1][1], out
+    assert out[-0.1][0] > 5 * out[-0.1][1], out
+
+
 def test_jj_sin2pi_initial_conditions(orc):
     """x0 = U(x0) in periods (no 2 pi), v0 = -2 + 4 U(x1)."""
     import oracle.philox_ref as pref
