@@ -297,6 +297,48 @@ def bench_surrogate(args, sde, torch, dev, n_train=100000, n_query=1000000, epoc
             "plain_simulation_s": t_plain, "speedup": t_plain / t_scan}
 
 
+def bench_fig2(args, sde, torch, dev):
+    """The paper's Fig. 2 ensemble: 2^19 paths of Eq. 1 with V(x) = sin(2 pi x)
+    at a = 4.2, gamma = 0.9, omega = 4.9, D = 0.001, f = 0.1, dt = 0.01 of the
+    drive period, 2000 periods (2*10^5 Heun steps), then the coarse-grained
+    position histogram (200 bins of one period, centred on the ensemble).
+    The paper's single-precision run took 20 s on its GPU, including writing
+    the trajectories to disk (not done here): context, not a target."""
+    pts = sde_inputs.jj_fig2()
+    P, n = pts[0]["n_paths"], pts[0]["n_steps"]
+    th = torch.empty(P, dtype=torch.float32, device=dev)
+    wd = torch.empty(P, dtype=torch.int32, device=dev)
+    v = torch.empty(P, dtype=torch.float32, device=dev)
+    acc = torch.empty(P, dtype=torch.float64, device=dev)
+    counts = torch.zeros(202, dtype=torch.int64, device=dev)
+    ctx = sde.sde_create(0)
+    run = sde.make_run(sde_inputs.seed_of(20))
+    stream = torch.cuda.current_stream()
+    sde.sde_jj_integrate(ctx, [dict(pts[0], n_steps=100)], run, th, wd, v, acc)  # warm-up
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record(stream)
+    sde.sde_jj_integrate(ctx, pts, run, th, wd, v, acc)
+    e.record(stream)
+    torch.cuda.synchronize()
+    t = s.elapsed_time(e) / 1e3
+    x0 = int(wd.median().item()) - 100
+    sde.sde_position_histogram(ctx, wd, x0, 200, counts)
+    torch.cuda.synchronize()
+    sde.sde_check(ctx)
+    sde.sde_destroy(ctx)
+    h = counts.cpu().numpy()
+    vb = acc.cpu().numpy() / n
+    x = th.cpu().double().numpy() + wd.cpu().double().numpy()
+    return {"workload": "jj_fig2", "potential": "sin(2 pi x)", "paths": P, "heun_steps": n,
+            "seconds": t, "path_steps_per_s": P * n / t,
+            "mean_velocity": float(vb.mean()), "mean_velocity_se": float(vb.std(ddof=1) / np.sqrt(P)),
+            "position_mean": float(x.mean()), "position_sd": float(x.std()),
+            "histogram": {"x0": x0, "bins": 200, "underflow": int(h[0]), "overflow": int(h[201]),
+                          "occupied_bins": int(np.count_nonzero(h[1:201])), "max_bin": int(h[1:201].max())},
+            "paper_reported_s": {"fp32": 20.0, "fp64": 780.0, "cpu_one_core": "> 10800"}}
+
+
 KURA = {
     "kuramoto_mf": dict(cfg="uniform", coupling=0, scheme=0, steps=100000),
     "kuramoto_mf_em": dict(cfg="uniform", coupling=0, scheme=1, steps=100000),
@@ -372,7 +414,7 @@ def main():
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="jj_scan",
-                    choices=["jj_scan", "jj_batch", "jj_surrogate"] + sorted(KURA))
+                    choices=["jj_scan", "jj_batch", "jj_surrogate", "jj_fig2"] + sorted(KURA))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kuramoto", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -404,10 +446,13 @@ def main():
                                                             (out["kernel_ms"] / 1e3))
             out["jj_batch"] = jb
             out["surrogate"] = bench_surrogate(args, sde, torch, dev)
+            out["fig2"] = bench_fig2(args, sde, torch, dev)
     elif args.workload == "jj_batch":
         out = bench_jj_batch(args, sde, torch, dev)
     elif args.workload == "jj_surrogate":
         out = bench_surrogate(args, sde, torch, dev)
+    elif args.workload == "jj_fig2":
+        out = bench_fig2(args, sde, torch, dev)
     else:
         out = bench_kuramoto(args.workload, args, sde, torch, dev, steps=args.kura_steps, reps=args.steps)
     if args.calibrate_copy:
