@@ -129,20 +129,34 @@ struct GemmArgs {
     uint32_t rows_offset;                   // first row of this minibatch in rows
     uint32_t M, N, K;
     int32_t last;                           // FWD: output layer (no GELU)
+    uint32_t kslices;                       // DW: the k range is split over grid.z = member *
+                                            // kslices + slice; slice s writes the M x N partial
+                                            // C + member * c_mstride + s * M * N (summed later)
 };
+
+// The k range of slice ks of kslices, in whole k steps.
+__device__ __forceinline__ void k_range(uint32_t K, uint32_t kslices, uint32_t ks, uint32_t& k_begin, uint32_t& k_end)
+{
+    const uint32_t per = ((K + kslices - 1) / kslices + kGK - 1) / kGK * kGK;
+    k_begin = min(K, ks * per);
+    k_end = min(K, k_begin + per);
+}
 
 template <int MODE>
 __global__ __launch_bounds__(256) void mlp_gemm_kernel(GemmArgs g)
 {
     __shared__ float As[kGK][kGT + 1];
     __shared__ float Bs[kGK][kGT + 1];
-    const uint32_t mem = blockIdx.z;
+    const uint32_t ksl = MODE == kDW ? g.kslices : 1u;
+    const uint32_t mem = blockIdx.z / ksl, ks = blockIdx.z % ksl;
     const float* A = g.A + mem * g.a_mstride;
     const float* B = g.B + mem * g.b_mstride;
     const uint32_t m0 = blockIdx.y * kGT, n0 = blockIdx.x * kGT;
     const uint32_t tx = threadIdx.x & 15u, ty = threadIdx.x >> 4;
+    uint32_t kb = 0, ke = g.K;
+    if (MODE == kDW) k_range(g.K, ksl, ks, kb, ke);
     float acc[4][4] = {};
-    for (uint32_t k0 = 0; k0 < g.K; k0 += kGK) {
+    for (uint32_t k0 = kb; k0 < ke; k0 += kGK) {
         // 64 x 16 elements of each operand, 4 per lane
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
@@ -160,7 +174,7 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(GemmArgs g)
                 As[kk][mm] = va;
             } else {
                 const uint32_t m = m0 + mm2, k = k0 + kk2;
-                if (m < g.M && k < g.K) va = A[(uint64_t)k * g.M + m];
+                if (m < g.M && k < ke) va = A[(uint64_t)k * g.M + m];
                 As[kk2][mm2] = va;
             }
             if (MODE == kFwd) {
@@ -169,7 +183,7 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(GemmArgs g)
                 Bs[kk][mm] = vb;
             } else {
                 const uint32_t n = n0 + mm2, k = k0 + kk2;
-                if (n < g.N && k < g.K) vb = B[(uint64_t)k * g.N + n];
+                if (n < g.N && k < ke) vb = B[(uint64_t)k * g.N + n];
                 Bs[kk2][mm2] = vb;
             }
         }
@@ -203,7 +217,7 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(GemmArgs g)
                 g.C[mem * g.c_mstride + o] = z;
                 g.C2[mem * g.c2_mstride + o] = g.last ? z : gelu(z);
             } else if (MODE == kDW) {
-                g.C[mem * g.c_mstride + o] = acc[i][j];
+                g.C[mem * g.c_mstride + (uint64_t)ks * g.M * g.N + o] = acc[i][j];
             } else {
                 g.C[mem * g.c_mstride + o] = acc[i][j] * gelu_grad(g.Zp[mem * g.zp_mstride + o]);
             }
@@ -216,21 +230,23 @@ __global__ __launch_bounds__(256) void mlp_gemm_dw_gather_kernel(GemmArgs g)
 {
     __shared__ float As[kGK][kGT + 1];
     __shared__ float Bs[kGK][kGT + 1];
-    const uint32_t mem = blockIdx.z;
+    const uint32_t mem = blockIdx.z / g.kslices, ks = blockIdx.z % g.kslices;
     const float* A = g.A + mem * g.a_mstride;
     const uint32_t m0 = blockIdx.y * kGT, n0 = blockIdx.x * kGT;
     const uint32_t tx = threadIdx.x & 15u, ty = threadIdx.x >> 4;
+    uint32_t kb, ke;
+    k_range(g.K, g.kslices, ks, kb, ke);
     float acc[4][4] = {};
-    for (uint32_t k0 = 0; k0 < g.K; k0 += kGK) {
+    for (uint32_t k0 = kb; k0 < ke; k0 += kGK) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) {
             const uint32_t idx = threadIdx.x + 256 * e;
             const uint32_t mm2 = idx & 63u, kk2 = idx >> 6;
             const uint32_t k = k0 + kk2;
             const uint32_t m = m0 + mm2, n = n0 + mm2;
-            As[kk2][mm2] = (m < g.M && k < g.K) ? A[(uint64_t)k * g.M + m] : 0.f;
+            As[kk2][mm2] = (m < g.M && k < ke) ? A[(uint64_t)k * g.M + m] : 0.f;
             float vb = 0.f;
-            if (n < g.N && k < g.K) {
+            if (n < g.N && k < ke) {
                 const uint64_t row = g.rows ? g.rows[mem * g.rows_mstride + g.rows_offset + k] : k;
                 vb = g.B[row * g.N + n];
             }
@@ -259,22 +275,52 @@ __global__ __launch_bounds__(256) void mlp_gemm_dw_gather_kernel(GemmArgs g)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const uint32_t n = n0 + tx * 4 + j;
-            if (n < g.N) g.C[mem * g.c_mstride + (uint64_t)m * g.N + n] = acc[i][j];
+            if (n < g.N) g.C[mem * g.c_mstride + (uint64_t)ks * g.M * g.N + (uint64_t)m * g.N + n] = acc[i][j];
         }
     }
 }
 
 
-// db[n] = sum_b dZ[b][n] (fixed order per column).
-__global__ void mlp_colsum_kernel(const float* dZ, uint64_t dz_mstride, float* db, uint64_t db_mstride, uint32_t B,
-                                  uint32_t N)
+// db[n] = sum_b dZ[b][n] in two passes with a fixed order: slices of
+// kColSlice rows summed in parallel (grid.y = slice), then the slice sums in
+// slice order.  One thread per column walking all B rows alone leaves a few
+// workgroups waiting out one load latency per row.
+constexpr uint32_t kColSlice = 64;
+
+__global__ void mlp_colsum_slices_kernel(const float* dZ, uint64_t dz_mstride, float* part, uint32_t B, uint32_t N)
+{
+    const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t sl = blockIdx.y, mem = blockIdx.z;
+    if (n >= N) return;
+    const float* p = dZ + mem * dz_mstride;
+    const uint32_t b0 = sl * kColSlice, b1 = min(B, b0 + kColSlice);
+    float s = 0.f;
+#pragma unroll 16
+    for (uint32_t b = b0; b < b1; ++b) s += p[(uint64_t)b * N + n];
+    part[((uint64_t)mem * gridDim.y + sl) * N + n] = s;
+}
+
+// dW = sum of the k-slice partials of a split weight-gradient product, in
+// slice order: part[member][slice][MN] -> out + member * out_mstride.
+__global__ void mlp_ksum_kernel(const float* part, uint32_t kslices, uint64_t MN, float* out, uint64_t out_mstride)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t mem = blockIdx.y;
+    if (i >= MN) return;
+    const float* p = part + (uint64_t)mem * kslices * MN + i;
+    float s = 0.f;
+    for (uint32_t k = 0; k < kslices; ++k) s += p[(uint64_t)k * MN];
+    out[mem * out_mstride + i] = s;
+}
+
+__global__ void mlp_colsum_kernel(const float* part, uint32_t n_slices, float* db, uint64_t db_mstride, uint32_t N)
 {
     const uint32_t n = blockIdx.x * blockDim.x + threadIdx.x;
     const uint32_t mem = blockIdx.y;
     if (n >= N) return;
-    const float* p = dZ + mem * dz_mstride;
+    const float* p = part + (uint64_t)mem * n_slices * N + n;
     float s = 0.f;
-    for (uint32_t b = 0; b < B; ++b) s += p[(uint64_t)b * N + n];
+    for (uint32_t sl = 0; sl < n_slices; ++sl) s += p[(uint64_t)sl * N];
     db[mem * db_mstride + n] = s;
 }
 
@@ -564,13 +610,33 @@ struct TrainBufs {
     float* yn;
     std::vector<float*> Z, Aout, dZ;   // per layer l = 0..L-1, [members][B][w_{l+1}]
     std::vector<uint64_t> stride;      // member stride of layer l buffers
+    float* colpart;                    // [members][B / kColSlice][max width] bias-gradient slice sums
+    float* dwpart;                     // [members][kMaxKSlices][max width^2] weight-gradient slice sums
     float* loss;                       // [members][steps_per_epoch]
 };
+
+static uint32_t max_width(const sde_surrogate* s)
+{
+    return *std::max_element(s->widths.begin(), s->widths.end());
+}
+
+// Slices of the batch sum of a weight-gradient product: enough workgroups to
+// cover the CUs (the M x N tiles alone give few), at least 64 rows each.
+constexpr uint32_t kMaxKSlices = 16;
+static uint32_t dw_kslices(uint32_t M, uint32_t N, uint32_t K, uint32_t members)
+{
+    const uint32_t tiles = ((N + kGT - 1) / kGT) * ((M + kGT - 1) / kGT) * members;
+    uint32_t k = (320 + tiles - 1) / tiles;
+    k = std::min(k, std::max(1u, K / 64));
+    return std::max(1u, std::min(k, kMaxKSlices));
+}
 
 size_t train_bytes(const sde_surrogate* s, uint64_t n, uint32_t B, uint32_t steps)
 {
     size_t e = n * (s->widths[0] + 1);
     for (size_t l = 0; l + 1 < s->widths.size(); ++l) e += 3ull * s->members * B * s->widths[l + 1];
+    e += (size_t)s->members * ((B + kColSlice - 1) / kColSlice) * max_width(s);
+    e += (size_t)s->members * kMaxKSlices * max_width(s) * max_width(s);
     e += (size_t)s->members * steps;
     return e * sizeof(float) + 4096;
 }
@@ -596,13 +662,17 @@ void carve(sde_surrogate* s, uint64_t n, uint32_t B, TrainBufs& t)
         t.dZ[l] = p;
         p += s->members * t.stride[l];
     }
+    t.colpart = p;
+    p += (size_t)s->members * ((B + kColSlice - 1) / kColSlice) * max_width(s);
+    t.dwpart = p;
+    p += (size_t)s->members * kMaxKSlices * max_width(s) * max_width(s);
     t.loss = p;
 }
 
 template <int MODE>
 int launch_gemm(sde_ctx* ctx, const GemmArgs& g, uint32_t members, hipStream_t st)
 {
-    dim3 grid((g.N + kGT - 1) / kGT, (g.M + kGT - 1) / kGT, members);
+    dim3 grid((g.N + kGT - 1) / kGT, (g.M + kGT - 1) / kGT, members * (MODE == kDW ? g.kslices : 1u));
     hipLaunchKernelGGL(mlp_gemm_kernel<MODE>, grid, dim3(256), 0, st, g);
     SDE_HIP(ctx, hipGetLastError());
     return SDE_OK;
@@ -650,16 +720,22 @@ int record_step(sde_surrogate* s, const TrainBufs& t, const uint32_t* rows, uint
         g.a_mstride = t.stride[l];
         g.B = l == 0 ? t.Xn : t.Aout[l - 1];
         g.b_mstride = l == 0 ? 0 : t.stride[l - 1];
-        g.C = s->grads + s->w_off[l];
-        g.c_mstride = s->P;
         g.M = out;
         g.N = in;
         g.K = B;
+        g.kslices = dw_kslices(out, in, B, M);
+        g.C = t.dwpart;
+        g.c_mstride = (uint64_t)g.kslices * out * in;
         if (l > 0) {  // the first layer's inputs are gathered rows: below
             if ((e = launch_gemm<kDW>(ctx, g, M, st))) return e;
+            hipLaunchKernelGGL(mlp_ksum_kernel, dim3((out * in + 255) / 256, M), dim3(256), 0, st, t.dwpart,
+                               g.kslices, (uint64_t)out * in, s->grads + s->w_off[l], s->P);
         }
-        hipLaunchKernelGGL(mlp_colsum_kernel, dim3((out + 255) / 256, M), dim3(256), 0, st, t.dZ[l], t.stride[l],
-                           s->grads + s->b_off[l], s->P, B, out);
+        const uint32_t n_slices = (B + kColSlice - 1) / kColSlice;
+        hipLaunchKernelGGL(mlp_colsum_slices_kernel, dim3((out + 255) / 256, n_slices, M), dim3(256), 0, st, t.dZ[l],
+                           t.stride[l], t.colpart, B, out);
+        hipLaunchKernelGGL(mlp_colsum_kernel, dim3((out + 255) / 256, M), dim3(256), 0, st, t.colpart, n_slices,
+                           s->grads + s->b_off[l], s->P, out);
         SDE_HIP(ctx, hipGetLastError());
         if (l > 0) {
             GemmArgs d{};
@@ -687,13 +763,16 @@ int record_step(sde_surrogate* s, const TrainBufs& t, const uint32_t* rows, uint
         g.rows = rows;
         g.rows_mstride = rows_mstride;
         g.rows_offset = offset;
-        g.C = s->grads + s->w_off[0];
-        g.c_mstride = s->P;
         g.M = s->widths[1];
         g.N = s->widths[0];
         g.K = B;
-        dim3 grid((g.N + kGT - 1) / kGT, (g.M + kGT - 1) / kGT, M);
+        g.kslices = dw_kslices(g.M, g.N, B, M);
+        g.C = t.dwpart;
+        g.c_mstride = (uint64_t)g.kslices * g.M * g.N;
+        dim3 grid((g.N + kGT - 1) / kGT, (g.M + kGT - 1) / kGT, M * g.kslices);
         hipLaunchKernelGGL(mlp_gemm_dw_gather_kernel, grid, dim3(256), 0, st, g);
+        hipLaunchKernelGGL(mlp_ksum_kernel, dim3((g.M * g.N + 255) / 256, M), dim3(256), 0, st, t.dwpart, g.kslices,
+                           (uint64_t)g.M * g.N, s->grads + s->w_off[0], s->P);
         SDE_HIP(ctx, hipGetLastError());
     }
     if (adam) {
