@@ -18,7 +18,11 @@
  * The stepper is the stochastic second-order Runge-Kutta (Heun) scheme of
  * Alg. 2, or Euler-Maruyama.  Noise comes from a counter-based Philox4x32-10
  * generator keyed by (seed, path, step) with Box-Muller Gaussians, so a run
- * can be resumed at any step and reproduced exactly.
+ * can be resumed at any step with the same noise.  A Josephson-junction run
+ * split into calls at a step that is a multiple of 4 and of M
+ * (sample_every) reproduces the single call bit for bit; at other steps
+ * the phase is re-wrapped and the window sum folded at the call boundary,
+ * so the two agree to rounding.
  *
  * Conventions for every call:
  *   - Buffers marked [device] are raw HIP device pointers owned by the
@@ -153,6 +157,18 @@ typedef struct {
 int sde_jj_integrate(sde_ctx* ctx, const sde_jj_point* pts /* [host] */, uint32_t n_pts,
                      const sde_run* run, float* theta, int32_t* winding, float* v, double* acc,
                      double* point_sums, void* hip_stream);
+
+/*
+ * sde_jj_integrate in double precision throughout (the paper's precision
+ * study, Sec. 5 and Fig. 2): the same points, run options, noise streams and
+ * layout, with theta and v as device double arrays and every operation of
+ * the step (drift, noise, Box-Muller) in FP64.  The drive table, the
+ * winding bookkeeping and the reductions are the same as in FP32.
+ * Errors: as sde_jj_integrate.
+ */
+int sde_jj_integrate_f64(sde_ctx* ctx, const sde_jj_point* pts /* [host] */, uint32_t n_pts,
+                         const sde_run* run, double* theta, int32_t* winding, double* v, double* acc,
+                         double* point_sums, void* hip_stream);
 
 /* ---- Kuramoto (Eq. 2, Eq. 3, Alg. 3) ------------------------------------- */
 typedef struct {

@@ -29,7 +29,7 @@ SDE_OBS_MEAN_F32, SDE_OBS_MEAN_F64, SDE_OBS_MEANSQ_F32, SDE_OBS_ORDER = 0, 1, 2,
 SDE_OPT_AUTOTUNE, SDE_OPT_GRAPHS, SDE_OPT_JJ_PPT = 1, 2, 3
 
 EXPORTS = ["sde_create", "sde_destroy", "sde_strerror", "sde_last_error", "sde_check",
-           "sde_jj_integrate", "sde_kuramoto_integrate", "sde_observables", "sde_position_histogram",
+           "sde_jj_integrate", "sde_jj_integrate_f64", "sde_kuramoto_integrate", "sde_observables", "sde_position_histogram",
            "sde_debug_philox", "sde_debug_gauss", "sde_set_option", "sde_set_tune_cache",
            "sde_get_stats", "sde_surrogate_create", "sde_surrogate_destroy",
            "sde_surrogate_param_count", "sde_surrogate_set_params", "sde_surrogate_get_params",
@@ -114,6 +114,9 @@ def lib():
         L.sde_jj_integrate.argtypes = [vp, ctypes.POINTER(sde_jj_point), u32, ctypes.POINTER(sde_run),
                                        vp, vp, vp, vp, vp, vp]
         L.sde_jj_integrate.restype = i32
+        L.sde_jj_integrate_f64.argtypes = [vp, ctypes.POINTER(sde_jj_point), u32, ctypes.POINTER(sde_run),
+                                           vp, vp, vp, vp, vp, vp]
+        L.sde_jj_integrate_f64.restype = i32
         L.sde_kuramoto_integrate.argtypes = [vp, ctypes.POINTER(sde_kuramoto_desc),
                                              ctypes.POINTER(sde_run), vp, vp, vp, vp, vp]
         L.sde_kuramoto_integrate.restype = i32
@@ -270,6 +273,16 @@ def sde_jj_integrate(ctx, pts, run, theta=None, winding=None, v=None, acc=None, 
     return _check(ctx, lib().sde_jj_integrate(ctx, pts, len(pts), ctypes.byref(run), _ptr(theta),
                                               _ptr(winding), _ptr(v), _ptr(acc), _ptr(point_sums),
                                               _stream(stream)))
+
+
+def sde_jj_integrate_f64(ctx, pts, run, theta=None, winding=None, v=None, acc=None, point_sums=None,
+                         stream=None):
+    """As sde_jj_integrate, with float64 theta and v."""
+    if not isinstance(pts, ctypes.Array):
+        pts = make_points(pts)
+    return _check(ctx, lib().sde_jj_integrate_f64(ctx, pts, len(pts), ctypes.byref(run), _ptr(theta),
+                                                  _ptr(winding), _ptr(v), _ptr(acc), _ptr(point_sums),
+                                                  _stream(stream)))
 
 
 def sde_kuramoto_integrate(ctx, desc, run, phi, omega, K=None, r_samples=None, stream=None):

@@ -44,13 +44,16 @@
 
 namespace sde {
 
-struct JJPointDev {
-    float dt, hdt, dtp, hdtp;      // dt, dt/2, dt/L, dt/(2L) with L the coordinate's period
+// Per-point constants in the arithmetic type R of the integration (float:
+// the FP32 path; double: the FP64 path).
+template <typename R>
+struct JJPointT {
+    R dt, hdt, dtp, hdtp;          // dt, dt/2, dt/L, dt/(2L) with L the coordinate's period
                                    // (2 pi for phi, 1 for x): theta' = v / L
-    float gim, kv, a_im, f_im;     // gamma/m, (force amplitude)/m, a/m, f/m with force
+    R gim, kv, a_im, f_im;         // gamma/m, (force amplitude)/m, a/m, f/m with force
                                    // amplitude 1 (sin phi) or 2 pi (2 pi cos 2 pi x);
                                    // overdamped: 1/gamma for 1/m
-    float c2, sig_v;               // c2 = -2 ln2 sigma^2 with sigma the noise increment per
+    R c2, sig_v;                   // c2 = -2 ln2 sigma^2 with sigma the noise increment per
                                    // Gaussian: on v (inertial) or on theta in periods
                                    // (overdamped); sig_v = L / dt turns the latter into
                                    // a velocity
@@ -59,21 +62,22 @@ struct JJPointDev {
     double inv_W;
     uint32_t chunk_first, n_chunks;
 };
-static_assert(sizeof(JJPointDev) % 8 == 0, "layout");
+using JJPointDev = JJPointT<float>;
+static_assert(sizeof(JJPointT<float>) % 8 == 0 && sizeof(JJPointT<double>) % 8 == 0, "layout");
 
 struct JJItem {
     uint32_t point, chunk;
 };
 
 struct JJArgs {
-    const JJPointDev* pts;
+    const void* pts;      // JJPointT<R>[]
     const JJItem* items;
-    const float* lut;
+    const void* lut;      // R[]
     uint32_t* queue;
     int* flag;
-    float* theta;
+    void* theta;          // R[]
     int32_t* winding;
-    float* v;
+    void* v;              // R[]
     double* acc;
     double* partials;
     uint64_t step0;
@@ -86,57 +90,89 @@ struct JJArgs {
 // uniform drive terms (a cos(w t) + f)/m at t_n and t_{n+1} (the second
 // drift evaluation of Alg. 2 is taken at t + dt), ns the noise increments.
 // The potential's shape at theta (in periods): sin(2 pi theta) for the
-// -sin phi force, cos(2 pi theta) for -V'(x) = -2 pi cos(2 pi x).
+// -sin phi force, cos(2 pi theta) for -V'(x) = -2 pi cos(2 pi x).  FP32: the
+// hardware v_sin/v_cos, which take revolutions; FP64: sinpi/cospi.
 template <bool COSF>
 __device__ __forceinline__ float jj_shape(float theta)
 {
     return COSF ? cos_rev(theta) : sin_rev(theta);
 }
+template <bool COSF>
+__device__ __forceinline__ double jj_shape(double theta)
+{
+    return COSF ? cospi(2.0 * theta) : sinpi(2.0 * theta);
+}
 
-template <int PPT, int SCHEME, bool INERTIAL, bool COSF, bool ACC>
-__device__ __forceinline__ void jj_step(const JJPointDev& P, float e0, float e1, const float (&ns)[PPT],
-                                        float (&th)[PPT], float (&vv)[PPT], float (&af)[PPT])
+__device__ __forceinline__ float fm(float a, float b, float c) { return fmaf(a, b, c); }
+__device__ __forceinline__ double fm(double a, double b, double c) { return fma(a, b, c); }
+
+// sigma * (the four Gaussians of Philox block c), c2 = -2 ln2 sigma^2.
+__device__ __forceinline__ void jj_gauss4(U4 c, uint32_t k0, uint32_t k1, float c2, float g[4])
+{
+    gauss4_scaled(c, k0, k1, c2, g);
+}
+__device__ __forceinline__ void jj_gauss4(U4 c, uint32_t k0, uint32_t k1, double c2, double g[4])
+{
+    const U4 x = philox4x32_10(c, k0, k1);
+    const uint32_t w[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+        const double u1 = (double)((w[2 * p] >> 8) + 1u) * 0x1p-24;
+        const double u2 = (double)(w[2 * p + 1] >> 8) * 0x1p-24;
+        const double rho = sqrt(c2 * log2(u1));
+        double sn, cs;
+        sincospi(2.0 * u2, &sn, &cs);
+        g[2 * p] = rho * cs;
+        g[2 * p + 1] = rho * sn;
+    }
+}
+
+template <typename R, int PPT, int SCHEME, bool INERTIAL, bool COSF, bool ACC>
+__device__ __forceinline__ void jj_step(const JJPointT<R>& P, R e0, R e1, const R (&ns)[PPT], R (&th)[PPT],
+                                        R (&vv)[PPT], R (&af)[PPT])
 {
 #pragma unroll
     for (int k = 0; k < PPT; ++k) {
         if (INERTIAL) {
             // X = (coordinate, v), F = (v, (force - gamma v + a cos wt + f)/m), noise on v
-            const float F1 = fmaf(-P.kv, jj_shape<COSF>(th[k]), fmaf(-P.gim, vv[k], e0));
+            const R F1 = fm(-P.kv, jj_shape<COSF>(th[k]), fm(-P.gim, vv[k], e0));
             if (SCHEME == SDE_HEUN) {
-                const float vt = fmaf(P.dt, F1, vv[k]) + ns[k];
-                const float tt = fmaf(P.dtp, vv[k], th[k]);
-                const float F2 = fmaf(-P.kv, jj_shape<COSF>(tt), fmaf(-P.gim, vt, e1));
-                th[k] = fmaf(P.hdtp, vv[k] + vt, th[k]);
-                vv[k] = fmaf(P.hdt, F1 + F2, vv[k]) + ns[k];
+                const R vt = fm(P.dt, F1, vv[k]) + ns[k];
+                const R tt = fm(P.dtp, vv[k], th[k]);
+                const R F2 = fm(-P.kv, jj_shape<COSF>(tt), fm(-P.gim, vt, e1));
+                th[k] = fm(P.hdtp, vv[k] + vt, th[k]);
+                vv[k] = fm(P.hdt, F1 + F2, vv[k]) + ns[k];
             } else {
-                th[k] = fmaf(P.dtp, vv[k], th[k]);
-                vv[k] = fmaf(P.dt, F1, vv[k]) + ns[k];
+                th[k] = fm(P.dtp, vv[k], th[k]);
+                vv[k] = fm(P.dt, F1, vv[k]) + ns[k];
             }
         } else {
             // overdamped: coordinate' = (force + a cos wt + f)/gamma + noise on
             // the coordinate; v reports the step's mean velocity (change / dt)
-            const float F1 = fmaf(-P.kv, jj_shape<COSF>(th[k]), e0);
+            const R F1 = fm(-P.kv, jj_shape<COSF>(th[k]), e0);
             if (SCHEME == SDE_HEUN) {
-                const float tt = fmaf(P.dtp, F1, th[k]) + ns[k];
-                const float F2 = fmaf(-P.kv, jj_shape<COSF>(tt), e1);
-                th[k] = fmaf(P.hdtp, F1 + F2, th[k]) + ns[k];
-                vv[k] = fmaf(0.5f, F1 + F2, P.sig_v * ns[k]);
+                const R tt = fm(P.dtp, F1, th[k]) + ns[k];
+                const R F2 = fm(-P.kv, jj_shape<COSF>(tt), e1);
+                th[k] = fm(P.hdtp, F1 + F2, th[k]) + ns[k];
+                vv[k] = fm(R(0.5), F1 + F2, P.sig_v * ns[k]);
             } else {
-                th[k] = fmaf(P.dtp, F1, th[k]) + ns[k];
-                vv[k] = fmaf(P.sig_v, ns[k], F1);
+                th[k] = fm(P.dtp, F1, th[k]) + ns[k];
+                vv[k] = fm(P.sig_v, ns[k], F1);
             }
         }
         if (ACC) af[k] += vv[k];
     }
 }
 
-template <int PPT, int SCHEME, bool INERTIAL, bool COSF>
+template <typename R, int PPT, int SCHEME, bool INERTIAL, bool COSF>
 __device__ __forceinline__ void jj_item(const JJArgs& A, uint32_t q, uint32_t chunk)
 {
-    const JJPointDev P = load_uniform(A.pts + q);
+    const JJPointT<R> P = load_uniform(static_cast<const JJPointT<R>*>(A.pts) + q);
     const uint32_t lane = threadIdx.x & (kWave - 1);
+    R* theta = static_cast<R*>(A.theta);
+    R* vel = static_cast<R*>(A.v);
 
-    float th[PPT], vv[PPT], af[PPT];
+    R th[PPT], vv[PPT], af[PPT];
     int32_t wd[PPT];
     double ad[PPT];
     uint32_t pid[PPT];
@@ -147,21 +183,21 @@ __device__ __forceinline__ void jj_item(const JJArgs& A, uint32_t q, uint32_t ch
         live[k] = pid[k] < P.n_paths;
         const uint64_t gi = P.path_first + pid[k];
         if (A.init_from_state) {
-            th[k] = live[k] ? A.theta[gi] : 0.f;
-            vv[k] = live[k] ? A.v[gi] : 0.f;
+            th[k] = live[k] ? theta[gi] : R(0);
+            vv[k] = live[k] ? vel[gi] : R(0);
             wd[k] = live[k] ? A.winding[gi] : 0;
             ad[k] = live[k] ? A.acc[gi] : 0.0;
         } else {
             const U4 x = philox4x32_10(U4{0u, pid[k], q, (uint32_t)SDE_TAG_INIT}, A.key0, A.key1);
-            th[k] = (float)(x.x >> 8) * 0x1p-24f;
-            vv[k] = -2.0f + 4.0f * ((float)(x.y >> 8) * 0x1p-24f);
+            th[k] = (R)(x.x >> 8) * R(0x1p-24);
+            vv[k] = R(-2) + R(4) * ((R)(x.y >> 8) * R(0x1p-24));
             wd[k] = 0;
             ad[k] = 0.0;
         }
-        af[k] = 0.f;
+        af[k] = R(0);
     }
 
-    const float* lut = A.lut + P.lut_off;  // cos(2 pi k / S) for k < S + 8
+    const R* lut = static_cast<const R*>(A.lut) + P.lut_off;  // cos(2 pi k / S) for k < S + 8
     const uint64_t n_end = A.step0 + P.n_steps;
     uint64_t n = A.step0;
     uint32_t kk = (uint32_t)(n % P.S);        // drive phase index of step n
@@ -172,7 +208,7 @@ __device__ __forceinline__ void jj_item(const JJArgs& A, uint32_t q, uint32_t ch
 #pragma unroll
             for (int k = 0; k < PPT; ++k) {
                 ad[k] += (double)af[k];
-                af[k] = 0.f;
+                af[k] = R(0);
             }
         }
         mc = (mc + 1 == A.M) ? 0u : mc + 1;
@@ -183,42 +219,42 @@ __device__ __forceinline__ void jj_item(const JJArgs& A, uint32_t q, uint32_t ch
         const uint64_t left = n_end - n;
         const uint32_t jn = left >= (uint64_t)(4u - j0) ? 4u : j0 + (uint32_t)left;
         // sigma * Gaussians of steps 4b .. 4b+3 (b = n >> 2) of each path
-        float g[PPT][4];
+        R g[PPT][4];
 #pragma unroll
         for (int k = 0; k < PPT; ++k)
-            gauss4_scaled(U4{(uint32_t)(n >> 2), pid[k], q, (uint32_t)SDE_TAG_NOISE}, A.key0, A.key1, P.c2, g[k]);
+            jj_gauss4(U4{(uint32_t)(n >> 2), pid[k], q, (uint32_t)SDE_TAG_NOISE}, A.key0, A.key1, P.c2, g[k]);
         if (j0 == 0 && jn == 4) {
-            float e[5];
+            R e[5];
 #pragma unroll
-            for (int j = 0; j < 5; ++j) e[j] = fmaf(P.a_im, load_uniform(lut + kk + j), P.f_im);
+            for (int j = 0; j < 5; ++j) e[j] = fm(P.a_im, load_uniform(lut + kk + j), P.f_im);
             if (n >= P.n_transient) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    float ns[PPT];
+                    R ns[PPT];
 #pragma unroll
                     for (int k = 0; k < PPT; ++k) ns[k] = g[k][j];
-                    jj_step<PPT, SCHEME, INERTIAL, COSF, true>(P, e[j], e[j + 1], ns, th, vv, af);
+                    jj_step<R, PPT, SCHEME, INERTIAL, COSF, true>(P, e[j], e[j + 1], ns, th, vv, af);
                     fold_tick();
                 }
             } else if (n + 4 <= P.n_transient) {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    float ns[PPT];
+                    R ns[PPT];
 #pragma unroll
                     for (int k = 0; k < PPT; ++k) ns[k] = g[k][j];
-                    jj_step<PPT, SCHEME, INERTIAL, COSF, false>(P, e[j], e[j + 1], ns, th, vv, af);
+                    jj_step<R, PPT, SCHEME, INERTIAL, COSF, false>(P, e[j], e[j + 1], ns, th, vv, af);
                     fold_tick();
                 }
             } else {
 #pragma unroll
                 for (int j = 0; j < 4; ++j) {
-                    float ns[PPT];
+                    R ns[PPT];
 #pragma unroll
                     for (int k = 0; k < PPT; ++k) ns[k] = g[k][j];
                     if (n + j >= P.n_transient)
-                        jj_step<PPT, SCHEME, INERTIAL, COSF, true>(P, e[j], e[j + 1], ns, th, vv, af);
+                        jj_step<R, PPT, SCHEME, INERTIAL, COSF, true>(P, e[j], e[j + 1], ns, th, vv, af);
                     else
-                        jj_step<PPT, SCHEME, INERTIAL, COSF, false>(P, e[j], e[j + 1], ns, th, vv, af);
+                        jj_step<R, PPT, SCHEME, INERTIAL, COSF, false>(P, e[j], e[j + 1], ns, th, vv, af);
                     fold_tick();
                 }
             }
@@ -228,16 +264,16 @@ __device__ __forceinline__ void jj_item(const JJArgs& A, uint32_t q, uint32_t ch
         } else {
             // partial block (first or last of the call): one step at a time
             for (uint32_t j = j0; j < jn; ++j) {
-                float ns[PPT];
+                R ns[PPT];
 #pragma unroll
                 for (int k = 0; k < PPT; ++k)
                     ns[k] = j == 0 ? g[k][0] : j == 1 ? g[k][1] : j == 2 ? g[k][2] : g[k][3];
-                const float ea = fmaf(P.a_im, load_uniform(lut + kk), P.f_im);
-                const float eb = fmaf(P.a_im, load_uniform(lut + kk + 1), P.f_im);
+                const R ea = fm(P.a_im, load_uniform(lut + kk), P.f_im);
+                const R eb = fm(P.a_im, load_uniform(lut + kk + 1), P.f_im);
                 if (n >= P.n_transient)
-                    jj_step<PPT, SCHEME, INERTIAL, COSF, true>(P, ea, eb, ns, th, vv, af);
+                    jj_step<R, PPT, SCHEME, INERTIAL, COSF, true>(P, ea, eb, ns, th, vv, af);
                 else
-                    jj_step<PPT, SCHEME, INERTIAL, COSF, false>(P, ea, eb, ns, th, vv, af);
+                    jj_step<R, PPT, SCHEME, INERTIAL, COSF, false>(P, ea, eb, ns, th, vv, af);
                 fold_tick();
                 ++n;
                 kk = (kk + 1 == P.S) ? 0u : kk + 1;
@@ -246,7 +282,7 @@ __device__ __forceinline__ void jj_item(const JJArgs& A, uint32_t q, uint32_t ch
         // keep theta in [0, 1): move whole revolutions into the winding count
 #pragma unroll
         for (int k = 0; k < PPT; ++k) {
-            const float fl = floorf(th[k]);
+            const R fl = floor(th[k]);
             th[k] -= fl;
             wd[k] += (int32_t)fl;
         }
@@ -259,9 +295,9 @@ __device__ __forceinline__ void jj_item(const JJArgs& A, uint32_t q, uint32_t ch
         ad[k] += (double)af[k];
         if (live[k]) {
             const uint64_t gi = P.path_first + pid[k];
-            if (A.theta) A.theta[gi] = th[k];
+            if (theta) theta[gi] = th[k];
             if (A.winding) A.winding[gi] = wd[k];
-            if (A.v) A.v[gi] = vv[k];
+            if (vel) vel[gi] = vv[k];
             if (A.acc) A.acc[gi] = ad[k];
             const double vb = ad[k] * P.inv_W;
             s1 += vb;
@@ -278,7 +314,7 @@ __device__ __forceinline__ void jj_item(const JJArgs& A, uint32_t q, uint32_t ch
     if (__ballot(bad) != 0 && lane == 0) atomicOr(A.flag, 1);
 }
 
-template <int PPT, int SCHEME, bool INERTIAL, bool COSF>
+template <typename R, int PPT, int SCHEME, bool INERTIAL, bool COSF>
 __global__ __launch_bounds__(256) void jj_persistent_kernel(JJArgs A)
 {
     const uint32_t lane = threadIdx.x & (kWave - 1);
@@ -288,13 +324,13 @@ __global__ __launch_bounds__(256) void jj_persistent_kernel(JJArgs A)
         item = uniform_u32(__shfl(item, 0, kWave));
         if (item >= A.n_items) break;
         const JJItem it = load_uniform(A.items + item);
-        jj_item<PPT, SCHEME, INERTIAL, COSF>(A, it.point, it.chunk);
+        jj_item<R, PPT, SCHEME, INERTIAL, COSF>(A, it.point, it.chunk);
     }
 }
 
 // Stage 2: per point, the chunk partials in chunk order.
-__global__ void jj_point_sums_kernel(const JJPointDev* pts, uint32_t n_pts, const double* partials,
-                                     double* out)
+template <typename R>
+__global__ void jj_point_sums_kernel(const JJPointT<R>* pts, uint32_t n_pts, const double* partials, double* out)
 {
     const uint32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= n_pts) return;
@@ -337,30 +373,34 @@ __global__ void gauss_dump_kernel(uint32_t k0, uint32_t k1, uint32_t tag, uint32
 
 using JJKernel = void (*)(JJArgs);
 
-template <bool INERTIAL, bool COSF>
+// Paths per lane: 1, 2 or 4 in FP32; FP64 holds twice the registers per
+// path and stops at 2.
+template <typename R, bool INERTIAL, bool COSF>
 static JJKernel pick_kernel_t(int ppt, int scheme)
 {
+    constexpr bool f32 = sizeof(R) == 4;
     if (scheme == SDE_HEUN) {
-        if (ppt == 1) return jj_persistent_kernel<1, SDE_HEUN, INERTIAL, COSF>;
-        if (ppt == 4) return jj_persistent_kernel<4, SDE_HEUN, INERTIAL, COSF>;
-        return jj_persistent_kernel<2, SDE_HEUN, INERTIAL, COSF>;
+        if (ppt == 1) return jj_persistent_kernel<R, 1, SDE_HEUN, INERTIAL, COSF>;
+        if (f32 && ppt == 4) return jj_persistent_kernel<R, f32 ? 4 : 2, SDE_HEUN, INERTIAL, COSF>;
+        return jj_persistent_kernel<R, 2, SDE_HEUN, INERTIAL, COSF>;
     }
-    if (ppt == 1) return jj_persistent_kernel<1, SDE_EULER, INERTIAL, COSF>;
-    if (ppt == 4) return jj_persistent_kernel<4, SDE_EULER, INERTIAL, COSF>;
-    return jj_persistent_kernel<2, SDE_EULER, INERTIAL, COSF>;
+    if (ppt == 1) return jj_persistent_kernel<R, 1, SDE_EULER, INERTIAL, COSF>;
+    if (f32 && ppt == 4) return jj_persistent_kernel<R, f32 ? 4 : 2, SDE_EULER, INERTIAL, COSF>;
+    return jj_persistent_kernel<R, 2, SDE_EULER, INERTIAL, COSF>;
 }
 
 // Point kinds, one persistent launch each: bit 0 = overdamped, bit 1 = the
 // sin(2 pi x) potential.
 constexpr int kJJKinds = 4;
 
+template <typename R>
 static JJKernel pick_kernel(int kind, int ppt, int scheme)
 {
     switch (kind) {
-    case 0: return pick_kernel_t<true, false>(ppt, scheme);
-    case 1: return pick_kernel_t<false, false>(ppt, scheme);
-    case 2: return pick_kernel_t<true, true>(ppt, scheme);
-    default: return pick_kernel_t<false, true>(ppt, scheme);
+    case 0: return pick_kernel_t<R, true, false>(ppt, scheme);
+    case 1: return pick_kernel_t<R, false, false>(ppt, scheme);
+    case 2: return pick_kernel_t<R, true, true>(ppt, scheme);
+    default: return pick_kernel_t<R, false, true>(ppt, scheme);
     }
 }
 
@@ -372,20 +412,22 @@ static bool finite_point(const sde_jj_point& p)
 
 // Work items of one paths-per-lane choice: chunk layout per point and the
 // queue of each point kind (longest first within a kind).
+template <typename R>
 struct JJPlan {
-    std::vector<JJPointDev> pts;
+    std::vector<JJPointT<R>> pts;
     std::vector<JJItem> items;
     uint32_t kind_begin[kJJKinds + 1] = {};  // items of kind k: [kind_begin[k], kind_begin[k + 1])
     uint32_t n_chunks = 0;
 };
 
-static void plan_items(std::vector<JJPointDev>& P, const std::vector<int>& kinds, int ppt, JJPlan& out)
+template <typename R>
+static void plan_items(std::vector<JJPointT<R>>& P, const std::vector<int>& kinds, int ppt, JJPlan<R>& out)
 {
     const uint32_t chunk_paths = (uint32_t)(kWave * ppt);
     std::vector<JJItem> it[kJJKinds];
     uint32_t chunk_first = 0;
     for (uint32_t q = 0; q < (uint32_t)P.size(); ++q) {
-        JJPointDev& d = P[q];
+        JJPointT<R>& d = P[q];
         d.n_chunks = (d.n_paths + chunk_paths - 1) / chunk_paths;
         d.chunk_first = chunk_first;
         for (uint32_t c = 0; c < d.n_chunks; ++c) it[kinds[q]].push_back(JJItem{q, c});
@@ -413,13 +455,14 @@ struct JJLaunch {
     double* point_sums;
 };
 
+template <typename R>
 static int jj_grids(sde_ctx* ctx, JJLaunch& L)
 {
     for (int kind = 0; kind < kJJKinds; ++kind) {
         const uint32_t count = L.kind_begin[kind + 1] - L.kind_begin[kind];
         L.grid[kind] = 0;
         if (!count) continue;
-        JJKernel kern = pick_kernel(kind, L.ppt, L.scheme);
+        JJKernel kern = pick_kernel<R>(kind, L.ppt, L.scheme);
         int per_cu = 0;
         SDE_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(kern), 256, 0));
         if (per_cu < 1) per_cu = 1;
@@ -431,6 +474,7 @@ static int jj_grids(sde_ctx* ctx, JJLaunch& L)
 
 // The launch sequence of one call: reset the queues, the persistent kernel
 // of each point kind present, the per-point sums.
+template <typename R>
 static int jj_record(sde_ctx* ctx, const JJLaunch& L, hipStream_t s)
 {
     int st = zero_counters(ctx, 0, kJJKinds, s);
@@ -442,34 +486,36 @@ static int jj_record(sde_ctx* ctx, const JJLaunch& L, hipStream_t s)
         A.items = all + L.kind_begin[kind];
         A.n_items = L.kind_begin[kind + 1] - L.kind_begin[kind];
         A.queue = ctx->counters + kind;
-        JJKernel kern = pick_kernel(kind, L.ppt, L.scheme);
+        JJKernel kern = pick_kernel<R>(kind, L.ppt, L.scheme);
         hipLaunchKernelGGL(kern, dim3(L.grid[kind]), dim3(256), 0, s, A);
         SDE_HIP(ctx, hipGetLastError());
     }
     if (L.point_sums) {
-        hipLaunchKernelGGL(jj_point_sums_kernel, dim3((L.n_pts + 255) / 256), dim3(256), 0, s, L.A.pts, L.n_pts,
-                           L.A.partials, L.point_sums);
+        hipLaunchKernelGGL(jj_point_sums_kernel<R>, dim3((L.n_pts + 255) / 256), dim3(256), 0, s,
+                           static_cast<const JJPointT<R>*>(L.A.pts), L.n_pts, L.A.partials, L.point_sums);
         SDE_HIP(ctx, hipGetLastError());
     }
     return SDE_OK;
 }
 
-static int jj_upload_plan(sde_ctx* ctx, const JJPlan& plan, hipStream_t stream, JJLaunch& L)
+template <typename R>
+static int jj_upload_plan(sde_ctx* ctx, const JJPlan<R>& plan, hipStream_t stream, JJLaunch& L)
 {
     int st;
-    if ((st = upload(ctx, kSlotJJPoints, 0, plan.pts.data(), plan.pts.size() * sizeof(JJPointDev), stream))) return st;
+    if ((st = upload(ctx, kSlotJJPoints, 0, plan.pts.data(), plan.pts.size() * sizeof(JJPointT<R>), stream)))
+        return st;
     if ((st = upload(ctx, kSlotJJItems, 1, plan.items.data(), plan.items.size() * sizeof(JJItem), stream))) return st;
     void* partials = nullptr;
     if ((st = ensure_ws(ctx, kSlotJJPartials, (size_t)std::max(plan.n_chunks, 1u) * 2 * sizeof(double), &partials)))
         return st;
     if ((st = ensure_counters(ctx, kJJKinds))) return st;
-    L.A.pts = static_cast<const JJPointDev*>(ctx->ws[kSlotJJPoints].ptr);
+    L.A.pts = ctx->ws[kSlotJJPoints].ptr;
     L.A.items = static_cast<const JJItem*>(ctx->ws[kSlotJJItems].ptr);
     L.A.partials = static_cast<double*>(partials);
     std::copy(plan.kind_begin, plan.kind_begin + kJJKinds + 1, L.kind_begin);
     L.n_items = (uint32_t)plan.items.size();
     L.n_pts = (uint32_t)plan.pts.size();
-    return jj_grids(ctx, L);
+    return jj_grids<R>(ctx, L);
 }
 
 static int ilog2u64(uint64_t x)
@@ -485,10 +531,11 @@ static int ilog2u64(uint64_t x)
 // Times the candidate paths-per-lane choices on a short slice of the call
 // (same points, at most 2048 steps, no per-path outputs) and returns the
 // fastest.  Nothing the caller passed is written.
-static int jj_tune(sde_ctx* ctx, const std::vector<JJPointDev>& P0, const std::vector<int>& kinds,
+template <typename R>
+static int jj_tune(sde_ctx* ctx, const std::vector<JJPointT<R>>& P0, const std::vector<int>& kinds,
                    const JJLaunch& base, hipStream_t stream, int* best_ppt)
 {
-    std::vector<JJPointDev> P = P0;
+    std::vector<JJPointT<R>> P = P0;
     uint64_t work = 0;
     for (auto& d : P) {
         d.n_steps = std::min<uint64_t>(d.n_steps, 2048);
@@ -503,8 +550,9 @@ static int jj_tune(sde_ctx* ctx, const std::vector<JJPointDev>& P0, const std::v
     SDE_HIP(ctx, hipEventCreate(&e1));
     double best = 1e300;
     int st = SDE_OK;
-    for (int ppt : {1, 2, 4}) {
-        JJPlan plan;
+    const std::vector<int> cands = sizeof(R) == 4 ? std::vector<int>{1, 2, 4} : std::vector<int>{1, 2};
+    for (int ppt : cands) {
+        JJPlan<R> plan;
         plan_items(P, kinds, ppt, plan);
         JJLaunch L = base;
         L.ppt = ppt;
@@ -519,7 +567,7 @@ static int jj_tune(sde_ctx* ctx, const std::vector<JJPointDev>& P0, const std::v
         float ms = 0.f;
         for (int rep = 0; rep < 2; ++rep) {  // first launch loads the code object
             if ((st = hipEventRecord(e0, stream) == hipSuccess ? SDE_OK : SDE_ERR_DEVICE)) break;
-            if ((st = jj_record(ctx, L, stream))) break;
+            if ((st = jj_record<R>(ctx, L, stream))) break;
             if ((st = hipEventRecord(e1, stream) == hipSuccess ? SDE_OK : SDE_ERR_DEVICE)) break;
             if (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
                 st = SDE_ERR_DEVICE;
@@ -538,9 +586,9 @@ static int jj_tune(sde_ctx* ctx, const std::vector<JJPointDev>& P0, const std::v
     return st;
 }
 
-int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run,
-                      float* theta, int32_t* winding, float* v, double* acc, double* point_sums,
-                      hipStream_t stream)
+template <typename R>
+static int jj_integrate_t(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run, R* theta,
+                          int32_t* winding, R* v, double* acc, double* point_sums, hipStream_t stream)
 {
     ctx->last = sde_stats{};
     if (!pts || !run || n_pts == 0) return fail(ctx, SDE_ERR_INVALID, "null points/run or n_pts = 0");
@@ -550,15 +598,15 @@ int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, con
         return fail(ctx, SDE_ERR_INVALID, "unknown init %d", run->init);
     if (run->init == SDE_INIT_FROM_STATE && (!theta || !winding || !v || !acc))
         return fail(ctx, SDE_ERR_INVALID, "SDE_INIT_FROM_STATE needs theta, winding, v and acc");
-    if (!aligned(theta, 4) || !aligned(winding, 4) || !aligned(v, 4) || !aligned(acc, 8) ||
+    if (!aligned(theta, sizeof(R)) || !aligned(winding, 4) || !aligned(v, sizeof(R)) || !aligned(acc, 8) ||
         !aligned(point_sums, 8))
         return fail(ctx, SDE_ERR_INVALID, "misaligned device pointer");
     const uint32_t M = run->sample_every ? run->sample_every : 100u;
 
-    std::vector<JJPointDev> P(n_pts);
+    std::vector<JJPointT<R>> P(n_pts);
     std::vector<int> kinds(n_pts);
     std::map<uint32_t, uint32_t> lut_of;  // S -> offset
-    std::vector<float> lut;
+    std::vector<R> lut;
     uint64_t path_first = 0, max_steps = 0;
     unsigned kinds_present = 0;
     for (uint32_t q = 0; q < n_pts; ++q) {
@@ -577,29 +625,29 @@ int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, con
         const double L = sin2pi ? 1.0 : 2.0 * M_PI;   // period of the coordinate
         const double amp = sin2pi ? 2.0 * M_PI : 1.0;  // amplitude of the potential force
         const double dt = 2.0 * M_PI / (p.omega * (double)p.steps_per_period);
-        JJPointDev& d = P[q];
-        d.dt = (float)dt;
-        d.hdt = (float)(0.5 * dt);
-        d.dtp = (float)(dt / L);
-        d.hdtp = (float)(0.5 * dt / L);
+        JJPointT<R>& d = P[q];
+        d.dt = (R)dt;
+        d.hdt = (R)(0.5 * dt);
+        d.dtp = (R)(dt / L);
+        d.hdtp = (R)(0.5 * dt / L);
         d.inertial = p.m > 0 ? 1u : 0u;
         if (d.inertial) {
-            d.kv = (float)(amp / p.m);
-            d.gim = (float)(p.gamma / p.m);
-            d.a_im = (float)(p.a / p.m);
-            d.f_im = (float)(p.f / p.m);
+            d.kv = (R)(amp / p.m);
+            d.gim = (R)(p.gamma / p.m);
+            d.a_im = (R)(p.a / p.m);
+            d.f_im = (R)(p.f / p.m);
             const double sig = std::sqrt(2.0 * p.gamma * p.D * dt) / p.m;
-            d.c2 = (float)(-2.0 * M_LN2 * sig * sig);
-            d.sig_v = 0.f;
+            d.c2 = (R)(-2.0 * M_LN2 * sig * sig);
+            d.sig_v = (R)0;
         } else {
             const double s = std::sqrt(2.0 * p.D * dt / p.gamma);
-            d.kv = (float)(amp / p.gamma);
-            d.gim = 0.f;
-            d.a_im = (float)(p.a / p.gamma);
-            d.f_im = (float)(p.f / p.gamma);
+            d.kv = (R)(amp / p.gamma);
+            d.gim = (R)0;
+            d.a_im = (R)(p.a / p.gamma);
+            d.f_im = (R)(p.f / p.gamma);
             const double sig = s / L;
-            d.c2 = (float)(-2.0 * M_LN2 * sig * sig);
-            d.sig_v = (float)(L / dt);
+            d.c2 = (R)(-2.0 * M_LN2 * sig * sig);
+            d.sig_v = (R)(L / dt);
         }
         kinds[q] = (d.inertial ? 0 : 1) + (sin2pi ? 2 : 0);
         kinds_present |= 1u << kinds[q];
@@ -608,7 +656,7 @@ int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, con
         if (it == lut_of.end()) {
             const uint32_t off = (uint32_t)lut.size();
             for (uint32_t k = 0; k < d.S + 8; ++k)
-                lut.push_back((float)std::cos(2.0 * M_PI * (double)(k % d.S) / (double)d.S));
+                lut.push_back((R)std::cos(2.0 * M_PI * (double)(k % d.S) / (double)d.S));
             it = lut_of.emplace(d.S, off).first;
         }
         d.lut_off = it->second;
@@ -625,11 +673,11 @@ int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, con
     if (path_first / kWave > 0xffffffffull) return fail(ctx, SDE_ERR_INVALID, "too many paths in one call");
 
     int st;
-    if ((st = upload(ctx, kSlotJJLut, 2, lut.data(), lut.size() * sizeof(float), stream))) return st;
+    if ((st = upload(ctx, kSlotJJLut, 2, lut.data(), lut.size() * sizeof(R), stream))) return st;
     JJLaunch L;
     L.scheme = run->scheme;
     L.point_sums = point_sums;
-    L.A.lut = static_cast<const float*>(ctx->ws[kSlotJJLut].ptr);
+    L.A.lut = ctx->ws[kSlotJJLut].ptr;
     L.A.flag = ctx->flag;
     L.A.theta = theta;
     L.A.winding = winding;
@@ -640,18 +688,20 @@ int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, con
     L.A.key1 = (uint32_t)(run->seed >> 32);
     L.A.M = M;
     L.A.init_from_state = run->init == SDE_INIT_FROM_STATE;
+    const char* prec = sizeof(R) == 4 ? "f32" : "f64";
 
     // paths per lane: forced, cached, or tuned on this call's shape class
     int ppt = ctx->jj_ppt;
+    if (sizeof(R) == 8 && ppt == 4) ppt = 2;
     if (!ppt) {
         char key[160];
-        snprintf(key, sizeof key, "jj|%s|scheme%d|kinds%x|paths2^%d|steps2^%d", ctx->arch.c_str(), run->scheme,
-                 kinds_present, ilog2u64(path_first), ilog2u64(std::max<uint64_t>(max_steps, 1)));
+        snprintf(key, sizeof key, "jj|%s|%s|scheme%d|kinds%x|paths2^%d|steps2^%d", ctx->arch.c_str(), prec,
+                 run->scheme, kinds_present, ilog2u64(path_first), ilog2u64(std::max<uint64_t>(max_steps, 1)));
         if (!tune_lookup(ctx, key, &ppt)) {
             ppt = 2;
             if (ctx->autotune) {
                 const auto t0 = std::chrono::steady_clock::now();
-                if ((st = jj_tune(ctx, P, kinds, L, stream, &ppt))) return st;
+                if ((st = jj_tune<R>(ctx, P, kinds, L, stream, &ppt))) return st;
                 ctx->last.tuned = 1;
                 ctx->last.tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
                 tune_store(ctx, key, ppt);
@@ -659,7 +709,7 @@ int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, con
         }
     }
     L.ppt = ppt;
-    JJPlan plan;
+    JJPlan<R> plan;
     plan_items(P, kinds, ppt, plan);
     if ((st = jj_upload_plan(ctx, plan, stream, L))) return st;
     ctx->last.jj_paths_per_lane = ppt;
@@ -667,17 +717,31 @@ int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, con
 
     // everything baked into the recorded launches
     char key[512];
-    snprintf(key, sizeof key, "jj|%p|%p|%p|%p|%p|%p|%p|%llu|%u|%u|%u|%d|%d|%d|%u|%u", (void*)L.A.pts,
-             (void*)L.A.items, (void*)L.A.lut, (void*)theta, (void*)winding, (void*)v, (void*)acc,
+    snprintf(key, sizeof key, "jj|%s|%p|%p|%p|%p|%p|%p|%p|%llu|%u|%u|%u|%d|%d|%d|%u|%u", prec, L.A.pts,
+             (const void*)L.A.items, L.A.lut, (void*)theta, (void*)winding, (void*)v, (void*)acc,
              (unsigned long long)run->step0, L.A.key0, L.A.key1, M, L.A.init_from_state, ppt, run->scheme,
              L.n_items, L.n_pts);
     std::string k = key;
     for (int kind = 0; kind < kJJKinds; ++kind)
         k += "|" + std::to_string(L.kind_begin[kind + 1]) + "/" + std::to_string(L.grid[kind]);
     k += point_sums ? "|ps" + std::to_string((uintptr_t)point_sums) : "|ps0";
-    if ((st = run_recorded(ctx, k, stream, [&](hipStream_t s) { return jj_record(ctx, L, s); }))) return st;
+    if ((st = run_recorded(ctx, k, stream, [&](hipStream_t s) { return jj_record<R>(ctx, L, s); }))) return st;
     if (run->sync) return sync_and_check(ctx, stream);
     return SDE_OK;
+}
+
+int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run,
+                      float* theta, int32_t* winding, float* v, double* acc, double* point_sums,
+                      hipStream_t stream)
+{
+    return jj_integrate_t<float>(ctx, pts, n_pts, run, theta, winding, v, acc, point_sums, stream);
+}
+
+int jj_integrate_f64_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run,
+                          double* theta, int32_t* winding, double* v, double* acc, double* point_sums,
+                          hipStream_t stream)
+{
+    return jj_integrate_t<double>(ctx, pts, n_pts, run, theta, winding, v, acc, point_sums, stream);
 }
 
 int debug_philox_impl(sde_ctx* ctx, uint64_t seed, uint32_t tag, uint32_t a, uint32_t b, uint64_t c0,

@@ -362,6 +362,20 @@ int sde_jj_integrate(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, cons
     }
 }
 
+int sde_jj_integrate_f64(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run,
+                         double* theta, int32_t* winding, double* v, double* acc, double* point_sums,
+                         void* hip_stream)
+{
+    if (!ctx) return SDE_ERR_INVALID;
+    ctx->last_error.clear();
+    try {
+        return jj_integrate_f64_impl(ctx, pts, n_pts, run, theta, winding, v, acc, point_sums,
+                                     static_cast<hipStream_t>(hip_stream));
+    } catch (...) {
+        return fail(ctx, SDE_ERR_NOMEM, "host allocation failed");
+    }
+}
+
 int sde_kuramoto_integrate(sde_ctx* ctx, const sde_kuramoto_desc* desc, const sde_run* run,
                            float* phi, const float* omega, const float* K, double* r_samples,
                            void* hip_stream)

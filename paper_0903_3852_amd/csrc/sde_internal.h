@@ -138,6 +138,9 @@ int step_counter(sde_ctx* ctx, uint64_t** out);
 int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run,
                       float* theta, int32_t* winding, float* v, double* acc, double* point_sums,
                       hipStream_t stream);
+int jj_integrate_f64_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run,
+                          double* theta, int32_t* winding, double* v, double* acc, double* point_sums,
+                          hipStream_t stream);
 int debug_philox_impl(sde_ctx* ctx, uint64_t seed, uint32_t tag, uint32_t a, uint32_t b,
                       uint64_t c0, uint64_t n, uint32_t* out, hipStream_t stream);
 int debug_gauss_impl(sde_ctx* ctx, uint64_t seed, uint32_t tag, uint32_t a, uint32_t b,
