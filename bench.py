@@ -322,13 +322,30 @@ def bench_fig2(args, sde, torch, dev):
     e.record(stream)
     torch.cuda.synchronize()
     t = s.elapsed_time(e) / 1e3
-    x0 = int(wd.median().item()) - 100
+    # the same ensemble in double precision (the paper's precision study)
+    th64 = torch.empty(P, dtype=torch.float64, device=dev)
+    wd64 = torch.empty(P, dtype=torch.int32, device=dev)
+    v64 = torch.empty(P, dtype=torch.float64, device=dev)
+    acc64 = torch.empty(P, dtype=torch.float64, device=dev)
+    sde.sde_jj_integrate_f64(ctx, [dict(pts[0], n_steps=100)], run, th64, wd64, v64, acc64)  # warm-up
+    torch.cuda.synchronize()
+    s.record(stream)
+    sde.sde_jj_integrate_f64(ctx, pts, run, th64, wd64, v64, acc64)
+    e.record(stream)
+    torch.cuda.synchronize()
+    t64 = s.elapsed_time(e) / 1e3
+    x0 = int(wd64.median().item()) - 100
+    counts64 = torch.zeros(202, dtype=torch.int64, device=dev)
     sde.sde_position_histogram(ctx, wd, x0, 200, counts)
+    sde.sde_position_histogram(ctx, wd64, x0, 200, counts64)
     torch.cuda.synchronize()
     sde.sde_check(ctx)
     sde.sde_destroy(ctx)
-    h = counts.cpu().numpy()
-    vb = acc.cpu().numpy() / n
+    h, h64 = counts.cpu().numpy(), counts64.cpu().numpy()
+    keep = (h + h64) >= 10
+    chi2 = float((((h[keep] - h64[keep]) ** 2) / (h[keep] + h64[keep])).sum())
+    from scipy import stats
+    vb, vb64 = acc.cpu().numpy() / n, acc64.cpu().numpy() / n
     x = th.cpu().double().numpy() + wd.cpu().double().numpy()
     return {"workload": "jj_fig2", "potential": "sin(2 pi x)", "paths": P, "heun_steps": n,
             "seconds": t, "path_steps_per_s": P * n / t,
@@ -336,6 +353,11 @@ def bench_fig2(args, sde, torch, dev):
             "position_mean": float(x.mean()), "position_sd": float(x.std()),
             "histogram": {"x0": x0, "bins": 200, "underflow": int(h[0]), "overflow": int(h[201]),
                           "occupied_bins": int(np.count_nonzero(h[1:201])), "max_bin": int(h[1:201].max())},
+            "fp64": {"seconds": t64, "path_steps_per_s": P * n / t64, "fp64_over_fp32_time": t64 / t,
+                     "mean_velocity": float(vb64.mean()), "mean_velocity_se": float(vb64.std(ddof=1) / np.sqrt(P)),
+                     "histogram_chi2": chi2, "histogram_dof": int(keep.sum() - 1),
+                     "histogram_p": float(stats.chi2.sf(chi2, keep.sum() - 1)),
+                     "same_final_period": float((wd == wd64).float().mean().item())},
             "paper_reported_s": {"fp32": 20.0, "fp64": 780.0, "cpu_one_core": "> 10800"}}
 
 
