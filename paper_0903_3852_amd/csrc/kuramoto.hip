@@ -31,13 +31,13 @@ namespace sde {
 
 // ---------------------------------------------------------------- MF ------
 constexpr int kMFThreads = 1024;
+constexpr uint32_t kMaxMFGroups = kMFThreads / 4;  // workgroups per realization (one polling lane per word)
 
 struct MFArgs {
     float* theta;            // [R][N] revolutions, in/out (this launch's realizations)
     const float* omega;      // [N]
     double* r_samples;       // [R][n_samples] or null
-    double* partials;        // [2 slots][R][G][2]
-    uint32_t* barrier;       // [R] arrival counters, zero at launch
+    uint64_t* slots;         // [2 parities][R][G][4] tagged words (kMFWordsPerGroup), zero at launch
     int* flag;               // error flag (NaN state, or a barrier that timed out)
     uint32_t N, R, G, M;
     uint32_t r_base;         // global index of this launch's first realization
@@ -52,14 +52,25 @@ struct MFArgs {
     uint32_t spin_limit;     // barrier give-up bound (iterations of s_sleep)
 };
 
-// Publish this workgroup's FP64 partial sums (s, c) for stage `epoch` of
-// realization r and wait until all G workgroups of r have published theirs.
-// The partials are stored and later read with agent-scope atomics; the
-// arrival counter is incremented with release and polled with acquire
-// semantics.  One lane does the waiting.  Returns false if the wait exceeded
-// the spin bound (the error flag is then set and the kernel winds down).
-__device__ __forceinline__ bool publish_and_wait(const MFArgs& A, uint32_t r, uint32_t w, uint32_t epoch,
-                                                 double s, double c, double* lds, int* lds_ok)
+// Exchange of the per-workgroup FP64 sums (s, c) of stage `epoch` among the
+// G workgroups of realization r; returns the realization's S and C (the
+// partials added in workgroup order, so every workgroup gets the same bits).
+//
+// No fences: each workgroup publishes its two doubles as four 64-bit words
+// (32 data bits, 32 bits of tag = epoch + 1) with relaxed agent-scope atomic
+// stores, and lane t < 4G polls word t with relaxed agent-scope atomic loads
+// until its tag matches.  A 64-bit atomic is read whole or not at all, so a
+// matching tag certifies its data; nothing else needs ordering.  A release
+// and acquire pair instead costs a write-back and an invalidation of the
+// L2 on this multi-XCD part at every stage.  Two parities of slots: a
+// workgroup can only publish epoch e + 2 after every workgroup published
+// e + 1, i.e. after all of them read epoch e.  Returns false if a wait
+// exceeded the spin bound (the error flag is then set).
+constexpr uint32_t kMFWordsPerGroup = 4;
+
+__device__ __forceinline__ bool mf_exchange(const MFArgs& A, uint32_t r, uint32_t w, uint32_t epoch, double s,
+                                            double c, double* lds, uint32_t* words, int* lds_ok, double& S,
+                                            double& C)
 {
     const int lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
     s = wave_sum(s);
@@ -69,39 +80,57 @@ __device__ __forceinline__ bool publish_and_wait(const MFArgs& A, uint32_t r, ui
         lds[2 * wid + 1] = c;
     }
     __syncthreads();
+    const uint64_t tag = (uint64_t)(epoch + 1) << 32;
+    uint64_t* slot = A.slots + ((uint64_t)(epoch & 1u) * A.R + r) * A.G * kMFWordsPerGroup;
     if (threadIdx.x == 0) {
-        double S = 0.0, C = 0.0;
-#pragma unroll 1
+        double Sw = 0.0, Cw = 0.0;
+#pragma unroll
         for (int k = 0; k < kMFThreads / kWave; ++k) {
-            S += lds[2 * k];
-            C += lds[2 * k + 1];
+            Sw += lds[2 * k];
+            Cw += lds[2 * k + 1];
         }
-        double* mine = A.partials + (((uint64_t)(epoch & 1u) * A.R + r) * A.G + w) * 2;
-        __hip_atomic_store(mine, S, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(mine + 1, C, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        const uint32_t target = (epoch + 1) * A.G;
-        __hip_atomic_fetch_add(A.barrier + r, 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t bs = (uint64_t)__double_as_longlong(Sw), bc = (uint64_t)__double_as_longlong(Cw);
+        uint64_t* mine = slot + (uint64_t)w * kMFWordsPerGroup;
+        __hip_atomic_store(mine + 0, tag | (bs & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(mine + 1, tag | (bs >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(mine + 2, tag | (bc & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(mine + 3, tag | (bc >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    if (threadIdx.x < kMFWordsPerGroup * A.G) {
         uint32_t spins = 0;
-        int ok = 1;
-        while (__hip_atomic_load(A.barrier + r, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        uint64_t v;
+        while (((v = __hip_atomic_load(slot + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) &
+                0xffffffff00000000ull) != tag) {
             __builtin_amdgcn_s_sleep(1);
             if (++spins > A.spin_limit) {
-                ok = 0;
                 atomicOr(A.flag, 2);
+                *lds_ok = 0;
                 break;
             }
         }
-        *lds_ok = ok;
+        words[threadIdx.x] = (uint32_t)v;
     }
     __syncthreads();
-    return *lds_ok != 0;
+    if (!*lds_ok) return false;
+    S = 0.0;
+    C = 0.0;
+#pragma unroll 4
+    for (uint32_t g = 0; g < A.G; ++g) {
+        const uint32_t* q = words + g * kMFWordsPerGroup;
+        S += __longlong_as_double((long long)(((uint64_t)q[1] << 32) | q[0]));
+        C += __longlong_as_double((long long)(((uint64_t)q[3] << 32) | q[2]));
+    }
+    __syncthreads();  // words and lds are rewritten by the next exchange
+    return true;
 }
 
 template <int OPT, int SCHEME>
 __global__ __launch_bounds__(kMFThreads, 1) void kuramoto_mf_kernel(MFArgs A)
 {
     __shared__ double lds[2 * kMFThreads / kWave];
+    __shared__ uint32_t words[kMFWordsPerGroup * kMaxMFGroups];
     __shared__ int lds_ok;
+    if (threadIdx.x == 0) lds_ok = 1;  // made visible by the exchange's first barrier
     // workgroup -> (realization r, slice w)
     uint32_t r, w;
     if (A.xcd_map) {
@@ -113,7 +142,7 @@ __global__ __launch_bounds__(kMFThreads, 1) void kuramoto_mf_kernel(MFArgs A)
         w = blockIdx.x % A.G;
     }
     const uint32_t N = A.N;
-    float th[OPT], F1[OPT];
+    float th[OPT], F1[OPT], om[OPT];
     uint32_t idx[OPT];
     bool live[OPT];
 #pragma unroll
@@ -121,6 +150,9 @@ __global__ __launch_bounds__(kMFThreads, 1) void kuramoto_mf_kernel(MFArgs A)
         idx[k] = (w * OPT + k) * kMFThreads + threadIdx.x;
         live[k] = idx[k] < N;
         const uint32_t i = live[k] ? idx[k] : 0u;
+        // omega stays in registers: each barrier's acquire invalidates the
+        // L2, so a per-stage load would wait out a memory round trip
+        om[k] = live[k] ? A.omega[i] : 0.f;
         if (A.init_from_state) {
             th[k] = live[k] ? A.theta[(uint64_t)r * N + i] : 0.f;
         } else {
@@ -142,15 +174,9 @@ __global__ __launch_bounds__(kMFThreads, 1) void kuramoto_mf_kernel(MFArgs A)
                 c += (double)cos_rev(t[k]);
             }
         }
-        if (!publish_and_wait(A, r, w, epoch, s, c, lds, &lds_ok)) return false;
-        const double* all = A.partials + ((uint64_t)(epoch & 1u) * A.R + r) * A.G * 2;
+        double S, C;
+        if (!mf_exchange(A, r, w, epoch, s, c, lds, words, &lds_ok, S, C)) return false;
         ++epoch;
-        double S = 0.0, C = 0.0;
-#pragma unroll 1
-        for (uint32_t g = 0; g < A.G; ++g) {
-            S += __hip_atomic_load(all + 2 * g, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            C += __hip_atomic_load(all + 2 * g + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
         Sd = S;
         Cd = C;
         Sf = (float)S;
@@ -181,7 +207,7 @@ __global__ __launch_bounds__(kMFThreads, 1) void kuramoto_mf_kernel(MFArgs A)
         }
         const uint32_t j = (uint32_t)n & 3u;
         auto noise = [&](int k) { return j == 0 ? g[k][0] : j == 1 ? g[k][1] : j == 2 ? g[k][2] : g[k][3]; };
-        auto omega_of = [&](int k) { return live[k] ? A.omega[idx[k]] : 0.f; };
+        auto omega_of = [&](int k) { return om[k]; };
         float tt[OPT];
 #pragma unroll
         for (int k = 0; k < OPT; ++k) {
@@ -215,6 +241,12 @@ __global__ __launch_bounds__(kMFThreads, 1) void kuramoto_mf_kernel(MFArgs A)
     }
     if (__ballot(bad) != 0 && (threadIdx.x & (kWave - 1)) == 0) atomicOr(A.flag, 1);
     (void)ok;
+}
+
+__global__ void mf_zero_kernel(uint32_t* p, size_t n)
+{
+    const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
 }
 
 // ------------------------------------------------------------- TILED ------
@@ -490,24 +522,29 @@ static int run_meanfield(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run
     int per_cu = 0;
     SDE_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kMFThreads, 0));
     const uint64_t capacity = (uint64_t)std::max(per_cu, 0) * ctx->n_cu;
-    if (capacity < G64)
+    if (capacity < G64 || G64 > kMaxMFGroups)
         return fail(ctx, SDE_ERR_UNSUPPORTED, "mean-field kernel: N = %u needs %llu co-resident workgroups, the "
-                    "device holds %llu", d->N, (unsigned long long)G64, (unsigned long long)capacity);
+                    "device holds %llu (at most %u per realization)", d->N, (unsigned long long)G64,
+                    (unsigned long long)capacity, kMaxMFGroups);
     // realizations per cooperative launch: as many as fit co-resident
     const uint32_t r_per_launch = (uint32_t)std::min<uint64_t>(d->R, capacity / G);
 
-    void* partials = nullptr;
-    int st = ensure_ws(ctx, kSlotKuraPartials, (size_t)2 * r_per_launch * G * 2 * sizeof(double), &partials);
+    void* slots = nullptr;
+    const size_t slot_words = (size_t)2 * r_per_launch * G * kMFWordsPerGroup;
+    int st = ensure_ws(ctx, kSlotKuraPartials, slot_words * sizeof(uint64_t), &slots);
     if (st) return st;
     for (uint32_t r0 = 0; r0 < d->R; r0 += r_per_launch) {
         const uint32_t nr = std::min(r_per_launch, d->R - r0);
-        if ((st = zero_counters(ctx, 0, nr, stream))) return st;
+        // tags start at 1: zeroed slots never match
+        const size_t n32 = 2 * slot_words;
+        hipLaunchKernelGGL(mf_zero_kernel, dim3((uint32_t)((n32 + 255) / 256)), dim3(256), 0, stream,
+                           static_cast<uint32_t*>(slots), n32);
+        SDE_HIP(ctx, hipGetLastError());
         MFArgs A;
         A.theta = phi + (uint64_t)r0 * d->N;
         A.omega = omega;
         A.r_samples = r_samples ? r_samples + (uint64_t)r0 * n_samples : nullptr;
-        A.partials = static_cast<double*>(partials);
-        A.barrier = ctx->counters;
+        A.slots = static_cast<uint64_t*>(slots);
         A.flag = ctx->flag;
         A.N = d->N;
         A.R = nr;
