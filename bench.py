@@ -40,6 +40,7 @@ import sde_inputs  # noqa: E402
 # ---------------------------------------------------------------------------
 PEAK_FMA_LANES = 256 * 128 * 2.4e9
 PEAK_MFMA_16BIT = 2.5e15           # dense bf16 / fp16 MFMA FLOP/s
+PEAK_MFMA_FP32 = 157.3e12          # FP32 MFMA FLOP/s
 W_INT = 2.0
 W_TRANS = 4.0
 # Noise per path (or oscillator) and step: Philox4x32-10 (20 wide
@@ -420,8 +421,9 @@ def bench_kuramoto(name, args, sde, torch, dev, steps=None, reps=1):
     else:
         gemm_flop = 2.0 * N * N * 2 * R * n * (2 if heun else 1)
         if spec["coupling"] == 2:
-            rec["roofline"] = {"bound": "alu", "achieved": gemm_flop / t / 1e12, "peak": 2 * PEAK_FMA_LANES / 1e12,
-                               "unit": "TFLOP/s", "frac": gemm_flop / t / (2 * PEAK_FMA_LANES), "traffic": None}
+            # FP32 MFMA (v_mfma_f32_16x16x4_f32): MI355X's FP32 matrix peak equals its FP32 vector peak
+            rec["roofline"] = {"bound": "mfma", "achieved": gemm_flop / t / 1e12, "peak": PEAK_MFMA_FP32 / 1e12,
+                               "unit": "TFLOP/s", "frac": gemm_flop / t / PEAK_MFMA_FP32, "traffic": None}
         else:
             executed = 3 * gemm_flop
             rec["gemm_equivalent_tflops"] = gemm_flop / t / 1e12

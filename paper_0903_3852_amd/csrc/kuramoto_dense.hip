@@ -10,7 +10,7 @@
 // build it).
 //
 // Variants:
-//  * FP32: LDS-tiled FP32 FMA product (VALU).
+//  * FP32: FP32 MFMA (v_mfma_f32_16x16x4_f32), FP32 products and accumulation.
 //  * BF16X3 / FP16X3: MFMA (v_mfma_f32_16x16x32_{bf16,f16}) with FP32
 //    accumulation on a hi/lo split of both operands,
 //       K B ~ K_hi B_hi + K_hi B_lo + K_lo B_hi,
@@ -29,8 +29,9 @@
 //                    load (a row-major tile puts the 16 rows of a fragment
 //                    8 KB apart, and the L1 then serves the load one lane at
 //                    a time);
-//   FP32 variant:    K [Mp][ld] row-major, B [2 Rp][ld] column-major, ld = Np
-//                    padded to an odd multiple of 128 bytes (dense_pitch).
+//   FP32 variant:    the same idea for the FP32 MFMA's operands (frag32_off):
+//                    16 rows by 16 k in one contiguous 1 KB block, a lane's
+//                    float4 holding the k of four consecutive MFMAs.
 // A workgroup owns 128 rows x 32 realizations (64 columns), so every lane
 // holds S and C of the same (i, r) in its accumulators.  Workgroups are
 // dealt to XCDs so that each XCD sweeps a contiguous band of rows over all
@@ -57,7 +58,7 @@ constexpr uint32_t kRealTile = 32;
 constexpr uint32_t kKStep = 32;
 
 struct DenseArgs {
-    const void* K;         // scaled K: packed 16-bit hi/lo, or FP32 [Mp][ld]
+    const void* K;         // scaled K, packed: 16-bit hi/lo (frag_off) or FP32 (frag32_off)
     const void* B;         // current sin/cos operand (same layout family)
     void* Bnext;           // operand for the next product
     const float* src;      // [R][N] phases the drift is evaluated at
@@ -67,7 +68,6 @@ struct DenseArgs {
     const float* omega;    // [N]
     const float* scale;    // device: {scale, 1/scale}
     uint32_t N, R, Np, Rp, Mp;  // Np: k extent of the product (N rounded up to 32)
-    uint32_t ld;           // FP32 variant: row pitch (elements) of K and of the operand columns
     const uint64_t* nbase; // device: absolute step of the current chunk's first step
     uint32_t k;            // step within the chunk
     uint32_t key0, key1;
@@ -93,6 +93,15 @@ __device__ __forceinline__ uint64_t frag_off(uint32_t row, uint32_t k, uint32_t 
     return ((((uint64_t)(row >> 4) * KB + (k >> 5)) * 2) * 64 + ((row & 15u) + 16u * ((k >> 3) & 3u))) * 8 + (k & 7u);
 }
 constexpr uint32_t kFragLo = 512;  // elements from a hi fragment to its lo part
+
+// Fragment-packed FP32 layout (k extent Np, KB16 = Np / 16 blocks of k): a
+// 16 x 16 block is one contiguous 1 KB run where lane l = row % 16 +
+// 16 * (k % 4) holds a float4 of k = k % 4 + {0, 4, 8, 12} -- the A (or B)
+// operands of four consecutive v_mfma_f32_16x16x4_f32.
+__device__ __forceinline__ uint64_t frag32_off(uint32_t row, uint32_t k, uint32_t KB16)
+{
+    return (((uint64_t)(row >> 4) * KB16 + (k >> 4)) * 64 + ((row & 15u) + 16u * (k & 3u))) * 4 + ((k & 15u) >> 2);
+}
 
 // x -> hi = round16(x) at p[idx], lo = round16(x - hi) at p[idx + kFragLo].
 template <typename T>
@@ -133,27 +142,6 @@ __device__ __forceinline__ float dense_stage(const DenseArgs& A, uint64_t n, uin
     return t;
 }
 
-// dense_stage with its loads and stores for one oscillator.
-__device__ __forceinline__ float dense_phase(const DenseArgs& A, uint32_t i, uint32_t r, float S, float C)
-{
-    const uint64_t gi = (uint64_t)r * A.N + i;
-    const uint64_t n = load_uniform(A.nbase) + A.k;
-    float carry = A.stage == 1 ? 0.f : A.F1[gi];
-    const float t = dense_stage(A, n, i, r, S, C, A.src[gi], A.base[gi], A.omega[i], carry);
-    if (A.stage == 1 && !A.euler) A.F1[gi] = carry;
-    A.dst[gi] = t;
-    return t;
-}
-
-// FP32 variant: dense_phase, then the oscillator's entries of the next operand.
-__device__ __forceinline__ void dense_update_f32(const DenseArgs& A, uint32_t i, uint32_t r, float S, float C)
-{
-    const float t = dense_phase(A, i, r, S, C);
-    float* B = static_cast<float*>(A.Bnext);
-    B[(uint64_t)bcol(r, 0) * A.ld + i] = sin_rev(t);
-    B[(uint64_t)bcol(r, 1) * A.ld + i] = cos_rev(t);
-}
-
 // workgroup -> (row tile, realization tile); XCD-aware when the row tiles
 // split evenly over the 8 XCDs.
 __device__ __forceinline__ void tile_of(uint32_t b, uint32_t n_mt, uint32_t n_nt, uint32_t& mt, uint32_t& nt)
@@ -179,23 +167,20 @@ __device__ __forceinline__ f32x4 mfma16(V a, V b, f32x4 c)
 }
 
 // Stage update of a 128-row x 32-realization tile whose S and C sit in LDS
-// as tS[realization][row], tC[realization][row] (already unscaled).
-//  1. Lane t takes the oscillators t, t + 256, ... of the tile in row-fastest
-//     order, so a wave's phase loads and stores cover 64 consecutive
-//     oscillators of one realization (256 contiguous bytes; with 8 rows per
-//     lane the lanes sit 32 bytes apart and the L1 serves them one by one).
-//     All of a lane's loads come before its first store: dst may be src (the
-//     in-place Euler step), so the compiler could not move a load above a
-//     store.  sin and cos of the new phase replace S and C in the tile.
-//  2. The tile goes out as the next operand in 16-byte rows: a wave writes one
-//     whole 1 KB packed fragment (hi) and its lo part per pass.
-template <typename T, typename V>
-__device__ __forceinline__ void dense_tile_update(const DenseArgs& A, uint32_t mt, uint32_t nt,
-                                                  float (*tS)[kRowTile + 1], float (*tC)[kRowTile + 1])
+// as tS[realization][row], tC[realization][row] (already unscaled).  Lane t
+// takes the oscillators t, t + 256, ... of the tile in row-fastest order, so
+// a wave's phase loads and stores cover 64 consecutive oscillators of one
+// realization (256 contiguous bytes; with 8 rows per lane the lanes sit 32
+// bytes apart and the L1 serves them one by one).  All of a lane's loads come
+// before its first store: dst may be src (the in-place Euler step), so the
+// compiler could not move a load above a store.  sin and cos of the new
+// phase replace S and C in the tile (zero outside R x N), for the store of
+// the next operand that follows.
+__device__ __forceinline__ void dense_tile_stage(const DenseArgs& A, uint32_t mt, uint32_t nt,
+                                                 float (*tS)[kRowTile + 1], float (*tC)[kRowTile + 1])
 {
     constexpr uint32_t kPer = kRowTile * kRealTile / kDenseThreads;  // oscillators per lane
     static_assert(kRowTile % kWave == 0 && kDenseThreads % kRowTile == 0, "a wave stays in one realization");
-    const uint32_t KB = A.Np / kKStep;
     const uint64_t n = load_uniform(A.nbase) + A.k;
     const bool corrector = A.stage != 1;
     float ts[kPer], th[kPer], cy[kPer], om[kPer];
@@ -238,8 +223,17 @@ __device__ __forceinline__ void dense_tile_update(const DenseArgs& A, uint32_t m
         tC[rl][il] = cv;
     }
     __syncthreads();
-    // pass j: lane -> (column c % 16, 8-row group within the 32-row block) of
-    // fragment (column block, k block) = ((u >> 6) & 3, u >> 8)
+}
+
+// The tile's sin/cos as the next 16-bit split operand, in 16-byte rows: pass
+// j sends lane -> (column c % 16, 8-row group of the 32-row block) of the
+// fragment (column block, k block) = ((u >> 6) & 3, u >> 8), so a wave writes
+// one whole 1 KB packed fragment (hi) and its lo part per pass.
+template <typename T, typename V>
+__device__ __forceinline__ void dense_tile_store(const DenseArgs& A, uint32_t mt, uint32_t nt,
+                                                 const float (*tS)[kRowTile + 1], const float (*tC)[kRowTile + 1])
+{
+    const uint32_t KB = A.Np / kKStep;
     T* B = static_cast<T*>(A.Bnext);
 #pragma unroll
     for (uint32_t j = 0; j < 2 * kRealTile * kRowTile / 8 / kDenseThreads; ++j) {
@@ -261,6 +255,66 @@ __device__ __forceinline__ void dense_tile_update(const DenseArgs& A, uint32_t m
     }
 }
 
+// The same for the FP32 operand: lane -> (column c % 16, k % 4) of the block
+// (column block, 16-row block) = ((u >> 6) & 3, u >> 8); one float4 (k, k + 4,
+// k + 8, k + 12) per lane, a whole 1 KB block per wave and pass.
+__device__ __forceinline__ void dense_tile_store_f32(const DenseArgs& A, uint32_t mt, uint32_t nt,
+                                                     const float (*tS)[kRowTile + 1], const float (*tC)[kRowTile + 1])
+{
+    const uint32_t KB16 = A.Np / 16;
+    float* B = static_cast<float*>(A.Bnext);
+#pragma unroll
+    for (uint32_t j = 0; j < 2 * kRealTile * kRowTile / 4 / kDenseThreads; ++j) {
+        const uint32_t u = threadIdx.x + j * kDenseThreads;
+        const uint32_t cb = (u >> 6) & 3u, kind = cb >> 1;
+        const uint32_t rl = (cb & 1u) * 16 + (u & 15u), il0 = (u >> 8) * 16 + ((u >> 4) & 3u);
+        const uint32_t r = nt * kRealTile + rl, i0 = mt * kRowTile + il0;
+        if (r >= A.R || i0 >= A.N) continue;
+        const float* src = kind ? &tC[rl][il0] : &tS[rl][il0];
+        const f32x4 v{src[0], src[4], src[8], src[12]};
+        *reinterpret_cast<f32x4*>(B + frag32_off(bcol(r, kind), i0, KB16)) = v;
+    }
+}
+
+// Sum of the four waves' partial 128 x 64 tiles in a fixed order, times the
+// exact power of two `inv`, transposed into tS/tC: waves 1..3 go through red,
+// wave 0 writes its own straight into the tile, then all lanes add
+// ((p1 + p2) + p3).
+constexpr uint32_t kSplitK = 4;
+
+__device__ __forceinline__ void dense_reduce_tile(const f32x4 (&acc)[8][4], f32x4 (*red)[32][kWave],
+                                                  float (*tS)[kRowTile + 1], float (*tC)[kRowTile + 1], float inv)
+{
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    if (wave > 0) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) red[wave - 1][m * 4 + n][lane] = acc[m][n];
+    } else {
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                float(*t)[kRowTile + 1] = (n >> 1) ? tC : tS;
+                const uint32_t rl = (n & 1) * 16 + (lane & 15u);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) t[rl][m * 16 + 4 * (lane >> 4) + q] = acc[m][n][q] * inv;
+            }
+    }
+    __syncthreads();
+    for (uint32_t p = threadIdx.x; p < 32 * kWave; p += kDenseThreads) {
+        const uint32_t quad = p / kWave, l = p % kWave;
+        const f32x4 sum = (red[0][quad][l] + red[1][quad][l]) + red[2][quad][l];
+        const uint32_t m = quad / 4, n = quad % 4;
+        float(*t)[kRowTile + 1] = (n >> 1) ? tC : tS;
+        const uint32_t rl = (n & 1) * 16 + (l & 15u);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) t[rl][m * 16 + 4 * (l >> 4) + q] += sum[q] * inv;
+    }
+    __syncthreads();
+}
+
 // Split-precision product and stage update of one 128-row x 32-realization
 // tile.  The output (N x 2R = 4096 x 512 at the benchmark size) is too small
 // to give each SIMD a large tile of its own, so the k loop is split instead:
@@ -271,7 +325,6 @@ __device__ __forceinline__ void dense_tile_update(const DenseArgs& A, uint32_t m
 // grid of 64 x 32 wave tiles needs (there the L1 bounds the loop).  The four
 // partial tiles are summed through LDS in a fixed order, then the stage
 // update runs on the sum.
-constexpr uint32_t kSplitK = 4;
 
 template <typename T, typename V>
 __global__ __launch_bounds__(kDenseThreads, 1) void dense_mfma_kernel(DenseArgs A)
@@ -335,111 +388,61 @@ __global__ __launch_bounds__(kDenseThreads, 1) void dense_mfma_kernel(DenseArgs 
 #pragma unroll
             for (int n = 0; n < 4; ++n) acc[m][n] = mfma16<T, V>(cal[m], cbh[n], acc[m][n]);
     }
-    // Partial tiles: waves 1..3 into red; wave 0 writes its own, unscaled by
-    // the exact power of two, straight into the transposed tile; then all
-    // lanes add ((p1 + p2) + p3) into it -- a fixed order.
-    const float inv = A.scale[1];
-    if (wave > 0) {
-#pragma unroll
-        for (int m = 0; m < 8; ++m)
-#pragma unroll
-            for (int n = 0; n < 4; ++n) red[wave - 1][m * 4 + n][lane] = acc[m][n];
-    } else {
-#pragma unroll
-        for (int m = 0; m < 8; ++m)
-#pragma unroll
-            for (int n = 0; n < 4; ++n) {
-                float(*t)[kRowTile + 1] = (n >> 1) ? tC : tS;
-                const uint32_t rl = (n & 1) * 16 + (lane & 15u);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) t[rl][m * 16 + 4 * (lane >> 4) + q] = acc[m][n][q] * inv;
-            }
-    }
-    __syncthreads();
-    for (uint32_t p = threadIdx.x; p < 32 * kWave; p += kDenseThreads) {
-        const uint32_t quad = p / kWave, l = p % kWave;
-        const f32x4 sum = (red[0][quad][l] + red[1][quad][l]) + red[2][quad][l];
-        const uint32_t m = quad / 4, n = quad % 4;
-        float(*t)[kRowTile + 1] = (n >> 1) ? tC : tS;
-        const uint32_t rl = (n & 1) * 16 + (l & 15u);
-#pragma unroll
-        for (int q = 0; q < 4; ++q) t[rl][m * 16 + 4 * (l >> 4) + q] += sum[q] * inv;
-    }
-    __syncthreads();
-    dense_tile_update<T, V>(A, mt, nt, tS, tC);
+    dense_reduce_tile(acc, red, tS, tC, A.scale[1]);
+    dense_tile_stage(A, mt, nt, tS, tC);
+    dense_tile_store<T, V>(A, mt, nt, tS, tC);
 }
 
-// ------------------------------------------------------------ FP32 SIMT ---
-// 256 lanes, tile 128 rows x 32 realizations, k step 16 through LDS; each
-// lane accumulates 8 rows x (2 realizations x {sin, cos}).
-constexpr uint32_t kF32K = 16;
-
-__global__ __launch_bounds__(kDenseThreads) void dense_fp32_kernel(DenseArgs A)
+// ------------------------------------------------------------- FP32 MFMA --
+// The FP32 product on v_mfma_f32_16x16x4_f32 with the same split of the k
+// loop: every wave computes the whole 128 x 64 tile over every fourth 16-k
+// block.  Per block a wave loads 8 K and 4 B float4 fragments (12 KB) and
+// issues 4 x 32 MFMAs (about 4096 cycles), so one block of prefetch covers
+// the memory latency.
+__global__ __launch_bounds__(kDenseThreads, 1) void dense_mfma32_kernel(DenseArgs A)
 {
-    __shared__ float As[kF32K][kRowTile + 4];
-    __shared__ float Bs[kF32K][2 * kRealTile + 4];
+    __shared__ f32x4 red[kSplitK - 1][32][kWave];
+    __shared__ float tS[kRealTile][kRowTile + 1], tC[kRealTile][kRowTile + 1];
     uint32_t mt, nt;
     tile_of(blockIdx.x, A.Mp / kRowTile, A.Rp / kRealTile, mt, nt);
-    const uint32_t tx = threadIdx.x & 15u, ty = threadIdx.x >> 4;  // 16 x 16
-    const float* K32 = static_cast<const float*>(A.K);
-    const float* B32 = static_cast<const float*>(A.B);
-    const uint64_t ld = A.ld;
-    float accS[8][2], accC[8][2];
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t KB16 = A.Np / 16;
+    const uint64_t stream = (uint64_t)KB16 * 256;  // floats per 16-row block
+    const float* pa = static_cast<const float*>(A.K) + (uint64_t)(mt * 8) * stream + lane * 4;
+    const float* pb = static_cast<const float*>(A.B) + (uint64_t)(nt * 4) * stream + lane * 4;
+
+    f32x4 acc[8][4];
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
+    for (int m = 0; m < 8; ++m)
 #pragma unroll
-        for (int b = 0; b < 2; ++b) accS[a][b] = accC[a][b] = 0.f;
-    // global -> LDS assignment: A tile 128 x 16 = 512 float4 (2 per lane),
-    // B tile 64 cols x 16 = 256 float4 (1 per lane)
-    const uint32_t arow = threadIdx.x >> 2, akq = (threadIdx.x & 3u) * 4;
-    const uint32_t bcolv = threadIdx.x >> 2, bkq = (threadIdx.x & 3u) * 4;
-    const float* pa0 = K32 + (uint64_t)(mt * kRowTile + arow) * ld + akq;
-    const float* pa1 = pa0 + 64 * ld;
-    const float* pb = B32 + (uint64_t)(nt * 2 * kRealTile + bcolv) * ld + bkq;
-    for (uint32_t k0 = 0; k0 < A.Np; k0 += kF32K) {
-        const float4 a0 = *reinterpret_cast<const float4*>(pa0 + k0);
-        const float4 a1 = *reinterpret_cast<const float4*>(pa1 + k0);
-        const float4 b0 = *reinterpret_cast<const float4*>(pb + k0);
-        __syncthreads();
-        As[akq + 0][arow] = a0.x;
-        As[akq + 1][arow] = a0.y;
-        As[akq + 2][arow] = a0.z;
-        As[akq + 3][arow] = a0.w;
-        As[akq + 0][arow + 64] = a1.x;
-        As[akq + 1][arow + 64] = a1.y;
-        As[akq + 2][arow + 64] = a1.z;
-        As[akq + 3][arow + 64] = a1.w;
-        Bs[bkq + 0][bcolv] = b0.x;
-        Bs[bkq + 1][bcolv] = b0.y;
-        Bs[bkq + 2][bcolv] = b0.z;
-        Bs[bkq + 3][bcolv] = b0.w;
-        __syncthreads();
+        for (int n = 0; n < 4; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    f32x4 a[8], b[4];
+    auto load = [&](uint64_t o) {
 #pragma unroll
-        for (uint32_t k = 0; k < kF32K; ++k) {
-            float a[8];
+        for (int m = 0; m < 8; ++m) a[m] = *reinterpret_cast<const f32x4*>(pa + m * stream + o);
 #pragma unroll
-            for (int q = 0; q < 8; ++q) a[q] = As[k][ty * 8 + q];
-            const float s0 = Bs[k][2 * tx], s1 = Bs[k][2 * tx + 1];
-            const float c0 = Bs[k][kRealTile + 2 * tx], c1 = Bs[k][kRealTile + 2 * tx + 1];
+        for (int n = 0; n < 4; ++n) b[n] = *reinterpret_cast<const f32x4*>(pb + n * stream + o);
+    };
+    uint32_t kb = wave;
+    if (kb < KB16) load((uint64_t)kb * 256);
+    for (; kb < KB16; kb += kSplitK) {
+        f32x4 ca[8], cb[4];
 #pragma unroll
-            for (int q = 0; q < 8; ++q) {
-                accS[q][0] = fmaf(a[q], s0, accS[q][0]);
-                accS[q][1] = fmaf(a[q], s1, accS[q][1]);
-                accC[q][0] = fmaf(a[q], c0, accC[q][0]);
-                accC[q][1] = fmaf(a[q], c1, accC[q][1]);
-            }
-        }
+        for (int m = 0; m < 8; ++m) ca[m] = a[m];
+#pragma unroll
+        for (int n = 0; n < 4; ++n) cb[n] = b[n];
+        if (kb + kSplitK < KB16) load((uint64_t)(kb + kSplitK) * 256);  // this wave's next block
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+            for (int m = 0; m < 8; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n)
+                    acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(ca[m][j], cb[n][j], acc[m][n], 0, 0, 0);
     }
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-        const uint32_t r = nt * kRealTile + 2 * tx + b;
-        if (r >= A.R) continue;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const uint32_t i = mt * kRowTile + ty * 8 + q;
-            if (i < A.N) dense_update_f32(A, i, r, accS[q][b], accC[q][b]);
-        }
-    }
+    dense_reduce_tile(acc, red, tS, tC, 1.f);
+    dense_tile_stage(A, mt, nt, tS, tC);
+    dense_tile_store_f32(A, mt, nt, tS, tC);
 }
 
 // ----------------------------------------------------------- preparation --
@@ -465,29 +468,29 @@ __global__ void dense_scale_kernel(const uint32_t* maxbits, float* scale, int un
     scale[1] = 1.f / s;
 }
 
-// K -> scaled, padded copy over Mp rows x ld columns (zero outside N x N):
-// FP32 row-major with pitch ld, or the packed 16-bit hi/lo split (ld = Np).
+// K -> scaled, padded copy over Mp rows x Np columns (zero outside N x N) in
+// the packed layout: FP32, or the 16-bit hi/lo split.
 template <typename T>
-__global__ void dense_split_kernel(const float* K, uint32_t N, uint32_t ld, uint32_t Mp, const float* scale, void* out)
+__global__ void dense_split_kernel(const float* K, uint32_t N, uint32_t Np, uint32_t Mp, const float* scale, void* out)
 {
     const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= (uint64_t)Mp * ld) return;
-    const uint32_t i = (uint32_t)(g / ld), j = (uint32_t)(g % ld);
+    if (g >= (uint64_t)Mp * Np) return;
+    const uint32_t i = (uint32_t)(g / Np), j = (uint32_t)(g % Np);
     const float x = (i < N && j < N) ? K[(uint64_t)i * N + j] * scale[0] : 0.f;
     if constexpr (sizeof(T) == 4)
-        static_cast<float*>(out)[g] = x;
+        static_cast<float*>(out)[frag32_off(i, j, Np / 16)] = x;
     else
-        store_split<T>(static_cast<T*>(out), frag_off(i, j, ld / kKStep), x);
+        store_split<T>(static_cast<T*>(out), frag_off(i, j, Np / kKStep), x);
 }
 
-// theta [R][N] -> sin/cos operand over 2 Rp columns x ld rows of k (zero in
-// the padding): FP32 columns of pitch ld, or packed 16-bit hi/lo (ld = Np).
+// theta [R][N] -> sin/cos operand over 2 Rp columns x Np rows of k (zero in
+// the padding) in the packed layout: FP32, or the 16-bit hi/lo split.
 template <typename T>
-__global__ void dense_operand_kernel(const float* theta, uint32_t N, uint32_t R, uint32_t ld, uint32_t Rp, void* out)
+__global__ void dense_operand_kernel(const float* theta, uint32_t N, uint32_t R, uint32_t Np, uint32_t Rp, void* out)
 {
     const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= (uint64_t)Rp * ld) return;
-    const uint32_t r = (uint32_t)(g / ld), j = (uint32_t)(g % ld);
+    if (g >= (uint64_t)Rp * Np) return;
+    const uint32_t r = (uint32_t)(g / Np), j = (uint32_t)(g % Np);
     float s = 0.f, c = 0.f;
     if (r < R && j < N) {
         const float t = theta[(uint64_t)r * N + j];
@@ -495,27 +498,16 @@ __global__ void dense_operand_kernel(const float* theta, uint32_t N, uint32_t R,
         c = cos_rev(t);
     }
     if constexpr (sizeof(T) == 4) {
-        static_cast<float*>(out)[(uint64_t)bcol(r, 0) * ld + j] = s;
-        static_cast<float*>(out)[(uint64_t)bcol(r, 1) * ld + j] = c;
+        static_cast<float*>(out)[frag32_off(bcol(r, 0), j, Np / 16)] = s;
+        static_cast<float*>(out)[frag32_off(bcol(r, 1), j, Np / 16)] = c;
     } else {
         T* B = static_cast<T*>(out);
-        store_split<T>(B, frag_off(bcol(r, 0), j, ld / kKStep), s);
-        store_split<T>(B, frag_off(bcol(r, 1), j, ld / kKStep), c);
+        store_split<T>(B, frag_off(bcol(r, 0), j, Np / kKStep), s);
+        store_split<T>(B, frag_off(bcol(r, 1), j, Np / kKStep), c);
     }
 }
 
 // ------------------------------------------------------------------ host --
-// FP32 row pitch: Np rounded up to an odd multiple of 128 bytes, so that the
-// same k slice of consecutive rows does not fall on one L2 channel (a
-// power-of-two pitch, e.g. 16 KB at N = 4096, maps them all to one).
-static uint32_t dense_pitch(uint32_t Np)
-{
-    constexpr uint32_t unit = 128 / sizeof(float);
-    uint32_t ld = (Np + unit - 1) / unit * unit;
-    if ((ld / unit) % 2 == 0) ld += unit;
-    return ld;
-}
-
 template <typename T>
 static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, float* phi,
                            const float* omega, const float* K, double* r_samples, uint64_t n_samples, uint32_t M,
@@ -528,10 +520,9 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
     const uint32_t Rp = (R + kRealTile - 1) / kRealTile * kRealTile;
     const uint64_t NR = (uint64_t)N * R;
     const bool split = sizeof(T) == 2;
-    const uint32_t ld = split ? Np : dense_pitch(Np);
     // bytes of the K copy and of one operand buffer (hi and lo for the split)
-    const size_t a_bytes = (size_t)Mp * ld * sizeof(T) * (split ? 2 : 1);
-    const size_t b_bytes = (size_t)2 * Rp * ld * sizeof(T) * (split ? 2 : 1);
+    const size_t a_bytes = (size_t)Mp * Np * sizeof(T) * (split ? 2 : 1);
+    const size_t b_bytes = (size_t)2 * Rp * Np * sizeof(T) * (split ? 2 : 1);
     void *wa = nullptr, *wb = nullptr, *wk = nullptr;
     int st;
     if ((st = ensure_ws(ctx, kSlotDenseA, a_bytes, &wa))) return st;
@@ -548,13 +539,13 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
     hipLaunchKernelGGL(dense_zero_kernel, dim3(1), dim3(1), 0, stream, maxbits);
     if (split) hipLaunchKernelGGL(dense_maxabs_kernel, dim3(1024), dim3(256), 0, stream, K, (uint64_t)N * N, maxbits);
     hipLaunchKernelGGL(dense_scale_kernel, dim3(1), dim3(1), 0, stream, maxbits, scale, split ? 0 : 1);
-    hipLaunchKernelGGL(dense_split_kernel<T>, dim3((uint32_t)(((uint64_t)Mp * ld + 255) / 256)), dim3(256), 0, stream,
-                       K, N, ld, Mp, scale, wa);
+    hipLaunchKernelGGL(dense_split_kernel<T>, dim3((uint32_t)(((uint64_t)Mp * Np + 255) / 256)), dim3(256), 0, stream,
+                       K, N, Np, Mp, scale, wa);
     // both operand buffers get their zero padding (rows j >= N, columns of
     // realizations r >= R) here; the epilogues only ever write the live part
     for (int b = 0; b < 2; ++b)
-        hipLaunchKernelGGL(dense_operand_kernel<T>, dim3((uint32_t)(((uint64_t)Rp * ld + 255) / 256)), dim3(256), 0,
-                           stream, phi, N, R, ld, Rp, Bbuf[b]);
+        hipLaunchKernelGGL(dense_operand_kernel<T>, dim3((uint32_t)(((uint64_t)Rp * Np + 255) / 256)), dim3(256), 0,
+                           stream, phi, N, R, Np, Rp, Bbuf[b]);
     SDE_HIP(ctx, hipGetLastError());
 
     DenseArgs A;
@@ -564,7 +555,6 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
     A.N = N;
     A.R = R;
     A.Np = Np;
-    A.ld = ld;
     A.Rp = Rp;
     A.Mp = Mp;
     A.key0 = (uint32_t)run->seed;
@@ -580,7 +570,7 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
     A.nbase = nbase;
     auto launch = [&](hipStream_t s) -> int {
         if constexpr (sizeof(T) == 4)
-            hipLaunchKernelGGL(dense_fp32_kernel, grid, dim3(kDenseThreads), 0, s, A);
+            hipLaunchKernelGGL(dense_mfma32_kernel, grid, dim3(kDenseThreads), 0, s, A);
         else if constexpr (__is_same(T, __bf16))
             hipLaunchKernelGGL((dense_mfma_kernel<__bf16, bf16x8>), grid, dim3(kDenseThreads), 0, s, A);
         else
