@@ -71,8 +71,8 @@ def mf_ops_per_osc_step(heun):
 # HBM traffic of the JJ kernel per launch, from profiles/jj_scan_hbm_counters.md
 # (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, copy-calibrated).  Only valid for
 # the kernel source it was measured on.
-JJ_TRAFFIC_BYTES = (9279 + 6697) * 1024
-JJ_TRAFFIC_SOURCE_SHA1 = "7a996f3f1f409908a4493fa4cfd990d0a300b9da"
+JJ_TRAFFIC_BYTES = (8826 + 6857) * 1024
+JJ_TRAFFIC_SOURCE_SHA1 = "a071e148941d648d63a8fadf3918f7f4549211c6"
 
 
 def _jj_source_sha1():
@@ -154,7 +154,7 @@ def bench_jj(args, sde, torch, dev):
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FMA_LANES / 1e12,
                      "unit": "T FP32-FMA-equivalent lane-ops/s", "frac": achieved / PEAK_FMA_LANES,
                      "traffic": traffic, "ops_per_path_step": ops,
-                     "kernel": f"jj_persistent_kernel<{stats['jj_paths_per_lane']}, HEUN, inertial>"},
+                     "kernel": f"jj_persistent_kernel<float, {stats['jj_paths_per_lane']}, HEUN, inertial, sin>"},
         "launch": {"paths_per_lane": stats["jj_paths_per_lane"], "graph_replayed": stats["graph_replayed"],
                    "work_items": stats["work_items"]},
         "fp32_tflops": jj_flops_per_path_step() * path_steps / kernel_s / 1e12,
