@@ -71,8 +71,8 @@ def mf_ops_per_osc_step(heun):
 # HBM traffic of the JJ kernel per launch, from profiles/jj_scan_hbm_counters.md
 # (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, copy-calibrated).  Only valid for
 # the kernel source it was measured on.
-JJ_TRAFFIC_BYTES = (8826 + 6857) * 1024
-JJ_TRAFFIC_SOURCE_SHA1 = "a071e148941d648d63a8fadf3918f7f4549211c6"
+JJ_TRAFFIC_BYTES = (9848 + 6826) * 1024
+JJ_TRAFFIC_SOURCE_SHA1 = "e65c71464620b3268634a409af59a15086af724b"
 
 
 def _jj_source_sha1():
@@ -302,9 +302,10 @@ def bench_fig2(args, sde, torch, dev):
     """The paper's Fig. 2 ensemble: 2^19 paths of Eq. 1 with V(x) = sin(2 pi x)
     at a = 4.2, gamma = 0.9, omega = 4.9, D = 0.001, f = 0.1, dt = 0.01 of the
     drive period, 2000 periods (2*10^5 Heun steps), then the coarse-grained
-    position histogram (200 bins of one period, centred on the ensemble).
-    The paper's single-precision run took 20 s on its GPU, including writing
-    the trajectories to disk (not done here): context, not a target."""
+    position histogram (200 bins of one period, centred on the ensemble), and
+    the density over time from every path's period streamed once per drive
+    period.  The paper's single-precision run took 20 s on its GPU, including
+    writing every particle position to disk: context, not a target."""
     pts = sde_inputs.jj_fig2()
     P, n = pts[0]["n_paths"], pts[0]["n_steps"]
     th = torch.empty(P, dtype=torch.float32, device=dev)
@@ -323,6 +324,44 @@ def bench_fig2(args, sde, torch, dev):
     e.record(stream)
     torch.cuda.synchronize()
     t = s.elapsed_time(e) / 1e3
+    # the density over time (Fig. 2, left panel): every path's winding after
+    # every drive period (100 steps), 2000 rows streamed into HBM during the
+    # run, then the histograms of all rows in one call (fixed window of 600
+    # periods around the start)
+    every = 100
+    rows = n // every
+    rec = torch.empty((rows, P), dtype=torch.int32, device=dev)
+    st2 = tuple(torch.empty_like(x) for x in (th, wd, v, acc))
+    sde.sde_jj_integrate_recorded(ctx, [dict(pts[0], n_steps=100)], run, every, rec[:1], *st2)  # warm-up
+    torch.cuda.synchronize()
+    s.record(stream)
+    sde.sde_jj_integrate_recorded(ctx, pts, run, every, rec, *st2)
+    e.record(stream)
+    torch.cuda.synchronize()
+    t_rec = s.elapsed_time(e) / 1e3
+    xlo, nbw = -400, 600
+    dens = torch.empty((rows, nbw + 2), dtype=torch.int64, device=dev)
+    sde.sde_position_histograms(ctx, rec[:2], xlo, nbw, dens[:2])  # warm-up
+    torch.cuda.synchronize()
+    s.record(stream)
+    sde.sde_position_histograms(ctx, rec, xlo, nbw, dens)
+    e.record(stream)
+    torch.cuda.synchronize()
+    t_hist = s.elapsed_time(e) / 1e3
+    same = bool(torch.equal(st2[1], wd) and torch.equal(st2[0], th) and torch.equal(rec[-1], wd))
+    dn = dens.cpu().numpy()
+    del rec, dens
+    centre = xlo + np.arange(nbw) + 0.5
+    inner = dn[:, 1:nbw + 1].astype(np.float64)
+    mean_t = (inner * centre).sum(axis=1) / inner.sum(axis=1)
+    sd_t = np.sqrt((inner * centre ** 2).sum(axis=1) / inner.sum(axis=1) - mean_t ** 2)
+    density = {"record_every_steps": every, "rows": rows, "bytes_streamed": rows * P * 4,
+               "seconds_recorded_run": t_rec, "recording_overhead": t_rec / t - 1.0,
+               "histogram_seconds_all_rows": t_hist, "window": [xlo, xlo + nbw],
+               "outside_window_max": int((dn[:, 0] + dn[:, nbw + 1]).max()),
+               "same_trajectory_as_plain_run": same,
+               "mean_sd_at_periods": {str(k): [round(float(mean_t[k - 1]), 3), round(float(sd_t[k - 1]), 3)]
+                                      for k in (10, 100, 500, 1000, 2000)}}
     # the same ensemble in double precision (the paper's precision study)
     th64 = torch.empty(P, dtype=torch.float64, device=dev)
     wd64 = torch.empty(P, dtype=torch.int32, device=dev)
@@ -354,6 +393,7 @@ def bench_fig2(args, sde, torch, dev):
             "position_mean": float(x.mean()), "position_sd": float(x.std()),
             "histogram": {"x0": x0, "bins": 200, "underflow": int(h[0]), "overflow": int(h[201]),
                           "occupied_bins": int(np.count_nonzero(h[1:201])), "max_bin": int(h[1:201].max())},
+            "density_over_time": density,
             "fp64": {"seconds": t64, "path_steps_per_s": P * n / t64, "fp64_over_fp32_time": t64 / t,
                      "mean_velocity": float(vb64.mean()), "mean_velocity_se": float(vb64.std(ddof=1) / np.sqrt(P)),
                      "histogram_chi2": chi2, "histogram_dof": int(keep.sum() - 1),

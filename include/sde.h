@@ -170,6 +170,30 @@ int sde_jj_integrate_f64(sde_ctx* ctx, const sde_jj_point* pts /* [host] */, uin
                          const sde_run* run, double* theta, int32_t* winding, double* v, double* acc,
                          double* point_sums, void* hip_stream);
 
+/*
+ * sde_jj_integrate that also streams the coarse-grained positions of every
+ * path while it integrates: the ensemble's density over time in Fig. 2
+ * (left panel, positions averaged over a potential period) and Sec. 5,
+ * where the paper wrote every particle position to a file.  With T the
+ * total number of paths of the call (row pitch) and r = 0, 1, ...:
+ *   rec_winding[r * T + path_first(q) + p] = winding of path p of point q
+ *   after absolute step (floor(step0 / record_every) + r + 1) * record_every,
+ * for every multiple of record_every in (step0, step0 + n_steps(q)];
+ * rows past a point's last step keep their contents.  The trajectory is the
+ * one sde_jj_integrate computes (bit for bit).
+ * record_every: a positive multiple of 4 (one noise block).  n_rows: rows
+ * the caller's buffer holds; each point needs
+ *   floor((step0 + n_steps) / record_every) - floor(step0 / record_every).
+ * rec_winding: [device] int32 [n_rows][T], caller-owned, 4-byte aligned.
+ * Errors: as sde_jj_integrate, plus SDE_ERR_INVALID for a NULL or
+ * misaligned rec_winding, record_every not a positive multiple of 4, or a
+ * point that needs more than n_rows rows (nothing is written).
+ */
+int sde_jj_integrate_recorded(sde_ctx* ctx, const sde_jj_point* pts /* [host] */, uint32_t n_pts,
+                              const sde_run* run, float* theta, int32_t* winding, float* v, double* acc,
+                              double* point_sums, uint32_t record_every, uint64_t n_rows,
+                              int32_t* rec_winding /* [device] */, void* hip_stream);
+
 /* ---- Kuramoto (Eq. 2, Eq. 3, Alg. 3) ------------------------------------- */
 typedef struct {
     uint32_t N;            /* oscillators per realization                         */
@@ -241,6 +265,18 @@ int sde_observables(sde_ctx* ctx, int kind, const void* dev_in /* [device] */,
  */
 int sde_position_histogram(sde_ctx* ctx, const int32_t* winding /* [device] */, uint64_t n, int64_t x0,
                            uint32_t n_bins, uint64_t* counts /* [device] */, void* hip_stream);
+/*
+ * sde_position_histogram of n_rows rows at once (the density P(x; t) of
+ * Fig. 2 from the rows sde_jj_integrate_recorded writes): row r is
+ * winding[r * pitch .. r * pitch + n - 1] and its counts go to
+ * counts[r * (n_bins + 2) .. (r + 1) * (n_bins + 2) - 1], laid out as above.
+ * pitch >= n when n_rows > 1 (ignored for one row).  Errors: as
+ * sde_position_histogram, plus SDE_ERR_INVALID for n_rows = 0 or
+ * n_rows > 2^32, or pitch < n with several rows.
+ */
+int sde_position_histograms(sde_ctx* ctx, const int32_t* winding /* [device] */, uint64_t n, uint64_t pitch,
+                            uint64_t n_rows, int64_t x0, uint32_t n_bins, uint64_t* counts /* [device] */,
+                            void* hip_stream);
 
 /* ---- learned surrogate for the mean velocity <v> ------------------------- */
 /*

@@ -29,7 +29,8 @@ SDE_OBS_MEAN_F32, SDE_OBS_MEAN_F64, SDE_OBS_MEANSQ_F32, SDE_OBS_ORDER = 0, 1, 2,
 SDE_OPT_AUTOTUNE, SDE_OPT_GRAPHS, SDE_OPT_JJ_PPT = 1, 2, 3
 
 EXPORTS = ["sde_create", "sde_destroy", "sde_strerror", "sde_last_error", "sde_check",
-           "sde_jj_integrate", "sde_jj_integrate_f64", "sde_kuramoto_integrate", "sde_observables", "sde_position_histogram",
+           "sde_jj_integrate", "sde_jj_integrate_f64", "sde_jj_integrate_recorded", "sde_kuramoto_integrate",
+           "sde_observables", "sde_position_histogram", "sde_position_histograms",
            "sde_debug_philox", "sde_debug_gauss", "sde_set_option", "sde_set_tune_cache",
            "sde_get_stats", "sde_surrogate_create", "sde_surrogate_destroy",
            "sde_surrogate_param_count", "sde_surrogate_set_params", "sde_surrogate_get_params",
@@ -117,6 +118,9 @@ def lib():
         L.sde_jj_integrate_f64.argtypes = [vp, ctypes.POINTER(sde_jj_point), u32, ctypes.POINTER(sde_run),
                                            vp, vp, vp, vp, vp, vp]
         L.sde_jj_integrate_f64.restype = i32
+        L.sde_jj_integrate_recorded.argtypes = [vp, ctypes.POINTER(sde_jj_point), u32, ctypes.POINTER(sde_run),
+                                                vp, vp, vp, vp, vp, u32, u64, vp, vp]
+        L.sde_jj_integrate_recorded.restype = i32
         L.sde_kuramoto_integrate.argtypes = [vp, ctypes.POINTER(sde_kuramoto_desc),
                                              ctypes.POINTER(sde_run), vp, vp, vp, vp, vp]
         L.sde_kuramoto_integrate.restype = i32
@@ -125,6 +129,8 @@ def lib():
         L.sde_observables.restype = i32
         L.sde_position_histogram.argtypes = [vp, vp, u64, ctypes.c_int64, u32, vp, vp]
         L.sde_position_histogram.restype = i32
+        L.sde_position_histograms.argtypes = [vp, vp, u64, u64, u64, ctypes.c_int64, u32, vp, vp]
+        L.sde_position_histograms.restype = i32
         L.sde_debug_philox.argtypes = [vp, u64, u32, u32, u32, u64, u64, vp, vp]
         L.sde_debug_philox.restype = i32
         L.sde_debug_gauss.argtypes = [vp, u64, u32, u32, u32, u64, u64, vp, vp]
@@ -285,6 +291,19 @@ def sde_jj_integrate_f64(ctx, pts, run, theta=None, winding=None, v=None, acc=No
                                                   _stream(stream)))
 
 
+def sde_jj_integrate_recorded(ctx, pts, run, record_every, rec_winding, theta=None, winding=None, v=None,
+                              acc=None, point_sums=None, stream=None):
+    """sde_jj_integrate that writes every path's winding every record_every
+    steps into the device int32 tensor rec_winding [n_rows, total paths]."""
+    if not isinstance(pts, ctypes.Array):
+        pts = make_points(pts)
+    n_rows = rec_winding.shape[0] if rec_winding is not None and rec_winding.dim() == 2 else 0
+    return _check(ctx, lib().sde_jj_integrate_recorded(ctx, pts, len(pts), ctypes.byref(run), _ptr(theta),
+                                                       _ptr(winding), _ptr(v), _ptr(acc), _ptr(point_sums),
+                                                       int(record_every), int(n_rows), _ptr(rec_winding),
+                                                       _stream(stream)))
+
+
 def sde_kuramoto_integrate(ctx, desc, run, phi, omega, K=None, r_samples=None, stream=None):
     return _check(ctx, lib().sde_kuramoto_integrate(ctx, ctypes.byref(desc), ctypes.byref(run),
                                                     _ptr(phi), _ptr(omega), _ptr(K),
@@ -308,6 +327,17 @@ def sde_position_histogram(ctx, winding, x0, n_bins, counts, stream=None):
     counts[n_bins + 2] (underflow, bins x0 .. x0 + n_bins - 1, overflow)."""
     return _check(ctx, lib().sde_position_histogram(ctx, _ptr(winding), int(winding.numel()), int(x0),
                                                     int(n_bins), _ptr(counts), _stream(stream)))
+
+
+def sde_position_histograms(ctx, winding, x0, n_bins, counts, n=None, stream=None):
+    """Row-wise histograms of a device int32 tensor winding [n_rows, pitch]
+    (the first n entries of each row, default all) into device uint64
+    counts [n_rows, n_bins + 2]."""
+    n_rows, pitch = winding.shape
+    n = pitch if n is None else n
+    return _check(ctx, lib().sde_position_histograms(ctx, _ptr(winding), int(n), int(winding.stride(0)),
+                                                     int(n_rows), int(x0), int(n_bins), _ptr(counts),
+                                                     _stream(stream)))
 
 
 def sde_debug_philox(ctx, seed, tag, a, b, ctr0_first, n_blocks, dev_out, stream=None):

@@ -80,9 +80,12 @@ struct JJArgs {
     void* v;              // R[]
     double* acc;
     double* partials;
+    int32_t* rec;         // optional windings every rec_every steps: [row][rec_pitch]
+    uint64_t rec_pitch;   // paths of the call
     uint64_t step0;
     uint32_t key0, key1;
     uint32_t n_items, M;
+    uint32_t rec_every;   // a multiple of 4 (records fall on block ends)
     int32_t init_from_state;
 };
 
@@ -202,6 +205,10 @@ __device__ __forceinline__ void jj_item(const JJArgs& A, uint32_t q, uint32_t ch
     uint64_t n = A.step0;
     uint32_t kk = (uint32_t)(n % P.S);        // drive phase index of step n
     uint32_t mc = (uint32_t)((n + 1) % A.M);  // (n + 1) mod M: fold after the step when 0
+    // recording: rc = n mod rec_every; row r holds the state after the
+    // (r + 1)-th multiple of rec_every past step0
+    uint32_t rc = A.rec ? (uint32_t)(n % A.rec_every) : 0u;
+    uint64_t row = 0;
 
     auto fold_tick = [&]() {
         if (mc == 0) {
@@ -285,6 +292,18 @@ __device__ __forceinline__ void jj_item(const JJArgs& A, uint32_t q, uint32_t ch
             const R fl = floor(th[k]);
             th[k] -= fl;
             wd[k] += (int32_t)fl;
+        }
+        // a block never crosses a multiple of 4, hence of rec_every
+        if (A.rec) {
+            rc += jn - j0;
+            if (rc == A.rec_every) {
+                rc = 0;
+                int32_t* out = A.rec + row * A.rec_pitch + P.path_first;
+#pragma unroll
+                for (int k = 0; k < PPT; ++k)
+                    if (live[k]) out[pid[k]] = wd[k];
+                ++row;
+            }
         }
     }
 
@@ -561,6 +580,7 @@ static int jj_tune(sde_ctx* ctx, const std::vector<JJPointT<R>>& P0, const std::
         L.A.winding = nullptr;
         L.A.v = nullptr;
         L.A.acc = nullptr;
+        L.A.rec = nullptr;
         L.A.init_from_state = 0;
         L.A.flag = ctx->tune_flag;  // a trial run's NaN is not the caller's
         if ((st = jj_upload_plan(ctx, plan, stream, L))) break;
@@ -588,7 +608,8 @@ static int jj_tune(sde_ctx* ctx, const std::vector<JJPointT<R>>& P0, const std::
 
 template <typename R>
 static int jj_integrate_t(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run, R* theta,
-                          int32_t* winding, R* v, double* acc, double* point_sums, hipStream_t stream)
+                          int32_t* winding, R* v, double* acc, double* point_sums, int32_t* rec,
+                          uint32_t rec_every, uint64_t rec_rows, hipStream_t stream)
 {
     ctx->last = sde_stats{};
     if (!pts || !run || n_pts == 0) return fail(ctx, SDE_ERR_INVALID, "null points/run or n_pts = 0");
@@ -671,6 +692,17 @@ static int jj_integrate_t(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts,
         max_steps = std::max<uint64_t>(max_steps, p.n_steps);
     }
     if (path_first / kWave > 0xffffffffull) return fail(ctx, SDE_ERR_INVALID, "too many paths in one call");
+    if (rec) {
+        if (rec_every == 0 || rec_every % 4 != 0)
+            return fail(ctx, SDE_ERR_INVALID, "record_every must be a positive multiple of 4");
+        if (!aligned(rec, 4)) return fail(ctx, SDE_ERR_INVALID, "misaligned record buffer");
+        for (uint32_t q = 0; q < n_pts; ++q) {
+            const uint64_t rows = (run->step0 + pts[q].n_steps) / rec_every - run->step0 / rec_every;
+            if (rows > rec_rows)
+                return fail(ctx, SDE_ERR_INVALID, "point %u needs %llu record rows, the buffer has %llu", q,
+                            (unsigned long long)rows, (unsigned long long)rec_rows);
+        }
+    }
 
     int st;
     if ((st = upload(ctx, kSlotJJLut, 2, lut.data(), lut.size() * sizeof(R), stream))) return st;
@@ -684,6 +716,9 @@ static int jj_integrate_t(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts,
     L.A.v = v;
     L.A.acc = acc;
     L.A.step0 = run->step0;
+    L.A.rec = rec;
+    L.A.rec_pitch = path_first;
+    L.A.rec_every = rec ? rec_every : 0u;
     L.A.key0 = (uint32_t)(run->seed & 0xffffffffu);
     L.A.key1 = (uint32_t)(run->seed >> 32);
     L.A.M = M;
@@ -725,6 +760,7 @@ static int jj_integrate_t(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts,
     for (int kind = 0; kind < kJJKinds; ++kind)
         k += "|" + std::to_string(L.kind_begin[kind + 1]) + "/" + std::to_string(L.grid[kind]);
     k += point_sums ? "|ps" + std::to_string((uintptr_t)point_sums) : "|ps0";
+    if (rec) k += "|rec" + std::to_string((uintptr_t)rec) + "/" + std::to_string(rec_every);
     if ((st = run_recorded(ctx, k, stream, [&](hipStream_t s) { return jj_record<R>(ctx, L, s); }))) return st;
     if (run->sync) return sync_and_check(ctx, stream);
     return SDE_OK;
@@ -734,14 +770,23 @@ int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, con
                       float* theta, int32_t* winding, float* v, double* acc, double* point_sums,
                       hipStream_t stream)
 {
-    return jj_integrate_t<float>(ctx, pts, n_pts, run, theta, winding, v, acc, point_sums, stream);
+    return jj_integrate_t<float>(ctx, pts, n_pts, run, theta, winding, v, acc, point_sums, nullptr, 0, 0, stream);
+}
+
+int jj_integrate_recorded_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run,
+                               float* theta, int32_t* winding, float* v, double* acc, double* point_sums,
+                               uint32_t record_every, uint64_t n_rows, int32_t* rec_winding, hipStream_t stream)
+{
+    if (!rec_winding) return fail(ctx, SDE_ERR_INVALID, "null record buffer");
+    return jj_integrate_t<float>(ctx, pts, n_pts, run, theta, winding, v, acc, point_sums, rec_winding,
+                                 record_every, n_rows, stream);
 }
 
 int jj_integrate_f64_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run,
                           double* theta, int32_t* winding, double* v, double* acc, double* point_sums,
                           hipStream_t stream)
 {
-    return jj_integrate_t<double>(ctx, pts, n_pts, run, theta, winding, v, acc, point_sums, stream);
+    return jj_integrate_t<double>(ctx, pts, n_pts, run, theta, winding, v, acc, point_sums, nullptr, 0, 0, stream);
 }
 
 int debug_philox_impl(sde_ctx* ctx, uint64_t seed, uint32_t tag, uint32_t a, uint32_t b, uint64_t c0,

@@ -90,47 +90,63 @@ __global__ __launch_bounds__(kObsThreads) void obs_kernel(int kind, const void* 
 // sums: the result does not depend on the order.
 constexpr uint32_t kHistLds = 8192;
 
-__global__ void hist_zero_kernel(uint64_t* counts, uint32_t n)
+__global__ void hist_zero_kernel(uint64_t* counts, uint64_t n)
 {
-    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) counts[i] = 0ull;
 }
 
-__global__ __launch_bounds__(256) void hist_kernel(const int32_t* w, uint64_t n, int64_t x0, uint32_t nb,
-                                                   uint64_t* counts)
+// Row r = blockIdx.y, blockIdx.y + gridDim.y, ... of `rows` rows of n
+// windings each (row pitch `pitch`), counted into counts[r][nb + 2].
+__global__ __launch_bounds__(256) void hist_kernel(const int32_t* w, uint64_t n, uint64_t pitch, uint64_t rows,
+                                                   int64_t x0, uint32_t nb, uint64_t* counts)
 {
     __shared__ uint32_t h[kHistLds];
     const bool lds = nb + 2 <= kHistLds;
-    if (lds)
-        for (uint32_t i = threadIdx.x; i < nb + 2; i += blockDim.x) h[i] = 0u;
-    __syncthreads();
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
-        const int64_t d = (int64_t)w[i] - x0;
-        const uint32_t b = d < 0 ? 0u : d >= (int64_t)nb ? nb + 1 : (uint32_t)d + 1;
+    for (uint64_t r = blockIdx.y; r < rows; r += gridDim.y) {
+        const int32_t* wr = w + r * pitch;
+        uint64_t* cr = counts + r * (uint64_t)(nb + 2);
         if (lds)
-            atomicAdd(&h[b], 1u);
-        else
-            atomicAdd(reinterpret_cast<unsigned long long*>(counts + b), 1ull);
+            for (uint32_t i = threadIdx.x; i < nb + 2; i += blockDim.x) h[i] = 0u;
+        __syncthreads();
+        for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+            const int64_t d = (int64_t)wr[i] - x0;
+            const uint32_t b = d < 0 ? 0u : d >= (int64_t)nb ? nb + 1 : (uint32_t)d + 1;
+            if (lds)
+                atomicAdd(&h[b], 1u);
+            else
+                atomicAdd(reinterpret_cast<unsigned long long*>(cr + b), 1ull);
+        }
+        __syncthreads();
+        if (lds)
+            for (uint32_t i = threadIdx.x; i < nb + 2; i += blockDim.x)
+                if (h[i]) atomicAdd(reinterpret_cast<unsigned long long*>(cr + i), (unsigned long long)h[i]);
+        __syncthreads();  // h is cleared for the next row
     }
-    __syncthreads();
-    if (lds)
-        for (uint32_t i = threadIdx.x; i < nb + 2; i += blockDim.x)
-            if (h[i]) atomicAdd(reinterpret_cast<unsigned long long*>(counts + i), (unsigned long long)h[i]);
 }
 
-int histogram_impl(sde_ctx* ctx, const int32_t* winding, uint64_t n, int64_t x0, uint32_t n_bins, uint64_t* counts,
-                   hipStream_t stream)
+int histogram_impl(sde_ctx* ctx, const int32_t* winding, uint64_t n, uint64_t pitch, uint64_t n_rows, int64_t x0,
+                   uint32_t n_bins, uint64_t* counts, hipStream_t stream)
 {
     if ((!winding && n) || !counts) return fail(ctx, SDE_ERR_INVALID, "null winding or counts");
     if (n_bins == 0 || n_bins > (1u << 24)) return fail(ctx, SDE_ERR_INVALID, "n_bins must be in [1, 2^24]");
+    if (n_rows == 0 || n_rows > (1ull << 32)) return fail(ctx, SDE_ERR_INVALID, "n_rows must be in [1, 2^32]");
+    if (n_rows > 1 && pitch < n) return fail(ctx, SDE_ERR_INVALID, "row pitch below the row length");
     if (!aligned(winding, 4) || !aligned(counts, 8)) return fail(ctx, SDE_ERR_INVALID, "misaligned pointer");
-    const uint32_t nc = n_bins + 2;
-    hipLaunchKernelGGL(hist_zero_kernel, dim3((nc + 255) / 256), dim3(256), 0, stream, counts, nc);
+    const uint64_t nc = (uint64_t)(n_bins + 2) * n_rows;
+    const uint64_t zb = (nc + 255) / 256;
+    if (zb > 0x7fffffffull) return fail(ctx, SDE_ERR_INVALID, "too many counts");
+    hipLaunchKernelGGL(hist_zero_kernel, dim3((uint32_t)zb), dim3(256), 0, stream, counts, nc);
     if (n) {
-        uint64_t grid = std::min<uint64_t>((n + 255) / 256, (uint64_t)ctx->n_cu * 4);
-        grid = std::max<uint64_t>(grid, (n >> 31) + 1);  // at most 2^31 paths per workgroup
-        hipLaunchKernelGGL(hist_kernel, dim3((uint32_t)grid), dim3(256), 0, stream, winding, n, x0, n_bins, counts);
+        // about 4 workgroups per CU in all, at least one per row (up to 65535
+        // rows in flight), at most 2^31 windings per workgroup
+        const uint64_t gy = std::min<uint64_t>(n_rows, 65535);
+        uint64_t gx = std::max<uint64_t>(1, (uint64_t)ctx->n_cu * 4 / gy);
+        gx = std::min<uint64_t>(gx, (n + 255) / 256);
+        gx = std::max<uint64_t>(gx, (n >> 31) + 1);
+        hipLaunchKernelGGL(hist_kernel, dim3((uint32_t)gx, (uint32_t)gy), dim3(256), 0, stream, winding, n,
+                           n_rows > 1 ? pitch : n, n_rows, x0, n_bins, counts);
     }
     SDE_HIP(ctx, hipGetLastError());
     return SDE_OK;

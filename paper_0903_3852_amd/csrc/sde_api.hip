@@ -376,6 +376,20 @@ int sde_jj_integrate_f64(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, 
     }
 }
 
+int sde_jj_integrate_recorded(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run,
+                              float* theta, int32_t* winding, float* v, double* acc, double* point_sums,
+                              uint32_t record_every, uint64_t n_rows, int32_t* rec_winding, void* hip_stream)
+{
+    if (!ctx) return SDE_ERR_INVALID;
+    ctx->last_error.clear();
+    try {
+        return jj_integrate_recorded_impl(ctx, pts, n_pts, run, theta, winding, v, acc, point_sums, record_every,
+                                          n_rows, rec_winding, static_cast<hipStream_t>(hip_stream));
+    } catch (...) {
+        return fail(ctx, SDE_ERR_NOMEM, "host allocation failed");
+    }
+}
+
 int sde_kuramoto_integrate(sde_ctx* ctx, const sde_kuramoto_desc* desc, const sde_run* run,
                            float* phi, const float* omega, const float* K, double* r_samples,
                            void* hip_stream)
@@ -408,7 +422,15 @@ int sde_position_histogram(sde_ctx* ctx, const int32_t* winding, uint64_t n, int
 {
     if (!ctx) return SDE_ERR_INVALID;
     ctx->last_error.clear();
-    return histogram_impl(ctx, winding, n, x0, n_bins, counts, static_cast<hipStream_t>(hip_stream));
+    return histogram_impl(ctx, winding, n, n, 1, x0, n_bins, counts, static_cast<hipStream_t>(hip_stream));
+}
+
+int sde_position_histograms(sde_ctx* ctx, const int32_t* winding, uint64_t n, uint64_t pitch, uint64_t n_rows,
+                            int64_t x0, uint32_t n_bins, uint64_t* counts, void* hip_stream)
+{
+    if (!ctx) return SDE_ERR_INVALID;
+    ctx->last_error.clear();
+    return histogram_impl(ctx, winding, n, pitch, n_rows, x0, n_bins, counts, static_cast<hipStream_t>(hip_stream));
 }
 
 int sde_debug_philox(sde_ctx* ctx, uint64_t seed, uint32_t tag, uint32_t a, uint32_t b,

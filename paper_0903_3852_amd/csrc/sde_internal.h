@@ -138,6 +138,9 @@ int step_counter(sde_ctx* ctx, uint64_t** out);
 int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run,
                       float* theta, int32_t* winding, float* v, double* acc, double* point_sums,
                       hipStream_t stream);
+int jj_integrate_recorded_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run,
+                               float* theta, int32_t* winding, float* v, double* acc, double* point_sums,
+                               uint32_t record_every, uint64_t n_rows, int32_t* rec_winding, hipStream_t stream);
 int jj_integrate_f64_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run,
                           double* theta, int32_t* winding, double* v, double* acc, double* point_sums,
                           hipStream_t stream);
@@ -147,8 +150,8 @@ int debug_gauss_impl(sde_ctx* ctx, uint64_t seed, uint32_t tag, uint32_t a, uint
                      uint64_t n0, uint64_t n, float* out, hipStream_t stream);
 int observables_impl(sde_ctx* ctx, int kind, const void* in, const uint32_t* counts,
                      uint32_t n_groups, double* host_out, hipStream_t stream);
-int histogram_impl(sde_ctx* ctx, const int32_t* winding, uint64_t n, int64_t x0, uint32_t n_bins, uint64_t* counts,
-                   hipStream_t stream);
+int histogram_impl(sde_ctx* ctx, const int32_t* winding, uint64_t n, uint64_t pitch, uint64_t n_rows, int64_t x0,
+                   uint32_t n_bins, uint64_t* counts, hipStream_t stream);
 int kuramoto_impl(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, float* phi,
                   const float* omega, const float* K, double* r_samples, hipStream_t stream);
 
