@@ -68,6 +68,27 @@ def mf_ops_per_osc_step(heun):
     return NOISE_OPS + stage * (2 if heun else 1) + 2
 
 
+def mfs_ops_per_osc_step(heun):
+    """Streamed mean field per oscillator-step: Philox every step and one
+    Gaussian (log, sqrt, sin or cos); per stage sin + cos at its input and two
+    FP64 conversions and adds; Heun evaluates sin/cos of theta, tt (twice)
+    and theta'; drift, update and wrap."""
+    noise = 60 * W_INT + 5 * W_INT + 3 + 3 * W_TRANS
+    trans = (8 if heun else 4) * W_TRANS
+    sums = (2 if heun else 1) * 2 * 2 * W_INT
+    return noise + trans + sums + (12 if heun else 7)
+
+
+def mfs_bytes_per_osc_step(heun):
+    """HBM bytes per oscillator-step of the streamed mean field: Heun reads
+    theta, omega and writes tt, carry; then reads tt, carry and writes theta
+    (7 words); Euler-Maruyama reads theta, omega and writes theta (3)."""
+    return 4 * (7 if heun else 3)
+
+
+PEAK_HBM = 8.0e12
+
+
 # HBM traffic of the JJ kernel per launch, from profiles/jj_scan_hbm_counters.md
 # (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, copy-calibrated).  Only valid for
 # the kernel source it was measured on.
@@ -472,13 +493,84 @@ def bench_kuramoto(name, args, sde, torch, dev, steps=None, reps=1):
     return rec
 
 
+def bench_fig4(args, sde, torch, dev):
+    """The globally coupled system of Fig. 4: 2^24 identical oscillators
+    (omega = 0), K = 4, D = 1, dt = 0.01, 2000 Heun steps of the mean field
+    (Eq. 3) streamed through HBM; r(t) every 100 steps.  Then the same run in
+    20 calls of 100 steps, each followed by the phase density P(x; t) in 100
+    bins (the figure's time evolution).  The paper's run took about 20 s on
+    its GPU: context, not a target."""
+    cfg = sde_inputs.kuramoto_fig4(n_steps=args.kura_steps or 2000)
+    N, n, M = cfg["N"], cfg["n_steps"], cfg["sample_every"]
+    om = torch.zeros(N, dtype=torch.float32, device=dev)
+    ph = torch.empty((1, N), dtype=torch.float32, device=dev)
+    rs = torch.zeros((1, n // M + 1), dtype=torch.float64, device=dev)
+    ctx = sde.sde_create(0)
+    desc = sde.sde_kuramoto_desc(N, 1, cfg["K"], cfg["D"], cfg["dt"], n, sde.SDE_MEANFIELD, 0)
+    run = sde.make_run(cfg["seed"], sample_every=M)
+    stream = torch.cuda.current_stream()
+    sde.sde_kuramoto_integrate(ctx, sde.sde_kuramoto_desc(N, 1, cfg["K"], cfg["D"], cfg["dt"], 8,
+                                                          sde.SDE_MEANFIELD, 0), run, ph, om, None, None)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(max(args.steps, 1)):
+        s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s.record(stream)
+        sde.sde_kuramoto_integrate(ctx, desc, run, ph, om, None, rs)
+        e.record(stream)
+        torch.cuda.synchronize()
+        times.append(s.elapsed_time(e) / 1e3)
+    streamed = sde.sde_get_stats(ctx)["mf_streamed"]
+    t = float(np.mean(times))
+    single = ph.clone()
+    # the time evolution of the phase density, one histogram per 100 steps
+    nb = 100
+    dens = torch.zeros((n // M + 1, nb + 1), dtype=torch.int64, device=dev)
+    chunk = sde.sde_kuramoto_desc(N, 1, cfg["K"], cfg["D"], cfg["dt"], M, sde.SDE_MEANFIELD, 0)
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record(stream)
+    sde.sde_kuramoto_integrate(ctx, sde.sde_kuramoto_desc(N, 1, cfg["K"], cfg["D"], cfg["dt"], 0,
+                                                          sde.SDE_MEANFIELD, 0), run, ph, om, None, None)
+    sde.sde_phase_histograms(ctx, ph, nb, dens[0:1])
+    for k in range(1, n // M + 1):
+        sde.sde_kuramoto_integrate(ctx, chunk, sde.make_run(cfg["seed"], step0=(k - 1) * M,
+                                                            init=sde.SDE_INIT_FROM_STATE, sample_every=M),
+                                   ph, om, None, None)
+        sde.sde_phase_histograms(ctx, ph, nb, dens[k:k + 1])
+    e.record(stream)
+    torch.cuda.synchronize()
+    t_snap = s.elapsed_time(e) / 1e3
+    sde.sde_check(ctx)
+    sde.sde_destroy(ctx)
+    h = dens.cpu().numpy()[:, :nb] * nb / N
+    r = rs.cpu().numpy()[0]
+    osc_steps = float(N) * n
+    ops, byts = mfs_ops_per_osc_step(True), mfs_bytes_per_osc_step(True)
+    hbm = byts * osc_steps / t
+    alu = ops * osc_steps / t
+    return {"workload": "kuramoto_fig4", "N": N, "R": 1, "omega": 0.0, "K": cfg["K"], "D": cfg["D"],
+            "dt": cfg["dt"], "steps": n, "scheme": "heun", "streamed_through_hbm": bool(streamed),
+            "seconds": t, "osc_steps_per_s": osc_steps / t, "us_per_step": t / n * 1e6,
+            "roofline": {"bound": "hbm", "achieved": hbm / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
+                         "frac": hbm / PEAK_HBM, "traffic": None, "bytes_per_osc_step": byts},
+            "alu": {"achieved": alu / 1e12, "peak": PEAK_FMA_LANES / 1e12, "frac": alu / PEAK_FMA_LANES,
+                    "ops_per_osc_step": ops},
+            "r_t": [round(float(x), 5) for x in r],
+            "r_self_consistency": 0.8314620247541972,
+            "density_snapshots": {"every_steps": M, "bins": nb, "seconds_with_snapshots": t_snap,
+                                  "same_as_single_call": bool(torch.equal(single, ph)),
+                                  "peak_density_at_t": {str(k * M * cfg["dt"]): round(float(h[k].max()), 4)
+                                                        for k in (0, 5, 10, 15, n // M)}},
+            "paper_reported_s": 20.0}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="jj_scan",
-                    choices=["jj_scan", "jj_batch", "jj_surrogate", "jj_fig2"] + sorted(KURA))
+                    choices=["jj_scan", "jj_batch", "jj_surrogate", "jj_fig2", "kuramoto_fig4"] + sorted(KURA))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kuramoto", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -517,6 +609,8 @@ def main():
         out = bench_surrogate(args, sde, torch, dev)
     elif args.workload == "jj_fig2":
         out = bench_fig2(args, sde, torch, dev)
+    elif args.workload == "kuramoto_fig4":
+        out = bench_fig4(args, sde, torch, dev)
     else:
         out = bench_kuramoto(args.workload, args, sde, torch, dev, steps=args.kura_steps, reps=args.steps)
     if args.calibrate_copy:

@@ -278,6 +278,25 @@ int sde_position_histograms(sde_ctx* ctx, const int32_t* winding /* [device] */,
                             uint64_t n_rows, int64_t x0, uint32_t n_bins, uint64_t* counts /* [device] */,
                             void* hip_stream);
 
+/*
+ * Histograms of phases held in revolutions (the density P(x; t) of the
+ * Kuramoto phases in Fig. 4, or of the JJ coordinate within a period): row
+ * r is theta[r * pitch .. r * pitch + n - 1] (e.g. the R realizations of a
+ * Kuramoto state with pitch = N) and counts[r][0 .. n_bins] receives
+ *   counts[r][b]       theta in [b / n_bins, (b + 1) / n_bins), b < n_bins
+ *                      (theta = 1 counts in the last bin),
+ *   counts[r][n_bins]  theta outside [0, 1] or NaN.
+ * The bin is floor(theta * n_bins) with the product formed in FP64 (exact),
+ * so it is reproducible bit for bit.  counts: [device] uint64
+ * [n_rows][n_bins + 1], overwritten by kernels (graph-safe).  pitch >= n
+ * when n_rows > 1.  Asynchronous on `hip_stream`.  Errors: SDE_ERR_INVALID
+ * for NULL counts, NULL theta with n > 0, n_bins = 0 or n_bins > 2^24,
+ * n_rows = 0 or n_rows > 2^32, pitch < n with several rows, a misaligned
+ * pointer.
+ */
+int sde_phase_histograms(sde_ctx* ctx, const float* theta /* [device] */, uint64_t n, uint64_t pitch,
+                         uint64_t n_rows, uint32_t n_bins, uint64_t* counts /* [device] */, void* hip_stream);
+
 /* ---- learned surrogate for the mean velocity <v> ------------------------- */
 /*
  * An ensemble of small fully connected networks maps the parameters of a
@@ -364,8 +383,12 @@ enum {
     SDE_OPT_GRAPHS = 2,   /* 1 (default): record each call's launch sequence once in */
                           /* a HIP graph keyed by its arguments and replay it; 0:    */
                           /* launch kernels directly                                 */
-    SDE_OPT_JJ_PPT = 3    /* Josephson-junction paths per lane: 0 (default) = tuned, */
+    SDE_OPT_JJ_PPT = 3,   /* Josephson-junction paths per lane: 0 (default) = tuned, */
                           /* or 1, 2, 4 to force                                     */
+    SDE_OPT_KURA_MF = 4   /* mean-field variant: 0 (default) = registers when the    */
+                          /* realization fits (N <= 2^20 on 256 CUs), else streamed  */
+                          /* through HBM; 1 = always streamed; 2 = always registers  */
+                          /* (SDE_ERR_UNSUPPORTED when N does not fit)               */
 };
 /* Sets an option of the context.  SDE_ERR_INVALID for an unknown option or
  * value. */
@@ -382,6 +405,9 @@ typedef struct {
     int32_t graphs_cached;   /* HIP graphs held by the context                        */
     double tune_ms;          /* time spent tuning in the last call                    */
     uint64_t work_items;     /* work items (point, path chunk) of the last JJ call    */
+    int32_t mf_streamed;     /* the last Kuramoto mean-field call streamed the state  */
+                             /* through HBM (1) or held it in registers (0)           */
+    int32_t reserved;
 } sde_stats;
 /* Statistics of the last integration call on `ctx`. */
 int sde_get_stats(const sde_ctx* ctx, sde_stats* out);

@@ -26,11 +26,11 @@ SDE_MEANFIELD, SDE_TILED, SDE_DENSE_FP32, SDE_DENSE_BF16X3, SDE_DENSE_FP16X3 = 0
 SDE_TAG_NOISE, SDE_TAG_INIT = 0, 1
 SDE_POTENTIAL_SIN, SDE_POTENTIAL_SIN2PI = 0, 1
 SDE_OBS_MEAN_F32, SDE_OBS_MEAN_F64, SDE_OBS_MEANSQ_F32, SDE_OBS_ORDER = 0, 1, 2, 3
-SDE_OPT_AUTOTUNE, SDE_OPT_GRAPHS, SDE_OPT_JJ_PPT = 1, 2, 3
+SDE_OPT_AUTOTUNE, SDE_OPT_GRAPHS, SDE_OPT_JJ_PPT, SDE_OPT_KURA_MF = 1, 2, 3, 4
 
 EXPORTS = ["sde_create", "sde_destroy", "sde_strerror", "sde_last_error", "sde_check",
            "sde_jj_integrate", "sde_jj_integrate_f64", "sde_jj_integrate_recorded", "sde_kuramoto_integrate",
-           "sde_observables", "sde_position_histogram", "sde_position_histograms",
+           "sde_observables", "sde_position_histogram", "sde_position_histograms", "sde_phase_histograms",
            "sde_debug_philox", "sde_debug_gauss", "sde_set_option", "sde_set_tune_cache",
            "sde_get_stats", "sde_surrogate_create", "sde_surrogate_destroy",
            "sde_surrogate_param_count", "sde_surrogate_set_params", "sde_surrogate_get_params",
@@ -62,7 +62,8 @@ class sde_run(ctypes.Structure):
 class sde_stats(ctypes.Structure):
     _fields_ = [("graph_replayed", ctypes.c_int32), ("tuned", ctypes.c_int32),
                 ("jj_paths_per_lane", ctypes.c_int32), ("graphs_cached", ctypes.c_int32),
-                ("tune_ms", ctypes.c_double), ("work_items", ctypes.c_uint64)]
+                ("tune_ms", ctypes.c_double), ("work_items", ctypes.c_uint64),
+                ("mf_streamed", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class sde_surrogate_scaling(ctypes.Structure):
@@ -131,6 +132,8 @@ def lib():
         L.sde_position_histogram.restype = i32
         L.sde_position_histograms.argtypes = [vp, vp, u64, u64, u64, ctypes.c_int64, u32, vp, vp]
         L.sde_position_histograms.restype = i32
+        L.sde_phase_histograms.argtypes = [vp, vp, u64, u64, u64, u32, vp, vp]
+        L.sde_phase_histograms.restype = i32
         L.sde_debug_philox.argtypes = [vp, u64, u32, u32, u32, u64, u64, vp, vp]
         L.sde_debug_philox.restype = i32
         L.sde_debug_gauss.argtypes = [vp, u64, u32, u32, u32, u64, u64, vp, vp]
@@ -338,6 +341,18 @@ def sde_position_histograms(ctx, winding, x0, n_bins, counts, n=None, stream=Non
     return _check(ctx, lib().sde_position_histograms(ctx, _ptr(winding), int(n), int(winding.stride(0)),
                                                      int(n_rows), int(x0), int(n_bins), _ptr(counts),
                                                      _stream(stream)))
+
+
+def sde_phase_histograms(ctx, theta, n_bins, counts, n=None, stream=None):
+    """Row-wise phase histograms of a device float32 tensor theta [n_rows,
+    pitch] (revolutions; the first n entries of each row, default all) into
+    device uint64 counts [n_rows, n_bins + 1] (last column: outside [0, 1])."""
+    if theta.dim() == 1:
+        theta = theta.view(1, -1)
+    n_rows, pitch = theta.shape
+    n = pitch if n is None else n
+    return _check(ctx, lib().sde_phase_histograms(ctx, _ptr(theta), int(n), int(theta.stride(0)), int(n_rows),
+                                                  int(n_bins), _ptr(counts), _stream(stream)))
 
 
 def sde_debug_philox(ctx, seed, tag, a, b, ctr0_first, n_blocks, dev_out, stream=None):

@@ -68,7 +68,8 @@ struct MFArgs {
 // exceeded the spin bound (the error flag is then set).
 constexpr uint32_t kMFWordsPerGroup = 4;
 
-__device__ __forceinline__ bool mf_exchange(const MFArgs& A, uint32_t r, uint32_t w, uint32_t epoch, double s,
+template <typename Args>
+__device__ __forceinline__ bool mf_exchange(const Args& A, uint32_t r, uint32_t w, uint32_t epoch, double s,
                                             double c, double* lds, uint32_t* words, int* lds_ok, double& S,
                                             double& C)
 {
@@ -241,6 +242,152 @@ __global__ __launch_bounds__(kMFThreads, 1) void kuramoto_mf_kernel(MFArgs A)
     }
     if (__ballot(bad) != 0 && (threadIdx.x & (kWave - 1)) == 0) atomicOr(A.flag, 1);
     (void)ok;
+}
+
+// ------------------------------------------------------ MF, streamed ------
+// The mean field for realizations too large for registers (beyond 256
+// workgroups x 4096 oscillators, e.g. the 2^24 identical oscillators of
+// Fig. 4): the same cooperative launch and exchange, but every workgroup
+// streams its slice of theta through HBM at every stage.  Heun: the
+// predictor pass reads theta and omega and writes the predictor tt and
+//   carry = theta + dt/(4 pi) (F1 + omega) + noise,
+// so that the corrector pass needs only tt and carry:
+//   theta' = carry + dt/(4 pi) (K/N) (cos tt S2 - sin tt C2)
+// (28 bytes per oscillator-step; Euler-Maruyama 12).  The noise is component
+// n & 3 of the Gaussians of Philox block n >> 2, regenerated every step: the
+// same stream the register-resident kernel draws once per block.
+struct MFSArgs {
+    float* theta;            // [R][N] revolutions, in/out (this launch's realizations)
+    const float* omega;      // [N]
+    float* tilde;            // [R][N] predictor (Heun)
+    float* carry;            // [R][N] theta + dt/(4 pi) (F1 + omega) + noise (Heun)
+    double* r_samples;       // [R][n_samples] or null
+    uint64_t* slots;         // exchange words, as MFArgs
+    int* flag;
+    uint32_t N, R, G, M;
+    uint32_t r_base;
+    uint32_t chunk;          // oscillators per workgroup slice
+    uint64_t step0, n_steps, n_samples;
+    uint32_t key0, key1;
+    float omega_scale, hdt2pi, kn, c2;
+    uint32_t spin_limit;
+};
+
+// Each pass takes kMFSBatch oscillators per lane per iteration (stride
+// kMFThreads), all loads first, to keep several memory requests in flight.
+constexpr int kMFSBatch = 4;
+
+template <int SCHEME>
+__global__ __launch_bounds__(kMFThreads, 1) void kuramoto_mfs_kernel(MFSArgs A)
+{
+    __shared__ double lds[2 * kMFThreads / kWave];
+    __shared__ uint32_t words[kMFWordsPerGroup * kMaxMFGroups];
+    __shared__ int lds_ok;
+    if (threadIdx.x == 0) lds_ok = 1;  // made visible by the exchange's first barrier
+    const uint32_t r = blockIdx.x / A.G, w = blockIdx.x % A.G;
+    const uint64_t N = A.N;
+    const uint64_t i0 = (uint64_t)w * A.chunk, i1 = std::min<uint64_t>(N, i0 + A.chunk);
+    float* th = A.theta + (uint64_t)r * N;
+    float* tl = A.tilde + (uint64_t)r * N;
+    float* cy = A.carry + (uint64_t)r * N;
+    const uint32_t rr = A.r_base + r;
+    constexpr uint64_t kStep = (uint64_t)kMFSBatch * kMFThreads;
+    uint32_t epoch = 0;
+    auto exchange = [&](double s, double c, double& S, double& C) -> bool {
+        if (!mf_exchange(A, r, w, epoch, s, c, lds, words, &lds_ok, S, C)) return false;
+        ++epoch;
+        return true;
+    };
+    double s = 0.0, c = 0.0, S, C;
+    for (uint64_t b = i0 + threadIdx.x; b < i1; b += kStep) {
+        float t[kMFSBatch];
+#pragma unroll
+        for (int k = 0; k < kMFSBatch; ++k) {
+            const uint64_t i = b + (uint64_t)k * kMFThreads;
+            t[k] = i < i1 ? th[i] : 0.f;
+        }
+#pragma unroll
+        for (int k = 0; k < kMFSBatch; ++k)
+            if (b + (uint64_t)k * kMFThreads < i1) {
+                s += (double)sin_rev(t[k]);
+                c += (double)cos_rev(t[k]);
+            }
+    }
+    if (!exchange(s, c, S, C)) return;
+    const double invN = 1.0 / (double)N;
+    uint64_t n = A.step0, local = 0;
+    const uint64_t n_end = A.step0 + A.n_steps;
+    for (;;) {
+        if (A.r_samples && local % A.M == 0 && w == 0 && threadIdx.x == 0)
+            A.r_samples[(uint64_t)r * A.n_samples + local / A.M] = std::sqrt(S * S + C * C) * invN;
+        if (n == n_end) break;
+        const uint32_t blk = (uint32_t)(n >> 2), j = (uint32_t)n & 3u;
+        float Sf = (float)S, Cf = (float)C;
+        s = 0.0;
+        c = 0.0;
+        // predictor (Heun) or the whole step (Euler-Maruyama)
+        for (uint64_t b = i0 + threadIdx.x; b < i1; b += kStep) {
+            float t0[kMFSBatch], om[kMFSBatch];
+#pragma unroll
+            for (int k = 0; k < kMFSBatch; ++k) {
+                const uint64_t i = b + (uint64_t)k * kMFThreads;
+                t0[k] = i < i1 ? th[i] : 0.f;
+                om[k] = i < i1 ? A.omega[i] : 0.f;
+            }
+#pragma unroll
+            for (int k = 0; k < kMFSBatch; ++k) {
+                const uint64_t i = b + (uint64_t)k * kMFThreads;
+                if (i >= i1) continue;
+                const float F1 = fmaf(A.kn, fmaf(cos_rev(t0[k]), Sf, -sin_rev(t0[k]) * Cf), om[k]);
+                const float ns =
+                    gauss1_scaled(U4{blk, (uint32_t)i, rr, (uint32_t)SDE_TAG_NOISE}, A.key0, A.key1, A.c2, j);
+                const float tt = fmaf(A.omega_scale, F1, t0[k]) + ns;
+                float u;
+                if (SCHEME == SDE_HEUN) {
+                    tl[i] = tt;
+                    cy[i] = fmaf(A.hdt2pi, F1 + om[k], t0[k]) + ns;
+                    u = tt;
+                } else {
+                    u = tt - floorf(tt);
+                    th[i] = u;
+                }
+                s += (double)sin_rev(u);
+                c += (double)cos_rev(u);
+            }
+        }
+        if (!exchange(s, c, S, C)) return;
+        if (SCHEME == SDE_HEUN) {
+            Sf = (float)S;
+            Cf = (float)C;
+            s = 0.0;
+            c = 0.0;
+            for (uint64_t b = i0 + threadIdx.x; b < i1; b += kStep) {
+                float tt[kMFSBatch], cv[kMFSBatch];
+#pragma unroll
+                for (int k = 0; k < kMFSBatch; ++k) {
+                    const uint64_t i = b + (uint64_t)k * kMFThreads;
+                    tt[k] = i < i1 ? tl[i] : 0.f;
+                    cv[k] = i < i1 ? cy[i] : 0.f;
+                }
+#pragma unroll
+                for (int k = 0; k < kMFSBatch; ++k) {
+                    const uint64_t i = b + (uint64_t)k * kMFThreads;
+                    if (i >= i1) continue;
+                    const float t = fmaf(A.hdt2pi, A.kn * fmaf(cos_rev(tt[k]), Sf, -sin_rev(tt[k]) * Cf), cv[k]);
+                    const float u = t - floorf(t);
+                    th[i] = u;
+                    s += (double)sin_rev(u);
+                    c += (double)cos_rev(u);
+                }
+            }
+            if (!exchange(s, c, S, C)) return;
+        }
+        ++n;
+        ++local;
+    }
+    bool bad = false;
+    for (uint64_t i = i0 + threadIdx.x; i < i1; i += kMFThreads) bad |= !isfinite(th[i]);
+    if (__ballot(bad) != 0 && (threadIdx.x & (kWave - 1)) == 0) atomicOr(A.flag, 1);
 }
 
 __global__ void mf_zero_kernel(uint32_t* p, size_t n)
@@ -499,6 +646,73 @@ static void* mf_kernel_ptr()
     return reinterpret_cast<void*>(kuramoto_mf_kernel<OPT, SCHEME>);
 }
 
+// The streamed mean field: G workgroups per realization (as many as fit
+// co-resident, at most kMaxMFGroups), each owning a contiguous slice.
+static int run_meanfield_streamed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, float* phi,
+                                  const float* omega, double* r_samples, uint64_t n_samples, uint32_t M,
+                                  hipStream_t stream)
+{
+    const KuraConsts kc = kuramoto_consts(d);
+    const bool heun = run->scheme == SDE_HEUN;
+    void* kern = heun ? reinterpret_cast<void*>(kuramoto_mfs_kernel<SDE_HEUN>)
+                      : reinterpret_cast<void*>(kuramoto_mfs_kernel<SDE_EULER>);
+    int per_cu = 0;
+    SDE_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kMFThreads, 0));
+    const uint64_t capacity = (uint64_t)std::max(per_cu, 0) * ctx->n_cu;
+    if (capacity == 0) return fail(ctx, SDE_ERR_UNSUPPORTED, "streamed mean-field kernel does not fit a CU");
+    const uint32_t r_per_launch = (uint32_t)std::min<uint64_t>(d->R, capacity);
+    const uint64_t by_lanes = ((uint64_t)d->N + kMFThreads - 1) / kMFThreads;
+    const uint32_t G = (uint32_t)std::max<uint64_t>(
+        1, std::min<uint64_t>({(uint64_t)kMaxMFGroups, capacity / r_per_launch, by_lanes}));
+    const uint32_t chunk = (uint32_t)(((uint64_t)d->N + G - 1) / G);
+    const uint64_t NR = (uint64_t)d->N * d->R;
+    if (run->init == SDE_INIT_PHILOX) {
+        launch_kuramoto_init(phi, d->N, d->R, run->seed, stream);
+        SDE_HIP(ctx, hipGetLastError());
+    }
+    void* work = nullptr;
+    int st = SDE_OK;
+    if (heun && (st = ensure_ws(ctx, kSlotKuraWork, (size_t)2 * NR * sizeof(float), &work))) return st;
+    void* slots = nullptr;
+    const size_t slot_words = (size_t)2 * r_per_launch * G * kMFWordsPerGroup;
+    if ((st = ensure_ws(ctx, kSlotKuraPartials, slot_words * sizeof(uint64_t), &slots))) return st;
+    for (uint32_t r0 = 0; r0 < d->R; r0 += r_per_launch) {
+        const uint32_t nr = std::min(r_per_launch, d->R - r0);
+        const size_t n32 = 2 * slot_words;
+        hipLaunchKernelGGL(mf_zero_kernel, dim3((uint32_t)((n32 + 255) / 256)), dim3(256), 0, stream,
+                           static_cast<uint32_t*>(slots), n32);
+        SDE_HIP(ctx, hipGetLastError());
+        MFSArgs A;
+        A.theta = phi + (uint64_t)r0 * d->N;
+        A.omega = omega;
+        A.tilde = heun ? static_cast<float*>(work) + (uint64_t)r0 * d->N : nullptr;
+        A.carry = heun ? static_cast<float*>(work) + NR + (uint64_t)r0 * d->N : nullptr;
+        A.r_samples = r_samples ? r_samples + (uint64_t)r0 * n_samples : nullptr;
+        A.slots = static_cast<uint64_t*>(slots);
+        A.flag = ctx->flag;
+        A.N = d->N;
+        A.R = nr;
+        A.G = G;
+        A.M = M;
+        A.r_base = r0;
+        A.chunk = chunk;
+        A.step0 = run->step0;
+        A.n_steps = d->n_steps;
+        A.n_samples = n_samples;
+        A.key0 = (uint32_t)run->seed;
+        A.key1 = (uint32_t)(run->seed >> 32);
+        A.omega_scale = kc.omega_scale;
+        A.hdt2pi = kc.hdt2pi;
+        A.kn = kc.kn;
+        A.c2 = kc.c2;
+        A.spin_limit = 1u << 26;
+        void* args[] = {&A};
+        SDE_HIP(ctx, hipLaunchCooperativeKernel(kern, dim3(nr * G), dim3(kMFThreads), args, 0, stream));
+    }
+    ctx->last.mf_streamed = 1;
+    return SDE_OK;
+}
+
 static int run_meanfield(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, float* phi,
                          const float* omega, double* r_samples, uint64_t n_samples, uint32_t M,
                          hipStream_t stream)
@@ -522,7 +736,10 @@ static int run_meanfield(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run
     int per_cu = 0;
     SDE_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kMFThreads, 0));
     const uint64_t capacity = (uint64_t)std::max(per_cu, 0) * ctx->n_cu;
-    if (capacity < G64 || G64 > kMaxMFGroups)
+    const bool fits = capacity >= G64 && G64 <= kMaxMFGroups;
+    if (ctx->kura_mf == 1 || (ctx->kura_mf == 0 && !fits))
+        return run_meanfield_streamed(ctx, d, run, phi, omega, r_samples, n_samples, M, stream);
+    if (!fits)
         return fail(ctx, SDE_ERR_UNSUPPORTED, "mean-field kernel: N = %u needs %llu co-resident workgroups, the "
                     "device holds %llu (at most %u per realization)", d->N, (unsigned long long)G64,
                     (unsigned long long)capacity, kMaxMFGroups);
@@ -654,6 +871,7 @@ static int run_tiled(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* ru
 int kuramoto_impl(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, float* phi, const float* omega,
                   const float* K, double* r_samples, hipStream_t stream)
 {
+    ctx->last = sde_stats{};
     int st = validate(ctx, d, run, phi, omega, K, r_samples);
     if (st) return st;
     const uint32_t M = run->sample_every ? run->sample_every : 100u;

@@ -152,6 +152,64 @@ int histogram_impl(sde_ctx* ctx, const int32_t* winding, uint64_t n, uint64_t pi
     return SDE_OK;
 }
 
+// Histogram of phases in revolutions (the density P(x; t) of Fig. 4): bin
+// b = floor(theta * nb) for theta in [0, 1] (theta = 1 into the last bin),
+// anything else (outside [0, 1], NaN) into bin nb.  theta * nb is formed in
+// FP64, exactly for nb < 2^29, so the bin is the exact floor.  Rows and LDS
+// bins as hist_kernel.
+__global__ __launch_bounds__(256) void phase_hist_kernel(const float* th, uint64_t n, uint64_t pitch, uint64_t rows,
+                                                         uint32_t nb, uint64_t* counts)
+{
+    __shared__ uint32_t h[kHistLds];
+    const bool lds = nb + 1 <= kHistLds;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t r = blockIdx.y; r < rows; r += gridDim.y) {
+        const float* tr = th + r * pitch;
+        uint64_t* cr = counts + r * (uint64_t)(nb + 1);
+        if (lds)
+            for (uint32_t i = threadIdx.x; i < nb + 1; i += blockDim.x) h[i] = 0u;
+        __syncthreads();
+        for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
+            const float t = tr[i];
+            uint32_t b = nb;
+            if (t >= 0.f && t <= 1.f) b = min((uint32_t)floor((double)t * (double)nb), nb - 1);
+            if (lds)
+                atomicAdd(&h[b], 1u);
+            else
+                atomicAdd(reinterpret_cast<unsigned long long*>(cr + b), 1ull);
+        }
+        __syncthreads();
+        if (lds)
+            for (uint32_t i = threadIdx.x; i < nb + 1; i += blockDim.x)
+                if (h[i]) atomicAdd(reinterpret_cast<unsigned long long*>(cr + i), (unsigned long long)h[i]);
+        __syncthreads();
+    }
+}
+
+int phase_histogram_impl(sde_ctx* ctx, const float* theta, uint64_t n, uint64_t pitch, uint64_t n_rows,
+                         uint32_t n_bins, uint64_t* counts, hipStream_t stream)
+{
+    if ((!theta && n) || !counts) return fail(ctx, SDE_ERR_INVALID, "null theta or counts");
+    if (n_bins == 0 || n_bins > (1u << 24)) return fail(ctx, SDE_ERR_INVALID, "n_bins must be in [1, 2^24]");
+    if (n_rows == 0 || n_rows > (1ull << 32)) return fail(ctx, SDE_ERR_INVALID, "n_rows must be in [1, 2^32]");
+    if (n_rows > 1 && pitch < n) return fail(ctx, SDE_ERR_INVALID, "row pitch below the row length");
+    if (!aligned(theta, 4) || !aligned(counts, 8)) return fail(ctx, SDE_ERR_INVALID, "misaligned pointer");
+    const uint64_t nc = (uint64_t)(n_bins + 1) * n_rows;
+    const uint64_t zb = (nc + 255) / 256;
+    if (zb > 0x7fffffffull) return fail(ctx, SDE_ERR_INVALID, "too many counts");
+    hipLaunchKernelGGL(hist_zero_kernel, dim3((uint32_t)zb), dim3(256), 0, stream, counts, nc);
+    if (n) {
+        const uint64_t gy = std::min<uint64_t>(n_rows, 65535);
+        uint64_t gx = std::max<uint64_t>(1, (uint64_t)ctx->n_cu * 4 / gy);
+        gx = std::min<uint64_t>(gx, (n + 255) / 256);
+        gx = std::max<uint64_t>(gx, (n >> 31) + 1);
+        hipLaunchKernelGGL(phase_hist_kernel, dim3((uint32_t)gx, (uint32_t)gy), dim3(256), 0, stream, theta, n,
+                           n_rows > 1 ? pitch : n, n_rows, n_bins, counts);
+    }
+    SDE_HIP(ctx, hipGetLastError());
+    return SDE_OK;
+}
+
 int observables_impl(sde_ctx* ctx, int kind, const void* in, const uint32_t* counts, uint32_t n_groups,
                      double* host_out, hipStream_t stream)
 {

@@ -304,6 +304,10 @@ int sde_set_option(sde_ctx* ctx, int option, int64_t value)
         if (value != 0 && value != 1 && value != 2 && value != 4) break;
         ctx->jj_ppt = (int)value;
         return SDE_OK;
+    case SDE_OPT_KURA_MF:
+        if (value < 0 || value > 2) break;
+        ctx->kura_mf = (int)value;
+        return SDE_OK;
     default: break;
     }
     return fail(ctx, SDE_ERR_INVALID, "option %d: invalid value %lld", option, (long long)value);
@@ -431,6 +435,14 @@ int sde_position_histograms(sde_ctx* ctx, const int32_t* winding, uint64_t n, ui
     if (!ctx) return SDE_ERR_INVALID;
     ctx->last_error.clear();
     return histogram_impl(ctx, winding, n, pitch, n_rows, x0, n_bins, counts, static_cast<hipStream_t>(hip_stream));
+}
+
+int sde_phase_histograms(sde_ctx* ctx, const float* theta, uint64_t n, uint64_t pitch, uint64_t n_rows,
+                         uint32_t n_bins, uint64_t* counts, void* hip_stream)
+{
+    if (!ctx) return SDE_ERR_INVALID;
+    ctx->last_error.clear();
+    return phase_histogram_impl(ctx, theta, n, pitch, n_rows, n_bins, counts, static_cast<hipStream_t>(hip_stream));
 }
 
 int sde_debug_philox(sde_ctx* ctx, uint64_t seed, uint32_t tag, uint32_t a, uint32_t b,

@@ -62,6 +62,7 @@ struct sde_ctx {
     int use_graphs = 1;
     int autotune = 1;
     int jj_ppt = 0;               // 0 = tuned
+    int kura_mf = 0;              // mean-field variant: 0 auto, 1 streamed, 2 registers
     std::map<std::string, int> tune;
     std::string tune_path;
     sde_stats last{};
@@ -152,6 +153,8 @@ int observables_impl(sde_ctx* ctx, int kind, const void* in, const uint32_t* cou
                      uint32_t n_groups, double* host_out, hipStream_t stream);
 int histogram_impl(sde_ctx* ctx, const int32_t* winding, uint64_t n, uint64_t pitch, uint64_t n_rows, int64_t x0,
                    uint32_t n_bins, uint64_t* counts, hipStream_t stream);
+int phase_histogram_impl(sde_ctx* ctx, const float* theta, uint64_t n, uint64_t pitch, uint64_t n_rows,
+                         uint32_t n_bins, uint64_t* counts, hipStream_t stream);
 int kuramoto_impl(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, float* phi,
                   const float* omega, const float* K, double* r_samples, hipStream_t stream);
 

@@ -85,6 +85,14 @@ def kuramoto_uniform(N=65536, R=16):
                 omega=kuramoto_omega(N, 1.0, seed_of(3)), seed=seed_of(3))
 
 
+def kuramoto_fig4(N=1 << 24, n_steps=2000):
+    """The globally coupled system of Fig. 4: 2^24 identical oscillators
+    (omega_i = 0), K = 4, T = 1 (D = 1), one realization, uniform random
+    initial phases, dt = 0.01; r(t) and the phase density every 100 steps."""
+    return dict(N=N, R=1, K=4.0, D=1.0, dt=0.01, n_steps=n_steps, sample_every=100,
+                omega=np.zeros(N, dtype=np.float32), seed=seed_of(6))
+
+
 def dense_coupling(N, K, seed):
     """Symmetric K_ij = (K/N)(1 + 0.5 u_ij), u_ij ~ U[-1,1], zero diagonal, float32."""
     rng = np.random.default_rng(seed + 1)
