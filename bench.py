@@ -564,13 +564,97 @@ def bench_fig4(args, sde, torch, dev):
             "paper_reported_s": 20.0}
 
 
+def _timed(torch, fn):
+    stream = torch.cuda.current_stream()
+    fn()  # warm-up: code object, workspace, tuning, graph
+    torch.cuda.synchronize()
+    s, e = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    s.record(stream)
+    fn()
+    e.record(stream)
+    torch.cuda.synchronize()
+    return s.elapsed_time(e) / 1e3
+
+
+def bench_sweep(args, sde, torch, dev):
+    """Throughput against the number of particles N (Fig. 5), each kernel
+    with and without the small-N remedy of Sec. 6: JJ paths of one point
+    (remedy: many parameter points at once, 2^20 paths in all), the
+    all-pairs sum for one realization (remedy: j split over workgroups), the
+    mean field for one realization (remedy: 16 realizations per launch).
+    GFLOPS use the paper's operation counts per particle-step: 79 (JJ),
+    44 + 6 N (all pairs), 66 (mean field)."""
+    ctx = sde.sde_create(0)
+    out = {"paper_saturation_gflops": {"jj": 450, "kuramoto_mf": 106}}
+    rows = []
+    for lg in range(8, 23, 2):
+        P, n = 1 << lg, 20000
+        pt = sde_inputs.jj_point(n_paths=P, n_steps=n)
+        st = tuple(torch.empty(P, dtype=dt, device=dev)
+                   for dt in (torch.float32, torch.int32, torch.float32, torch.float64))
+        run = sde.make_run(sde_inputs.seed_of(30))
+        t = _timed(torch, lambda: sde.sde_jj_integrate(ctx, [pt], run, *st))
+        ppt = sde.sde_get_stats(ctx)["jj_paths_per_lane"]
+        rec = {"N": P, "seconds": t, "path_steps_per_s": P * n / t, "paper_gflops": 79 * P * n / t / 1e9,
+               "paths_per_lane": ppt}
+        if P < (1 << 20):
+            q = (1 << 20) // P  # the same paths per point, many points
+            pts = [dict(pt, f=0.5 * k / q) for k in range(q)]
+            stb = tuple(torch.empty(1 << 20, dtype=dt, device=dev)
+                        for dt in (torch.float32, torch.int32, torch.float32, torch.float64))
+            tb = _timed(torch, lambda: sde.sde_jj_integrate(ctx, pts, run, *stb))
+            rec["batched"] = {"points": q, "path_steps_per_s": (1 << 20) * n / tb,
+                              "paper_gflops": 79 * (1 << 20) * n / tb / 1e9}
+        rows.append(rec)
+        print(f"sweep jj N={P}: {rec['path_steps_per_s']:.3g} path-steps/s", file=sys.stderr, flush=True)
+    out["jj"] = rows
+
+    def kura(N, R, n, coupling, jsplit=0):
+        cfg = sde_inputs.kuramoto_uniform(N=N, R=R)
+        om = torch.from_numpy(cfg["omega"]).to(dev)
+        ph = torch.empty((R, N), dtype=torch.float32, device=dev)
+        sde.sde_set_option(ctx, sde.SDE_OPT_KURA_JSPLIT, jsplit)
+        desc = sde.sde_kuramoto_desc(N, R, cfg["K"], cfg["D"], cfg["dt"], n, coupling, 0)
+        run = sde.make_run(cfg["seed"])
+        t = _timed(torch, lambda: sde.sde_kuramoto_integrate(ctx, desc, run, ph, om, None, None))
+        return t, sde.sde_get_stats(ctx)
+
+    rows = []
+    for N in (256, 1024, 4096, 16384, 65536):
+        n = 20 if N >= 16384 else 200
+        t1, _ = kura(N, 1, n, sde.SDE_TILED, jsplit=1)
+        tj, stj = kura(N, 1, n, sde.SDE_TILED, jsplit=0)
+        ops = (44 + 6 * N) * N * n
+        rows.append({"N": N, "steps": n, "pairs_per_s": 2.0 * N * N * n / t1, "paper_gflops": ops / t1 / 1e9,
+                     "j_split": {"J": stj["kura_jsplit"], "pairs_per_s": 2.0 * N * N * n / tj,
+                                 "paper_gflops": ops / tj / 1e9}})
+        print(f"sweep tiled N={N}: J=1 {rows[-1]['pairs_per_s']:.3g}, J={stj['kura_jsplit']} "
+              f"{rows[-1]['j_split']['pairs_per_s']:.3g} pairs/s", file=sys.stderr, flush=True)
+    out["kuramoto_all_pairs"] = rows
+    rows = []
+    for lg in range(10, 25, 2):
+        N, n = 1 << lg, 1000
+        t1, st1 = kura(N, 1, n, sde.SDE_MEANFIELD)
+        rec = {"N": N, "steps": n, "osc_steps_per_s": N * n / t1, "paper_gflops": 66 * N * n / t1 / 1e9,
+               "streamed": st1["mf_streamed"]}
+        if N <= (1 << 20):
+            t16, _ = kura(N, 16, n, sde.SDE_MEANFIELD)
+            rec["16_realizations"] = {"osc_steps_per_s": 16 * N * n / t16, "paper_gflops": 66 * 16 * N * n / t16 / 1e9}
+        rows.append(rec)
+        print(f"sweep mean field N={N}: {rec['osc_steps_per_s']:.3g} osc-steps/s", file=sys.stderr, flush=True)
+    out["kuramoto_mean_field"] = rows
+    sde.sde_check(ctx)
+    sde.sde_destroy(ctx)
+    return {"workload": "sweep", "sweep": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="jj_scan",
-                    choices=["jj_scan", "jj_batch", "jj_surrogate", "jj_fig2", "kuramoto_fig4"] + sorted(KURA))
+                    choices=["jj_scan", "jj_batch", "jj_surrogate", "jj_fig2", "kuramoto_fig4", "sweep"] + sorted(KURA))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kuramoto", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -611,6 +695,8 @@ def main():
         out = bench_fig2(args, sde, torch, dev)
     elif args.workload == "kuramoto_fig4":
         out = bench_fig4(args, sde, torch, dev)
+    elif args.workload == "sweep":
+        out = bench_sweep(args, sde, torch, dev)
     else:
         out = bench_kuramoto(args.workload, args, sde, torch, dev, steps=args.kura_steps, reps=args.steps)
     if args.calibrate_copy:

@@ -414,6 +414,58 @@ struct TiledArgs {
     int32_t euler;
 };
 
+// The stage update of oscillator i of realization r from its coupling sum
+// acc = sum_j sin(2 pi (src_j - src_i)).
+__device__ __forceinline__ void tiled_stage_update(const TiledArgs& A, uint32_t r, uint32_t i, float acc, uint64_t n)
+{
+    const uint64_t gi = (uint64_t)r * A.N + i;
+    const float F = fmaf(A.kn, acc, A.omega[i]);
+    const float ns = gauss1_scaled(U4{(uint32_t)(n >> 2), i, r, (uint32_t)SDE_TAG_NOISE}, A.key0, A.key1, A.c2,
+                                   (uint32_t)n & 3u);
+    const float th = A.base[gi];
+    if (A.stage == 1) {
+        const float t = fmaf(A.omega_scale, F, th) + ns;
+        A.dst[gi] = A.euler ? t - floorf(t) : t;
+        if (!A.euler) A.F1[gi] = F;
+    } else {
+        const float t = fmaf(A.hdt2pi, A.F1[gi] + F, th) + ns;
+        A.dst[gi] = t - floorf(t);
+    }
+}
+
+// Coupling sums of OPT oscillators per lane over j in [j_lo, j_hi):
+// tiles of src_j staged in LDS and read by all lanes (broadcast).
+template <int OPT>
+__device__ __forceinline__ void tiled_sums(const float* src, uint32_t N, uint32_t j_lo, uint32_t j_hi, float* tile,
+                                           const float (&mine)[OPT], float (&acc)[OPT])
+{
+    constexpr int TILE = kTileThreads * OPT;
+    for (uint32_t j0 = j_lo; j0 < j_hi; j0 += TILE) {
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < OPT; ++k) {
+            const uint32_t j = j0 + k * kTileThreads + threadIdx.x;
+            tile[k * kTileThreads + threadIdx.x] = j < j_hi ? src[j] : 0.f;
+        }
+        __syncthreads();
+        const uint32_t cnt = j_hi - j0 < (uint32_t)TILE ? j_hi - j0 : (uint32_t)TILE;
+        if (cnt == (uint32_t)TILE) {
+#pragma unroll 8
+            for (int t = 0; t < TILE; ++t) {
+                const float x = tile[t];
+#pragma unroll
+                for (int k = 0; k < OPT; ++k) acc[k] += sin_rev(x - mine[k]);
+            }
+        } else {
+            for (uint32_t t = 0; t < cnt; ++t) {
+                const float x = tile[t];
+#pragma unroll
+                for (int k = 0; k < OPT; ++k) acc[k] += sin_rev(x - mine[k]);
+            }
+        }
+    }
+}
+
 // One stage for OPT oscillators per lane: F_i = omega_i + kn sum_j
 // sin(2 pi (src_j - src_i)) over all j, then the stage's update.
 template <int OPT>
@@ -432,52 +484,51 @@ __global__ __launch_bounds__(kTileThreads) void kuramoto_tiled_kernel(TiledArgs 
         mine[k] = idx[k] < N ? src[idx[k]] : 0.f;
         acc[k] = 0.f;
     }
-    for (uint32_t j0 = 0; j0 < N; j0 += TILE) {
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < OPT; ++k) {
-            const uint32_t j = j0 + k * kTileThreads + threadIdx.x;
-            tile[k * kTileThreads + threadIdx.x] = j < N ? src[j] : 0.f;
-        }
-        __syncthreads();
-        const uint32_t cnt = N - j0 < (uint32_t)TILE ? N - j0 : (uint32_t)TILE;
-        if (cnt == (uint32_t)TILE) {
-#pragma unroll 8
-            for (int t = 0; t < TILE; ++t) {
-                const float x = tile[t];
-#pragma unroll
-                for (int k = 0; k < OPT; ++k) acc[k] += sin_rev(x - mine[k]);
-            }
-        } else {
-            for (uint32_t t = 0; t < cnt; ++t) {
-                const float x = tile[t];
-#pragma unroll
-                for (int k = 0; k < OPT; ++k) acc[k] += sin_rev(x - mine[k]);
-            }
-        }
-    }
+    tiled_sums<OPT>(src, N, 0, N, tile, mine, acc);
     const uint64_t n = load_uniform(A.nbase) + A.k;
-    const uint32_t j = (uint32_t)n & 3u;
 #pragma unroll
-    for (int k = 0; k < OPT; ++k) {
-        if (idx[k] >= N) continue;
-        const uint64_t gi = (uint64_t)r * N + idx[k];
-        const float F = fmaf(A.kn, acc[k], A.omega[idx[k]]);
-        const float ns = gauss1_scaled(U4{(uint32_t)(n >> 2), idx[k], r, (uint32_t)SDE_TAG_NOISE}, A.key0, A.key1, A.c2, j);
-        const float th = A.base[gi];
-        if (A.stage == 1) {
-            const float t = fmaf(A.omega_scale, F, th) + ns;
-            A.dst[gi] = A.euler ? t - floorf(t) : t;
-            if (!A.euler) A.F1[gi] = F;
-        } else {
-            const float t = fmaf(A.hdt2pi, A.F1[gi] + F, th) + ns;
-            A.dst[gi] = t - floorf(t);
-        }
-    }
+    for (int k = 0; k < OPT; ++k)
+        if (idx[k] < N) tiled_stage_update(A, r, idx[k], acc[k], n);
 }
 
-// r = |N^-1 sum_j exp(2 pi i theta_j)| of each realization, written to
-// out[r * stride + col].  One workgroup per realization, FP64 sums.
+// Small-N remedy (the paper's suggestion of less work per thread and more
+// threads, Sec. 6): the j range is split into gridDim.z slices of `jlen`;
+// slice z writes its partial sums to part[z][r][i] ...
+template <int OPT>
+__global__ __launch_bounds__(kTileThreads) void kuramoto_tiled_part_kernel(TiledArgs A, float* part, uint32_t jlen)
+{
+    constexpr int TILE = kTileThreads * OPT;
+    __shared__ float tile[TILE];
+    const uint32_t r = blockIdx.y, z = blockIdx.z;
+    const uint32_t N = A.N;
+    const float* src = A.src + (uint64_t)r * N;
+    const uint32_t j_lo = z * jlen, j_hi = min(N, j_lo + jlen);
+    float mine[OPT], acc[OPT];
+    uint32_t idx[OPT];
+#pragma unroll
+    for (int k = 0; k < OPT; ++k) {
+        idx[k] = blockIdx.x * TILE + k * kTileThreads + threadIdx.x;
+        mine[k] = idx[k] < N ? src[idx[k]] : 0.f;
+        acc[k] = 0.f;
+    }
+    tiled_sums<OPT>(src, N, j_lo, j_hi, tile, mine, acc);
+#pragma unroll
+    for (int k = 0; k < OPT; ++k)
+        if (idx[k] < N) part[((uint64_t)z * A.R + r) * N + idx[k]] = acc[k];
+}
+
+// ... and this kernel adds the J partials of each oscillator in slice order
+// (bitwise reproducible) and applies the stage update.
+__global__ __launch_bounds__(256) void kuramoto_tiled_combine_kernel(TiledArgs A, const float* part, uint32_t J)
+{
+    const uint64_t NR = (uint64_t)A.N * A.R;
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= NR) return;
+    float acc = 0.f;
+    for (uint32_t z = 0; z < J; ++z) acc += part[(uint64_t)z * NR + g];
+    tiled_stage_update(A, (uint32_t)(g / A.N), (uint32_t)(g % A.N), acc, load_uniform(A.nbase) + A.k);
+}
+
 __global__ __launch_bounds__(256) void order_parameter_kernel(const float* theta, uint32_t N, double* out,
                                                               uint64_t stride, uint64_t col)
 {
@@ -786,14 +837,41 @@ static int run_meanfield(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run
     return SDE_OK;
 }
 
+// One stage: the whole j range per workgroup (J = 1), or J slices of jlen
+// into `part` and the combining update.
 template <int OPT>
-static int launch_tiled(sde_ctx* ctx, const TiledArgs& A, hipStream_t stream)
+static int launch_tiled(sde_ctx* ctx, const TiledArgs& A, uint32_t J, uint32_t jlen, float* part, hipStream_t stream)
 {
     constexpr uint32_t TILE = kTileThreads * OPT;
-    dim3 grid((A.N + TILE - 1) / TILE, A.R);
-    hipLaunchKernelGGL(kuramoto_tiled_kernel<OPT>, grid, dim3(kTileThreads), 0, stream, A);
+    if (J <= 1) {
+        dim3 grid((A.N + TILE - 1) / TILE, A.R);
+        hipLaunchKernelGGL(kuramoto_tiled_kernel<OPT>, grid, dim3(kTileThreads), 0, stream, A);
+    } else {
+        dim3 grid((A.N + TILE - 1) / TILE, A.R, J);
+        hipLaunchKernelGGL(kuramoto_tiled_part_kernel<OPT>, grid, dim3(kTileThreads), 0, stream, A, part, jlen);
+        const uint64_t NR = (uint64_t)A.N * A.R;
+        hipLaunchKernelGGL(kuramoto_tiled_combine_kernel, dim3((uint32_t)((NR + 255) / 256)), dim3(256), 0, stream, A,
+                           static_cast<const float*>(part), J);
+    }
     SDE_HIP(ctx, hipGetLastError());
     return SDE_OK;
+}
+
+// j slices of the all-pairs sum: forced by the context option, else enough
+// to give about 4 workgroups per CU when the plain launch has fewer than 2;
+// every slice holds at least 64 j.
+static void tiled_split(const sde_ctx* ctx, uint32_t N, uint32_t R, uint32_t tile, uint32_t* J, uint32_t* jlen)
+{
+    const uint64_t wgs = (((uint64_t)N + tile - 1) / tile) * R;
+    uint64_t j = 1;
+    if (ctx->kura_jsplit > 0)
+        j = (uint64_t)ctx->kura_jsplit;
+    else if (wgs < 2 * (uint64_t)ctx->n_cu)
+        j = (4 * (uint64_t)ctx->n_cu + wgs - 1) / wgs;
+    j = std::min<uint64_t>({j, std::max<uint64_t>(1, N / 64), 65535});
+    const uint64_t len = ((uint64_t)N + j - 1) / j;
+    *jlen = (uint32_t)len;
+    *J = (uint32_t)(((uint64_t)N + len - 1) / len);
 }
 
 static int run_tiled(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, float* phi,
@@ -802,14 +880,18 @@ static int run_tiled(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* ru
 {
     const KuraConsts kc = kuramoto_consts(d);
     const uint64_t NR = (uint64_t)d->N * d->R;
+    const int opt = d->N >= 4096 ? 4 : 1;
+    uint32_t J = 1, jlen = d->N;
+    tiled_split(ctx, d->N, d->R, kTileThreads * opt, &J, &jlen);
     void* work = nullptr;
-    int st = ensure_ws(ctx, kSlotKuraWork, (size_t)2 * NR * sizeof(float), &work);
+    int st = ensure_ws(ctx, kSlotKuraWork, (size_t)(2 + (J > 1 ? J : 0)) * NR * sizeof(float), &work);
     if (st) return st;
     uint64_t* nbase = nullptr;
     if ((st = step_counter(ctx, &nbase))) return st;
     float* tilde = static_cast<float*>(work);
     float* F1 = tilde + NR;
-    const int opt = d->N >= 4096 ? 4 : 1;
+    float* part = F1 + NR;
+    ctx->last.kura_jsplit = (int32_t)J;
     TiledArgs A;
     A.omega = omega;
     A.nbase = nbase;
@@ -832,7 +914,7 @@ static int run_tiled(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* ru
             A.src = phi;
             A.base = phi;
             A.dst = tilde;  // every lane reads all of src, so no step writes in place
-            int e = opt == 4 ? launch_tiled<4>(ctx, A, s) : launch_tiled<1>(ctx, A, s);
+            int e = opt == 4 ? launch_tiled<4>(ctx, A, J, jlen, part, s) : launch_tiled<1>(ctx, A, J, jlen, part, s);
             if (e) return e;
             if (A.euler) {
                 hipLaunchKernelGGL(copy_f32_kernel, dim3((uint32_t)((NR + 255) / 256)), dim3(256), 0, s, phi, tilde, NR);
@@ -842,7 +924,7 @@ static int run_tiled(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* ru
             A.src = tilde;
             A.base = phi;
             A.dst = phi;
-            e = opt == 4 ? launch_tiled<4>(ctx, A, s) : launch_tiled<1>(ctx, A, s);
+            e = opt == 4 ? launch_tiled<4>(ctx, A, J, jlen, part, s) : launch_tiled<1>(ctx, A, J, jlen, part, s);
             if (e) return e;
         }
         launch_step_advance(nbase, count, s);
@@ -852,9 +934,9 @@ static int run_tiled(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* ru
     launch_step_set(nbase, run->step0, stream);
     const uint32_t C = chunk_steps(M, d->n_steps, false);
     char key[256];
-    snprintf(key, sizeof key, "tiled|%p|%p|%p|%p|%u|%u|%u|%u|%a|%a|%a|%a|%d|%llu|%u|%llu", (void*)phi, (void*)omega,
-             (void*)r_samples, (void*)work, d->N, d->R, A.key0, A.key1, A.omega_scale, A.hdt2pi, A.kn, A.c2, A.euler,
-             (unsigned long long)run->step0, M, (unsigned long long)n_samples);
+    snprintf(key, sizeof key, "tiled|%p|%p|%p|%p|%u|%u|%u|%u|%a|%a|%a|%a|%d|%llu|%u|%llu|J%u/%u", (void*)phi,
+             (void*)omega, (void*)r_samples, (void*)work, d->N, d->R, A.key0, A.key1, A.omega_scale, A.hdt2pi, A.kn,
+             A.c2, A.euler, (unsigned long long)run->step0, M, (unsigned long long)n_samples, J, jlen);
     const uint64_t full = d->n_steps / C, rem = d->n_steps % C;
     for (uint64_t c = 0; c < full; ++c)
         if ((st = run_recorded(ctx, std::string(key) + "|C" + std::to_string(C), stream,

@@ -63,6 +63,7 @@ struct sde_ctx {
     int autotune = 1;
     int jj_ppt = 0;               // 0 = tuned
     int kura_mf = 0;              // mean-field variant: 0 auto, 1 streamed, 2 registers
+    int kura_jsplit = 0;          // all-pairs j slices: 0 auto, else forced
     std::map<std::string, int> tune;
     std::string tune_path;
     sde_stats last{};
