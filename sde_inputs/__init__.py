@@ -110,6 +110,20 @@ def kuramoto_dense(N=4096, R=256):
                 seed=seed_of(4))
 
 
+def jj_anm_params(n, seed):
+    """(a, omega, f, D, gamma) rows around the paper's Fig. 2 point in its own
+    potential V(x) = sin(2 pi x), where the mean velocity changes sign and
+    magnitude (anomalous response): a ~ U[3.5, 5], omega ~ U[4, 6],
+    f ~ U[-0.3, 0.3], log10 D ~ U[-4, -2], gamma ~ U[0.7, 1.2]."""
+    rng = np.random.default_rng(seed)
+    a = rng.uniform(3.5, 5.0, n)
+    om = rng.uniform(4.0, 6.0, n)
+    f = rng.uniform(-0.3, 0.3, n)
+    D = 10.0 ** rng.uniform(-4.0, -2.0, n)
+    g = rng.uniform(0.7, 1.2, n)
+    return np.stack([a, om, f, D, g], axis=1)
+
+
 def jj_random_params(n, seed):
     """(a, omega, f, D, gamma) rows drawn from the batch distribution."""
     rng = np.random.default_rng(seed)
