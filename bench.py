@@ -725,7 +725,9 @@ def main():
                                                             (out["kernel_ms"] / 1e3))
             out["jj_batch"] = jb
             out["surrogate"] = bench_surrogate(args, sde, torch, dev)
+            out["surrogate_anm"] = bench_surrogate(args, sde, torch, dev, variant="anm")
             out["fig2"] = bench_fig2(args, sde, torch, dev)
+            out["fig4"] = bench_fig4(args, sde, torch, dev)
     elif args.workload == "jj_batch":
         out = bench_jj_batch(args, sde, torch, dev)
     elif args.workload == "jj_surrogate":
