@@ -38,6 +38,7 @@ struct MFArgs {
     const float* omega;      // [N]
     double* r_samples;       // [R][n_samples] or null
     uint64_t* slots;         // [2 parities][R][G][4] tagged words (kMFWordsPerGroup), zero at launch
+    uint64_t* slots2;        // [2 parities][R][8][4] group sums of the tree exchange, zero at launch
     int* flag;               // error flag (NaN state, or a barrier that timed out)
     uint32_t N, R, G, M;
     uint32_t r_base;         // global index of this launch's first realization
@@ -50,6 +51,7 @@ struct MFArgs {
     int32_t init_from_state;
     int32_t xcd_map;         // 1: realization r lives on XCD r / (R / 8)
     uint32_t spin_limit;     // barrier give-up bound (iterations of s_sleep)
+    uint32_t tree;           // two-level exchange (G a multiple of 8)
 };
 
 // Exchange of the per-workgroup FP64 sums (s, c) of stage `epoch` among the
@@ -58,15 +60,75 @@ struct MFArgs {
 //
 // No fences: each workgroup publishes its two doubles as four 64-bit words
 // (32 data bits, 32 bits of tag = epoch + 1) with relaxed agent-scope atomic
-// stores, and lane t < 4G polls word t with relaxed agent-scope atomic loads
+// stores, and lane t polls word t with relaxed agent-scope atomic loads
 // until its tag matches.  A 64-bit atomic is read whole or not at all, so a
 // matching tag certifies its data; nothing else needs ordering.  A release
 // and acquire pair instead costs a write-back and an invalidation of the
-// L2 on this multi-XCD part at every stage.  Two parities of slots: a
-// workgroup can only publish epoch e + 2 after every workgroup published
-// e + 1, i.e. after all of them read epoch e.  Returns false if a wait
-// exceeded the spin bound (the error flag is then set).
+// L2 on this multi-XCD part at every stage.
+//
+// Flat (A.tree = 0): every workgroup polls all 4G words and adds the G
+// pairs in workgroup order.  Tree (A.tree = 1, G a multiple of 8, used when
+// G is large): workgroup w belongs to group w mod 8 (one XCD under the
+// round-robin dispatch); the group's first workgroup polls its G/8 members,
+// adds them in order and publishes the group sum as four words in slots2;
+// every workgroup then polls the 8 group sums and adds them in group order.
+// That replaces 4G polled words per workgroup by 32 (and 4G/8 for the
+// leaders) at the price of a second round trip.
+//
+// Two parities of slots (and of slots2): a workgroup can only publish epoch
+// e + 2 after every workgroup published e + 1, i.e. after all of them read
+// epoch e -- in the tree, publishing level-one words of e + 2 requires the
+// group sums of e + 1, which require every workgroup's e + 1 words.  Returns
+// false if a wait exceeded the spin bound (the error flag is then set).
 constexpr uint32_t kMFWordsPerGroup = 4;
+constexpr uint32_t kMFTreeMinGroups = 32;  // tree exchange from this many workgroups per realization
+
+__device__ __forceinline__ void mf_publish(uint64_t* dst, uint64_t tag, double S, double C)
+{
+    const uint64_t bs = (uint64_t)__double_as_longlong(S), bc = (uint64_t)__double_as_longlong(C);
+    __hip_atomic_store(dst + 0, tag | (bs & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(dst + 1, tag | (bs >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(dst + 2, tag | (bc & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(dst + 3, tag | (bc >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Lanes t < n poll the word at addr(t) until it carries `tag`, keeping its
+// data bits in words[t]; returns false (all lanes) on a timed-out wait.
+template <typename Args, typename Addr>
+__device__ __forceinline__ bool mf_poll(const Args& A, uint32_t n, Addr addr, uint64_t tag, uint32_t* words,
+                                        int* lds_ok)
+{
+    if (threadIdx.x < n) {
+        const uint64_t* p = addr(threadIdx.x);
+        uint32_t spins = 0;
+        uint64_t v;
+        while (((v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) & 0xffffffff00000000ull) !=
+               tag) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > A.spin_limit) {
+                atomicOr(A.flag, 2);
+                *lds_ok = 0;
+                break;
+            }
+        }
+        words[threadIdx.x] = (uint32_t)v;
+    }
+    __syncthreads();
+    return *lds_ok != 0;
+}
+
+// Sum of the n (S, C) pairs held as word quadruples in words, in order.
+__device__ __forceinline__ void mf_sum_words(const uint32_t* words, uint32_t n, double& S, double& C)
+{
+    S = 0.0;
+    C = 0.0;
+#pragma unroll 4
+    for (uint32_t g = 0; g < n; ++g) {
+        const uint32_t* q = words + g * kMFWordsPerGroup;
+        S += __longlong_as_double((long long)(((uint64_t)q[1] << 32) | q[0]));
+        C += __longlong_as_double((long long)(((uint64_t)q[3] << 32) | q[2]));
+    }
+}
 
 template <typename Args>
 __device__ __forceinline__ bool mf_exchange(const Args& A, uint32_t r, uint32_t w, uint32_t epoch, double s,
@@ -90,38 +152,32 @@ __device__ __forceinline__ bool mf_exchange(const Args& A, uint32_t r, uint32_t 
             Sw += lds[2 * k];
             Cw += lds[2 * k + 1];
         }
-        const uint64_t bs = (uint64_t)__double_as_longlong(Sw), bc = (uint64_t)__double_as_longlong(Cw);
-        uint64_t* mine = slot + (uint64_t)w * kMFWordsPerGroup;
-        __hip_atomic_store(mine + 0, tag | (bs & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(mine + 1, tag | (bs >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(mine + 2, tag | (bc & 0xffffffffull), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __hip_atomic_store(mine + 3, tag | (bc >> 32), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        mf_publish(slot + (uint64_t)w * kMFWordsPerGroup, tag, Sw, Cw);
     }
-    if (threadIdx.x < kMFWordsPerGroup * A.G) {
-        uint32_t spins = 0;
-        uint64_t v;
-        while (((v = __hip_atomic_load(slot + threadIdx.x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) &
-                0xffffffff00000000ull) != tag) {
-            __builtin_amdgcn_s_sleep(1);
-            if (++spins > A.spin_limit) {
-                atomicOr(A.flag, 2);
-                *lds_ok = 0;
-                break;
-            }
+    if (!A.tree) {
+        if (!mf_poll(A, kMFWordsPerGroup * A.G, [&](uint32_t t) { return slot + t; }, tag, words, lds_ok))
+            return false;
+        mf_sum_words(words, A.G, S, C);
+        __syncthreads();  // words and lds are rewritten by the next exchange
+        return true;
+    }
+    const uint32_t x = w & 7u, g = A.G >> 3;
+    uint64_t* slot2 = A.slots2 + ((uint64_t)(epoch & 1u) * A.R + r) * 8 * kMFWordsPerGroup;
+    if (w < 8) {  // group leader: members x, x + 8, x + 16, ...
+        if (!mf_poll(A, kMFWordsPerGroup * g,
+                     [&](uint32_t t) { return slot + (uint64_t)(x + 8 * (t >> 2)) * kMFWordsPerGroup + (t & 3u); },
+                     tag, words, lds_ok))
+            return false;
+        if (threadIdx.x == 0) {
+            double Sx, Cx;
+            mf_sum_words(words, g, Sx, Cx);
+            mf_publish(slot2 + (uint64_t)x * kMFWordsPerGroup, tag, Sx, Cx);
         }
-        words[threadIdx.x] = (uint32_t)v;
     }
+    uint32_t* w2 = words + kMFWordsPerGroup * kMaxMFGroups / 2;
+    if (!mf_poll(A, 8 * kMFWordsPerGroup, [&](uint32_t t) { return slot2 + t; }, tag, w2, lds_ok)) return false;
+    mf_sum_words(w2, 8, S, C);
     __syncthreads();
-    if (!*lds_ok) return false;
-    S = 0.0;
-    C = 0.0;
-#pragma unroll 4
-    for (uint32_t g = 0; g < A.G; ++g) {
-        const uint32_t* q = words + g * kMFWordsPerGroup;
-        S += __longlong_as_double((long long)(((uint64_t)q[1] << 32) | q[0]));
-        C += __longlong_as_double((long long)(((uint64_t)q[3] << 32) | q[2]));
-    }
-    __syncthreads();  // words and lds are rewritten by the next exchange
     return true;
 }
 
@@ -263,6 +319,7 @@ struct MFSArgs {
     float* carry;            // [R][N] theta + dt/(4 pi) (F1 + omega) + noise (Heun)
     double* r_samples;       // [R][n_samples] or null
     uint64_t* slots;         // exchange words, as MFArgs
+    uint64_t* slots2;
     int* flag;
     uint32_t N, R, G, M;
     uint32_t r_base;
@@ -271,6 +328,7 @@ struct MFSArgs {
     uint32_t key0, key1;
     float omega_scale, hdt2pi, kn, c2;
     uint32_t spin_limit;
+    uint32_t tree;
 };
 
 // Each pass takes kMFSBatch oscillators per lane per iteration (stride
@@ -726,14 +784,17 @@ static int run_meanfield_streamed(sde_ctx* ctx, const sde_kuramoto_desc* d, cons
     if (heun && (st = ensure_ws(ctx, kSlotKuraWork, (size_t)2 * NR * sizeof(float), &work))) return st;
     void* slots = nullptr;
     const size_t slot_words = (size_t)2 * r_per_launch * G * kMFWordsPerGroup;
-    if ((st = ensure_ws(ctx, kSlotKuraPartials, slot_words * sizeof(uint64_t), &slots))) return st;
+    const size_t slot2_words = (size_t)2 * r_per_launch * 8 * kMFWordsPerGroup;
+    if ((st = ensure_ws(ctx, kSlotKuraPartials, (slot_words + slot2_words) * sizeof(uint64_t), &slots))) return st;
     for (uint32_t r0 = 0; r0 < d->R; r0 += r_per_launch) {
         const uint32_t nr = std::min(r_per_launch, d->R - r0);
-        const size_t n32 = 2 * slot_words;
+        const size_t n32 = 2 * (slot_words + slot2_words);
         hipLaunchKernelGGL(mf_zero_kernel, dim3((uint32_t)((n32 + 255) / 256)), dim3(256), 0, stream,
                            static_cast<uint32_t*>(slots), n32);
         SDE_HIP(ctx, hipGetLastError());
         MFSArgs A;
+        A.slots2 = static_cast<uint64_t*>(slots) + slot_words;
+        A.tree = (G >= kMFTreeMinGroups && G % 8 == 0) ? 1u : 0u;
         A.theta = phi + (uint64_t)r0 * d->N;
         A.omega = omega;
         A.tilde = heun ? static_cast<float*>(work) + (uint64_t)r0 * d->N : nullptr;
@@ -799,16 +860,19 @@ static int run_meanfield(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run
 
     void* slots = nullptr;
     const size_t slot_words = (size_t)2 * r_per_launch * G * kMFWordsPerGroup;
-    int st = ensure_ws(ctx, kSlotKuraPartials, slot_words * sizeof(uint64_t), &slots);
+    const size_t slot2_words = (size_t)2 * r_per_launch * 8 * kMFWordsPerGroup;
+    int st = ensure_ws(ctx, kSlotKuraPartials, (slot_words + slot2_words) * sizeof(uint64_t), &slots);
     if (st) return st;
     for (uint32_t r0 = 0; r0 < d->R; r0 += r_per_launch) {
         const uint32_t nr = std::min(r_per_launch, d->R - r0);
         // tags start at 1: zeroed slots never match
-        const size_t n32 = 2 * slot_words;
+        const size_t n32 = 2 * (slot_words + slot2_words);
         hipLaunchKernelGGL(mf_zero_kernel, dim3((uint32_t)((n32 + 255) / 256)), dim3(256), 0, stream,
                            static_cast<uint32_t*>(slots), n32);
         SDE_HIP(ctx, hipGetLastError());
         MFArgs A;
+        A.slots2 = static_cast<uint64_t*>(slots) + slot_words;
+        A.tree = (G >= kMFTreeMinGroups && G % 8 == 0) ? 1u : 0u;
         A.theta = phi + (uint64_t)r0 * d->N;
         A.omega = omega;
         A.r_samples = r_samples ? r_samples + (uint64_t)r0 * n_samples : nullptr;

@@ -73,6 +73,24 @@ def test_streamed_first_100_steps(gpu, scheme, N, R):
     np.testing.assert_allclose(rs.cpu().numpy(), rref, rtol=0, atol=1e-6)
 
 
+@pytest.mark.parametrize("streamed", [True, False])
+def test_tree_exchange_vs_oracle(gpu, streamed):
+    """N = 2^17, 2 realizations: 32 (registers) or 128 (streamed) workgroups
+    per realization, so the sums go through the two-level exchange (group
+    leaders, then the 8 group sums); first 100 steps against the oracle."""
+    N, R = 1 << 17, 2
+    cfg = sde_inputs.kuramoto_uniform(N=N, R=R)
+    for scheme in (0, 1):
+        ph, rs = _run(gpu, N, R, cfg["K"], cfg["D"], cfg["dt"], 100, scheme, cfg["seed"], cfg["omega"],
+                      streamed=streamed)
+        ref, rref = oracle.kuramoto_integrate(N, R, cfg["K"], cfg["D"], cfg["dt"], 100, 100, oracle.MEANFIELD,
+                                              scheme, cfg["seed"], cfg["omega"].astype(np.float64))
+        err = _circ_err(ph.cpu().numpy(), ref)
+        print(f"tree exchange, streamed {streamed}, scheme {scheme}: max phase error {err.max():.2e}")
+        assert err.max() <= 1e-5
+        np.testing.assert_allclose(rs.cpu().numpy(), rref, rtol=0, atol=1e-6)
+
+
 def test_streamed_matches_register_resident(gpu):
     """Both variants are within 1e-5 of the oracle after 100 steps, so within
     2e-5 of each other (they round differently: the carry form, the slice
