@@ -389,11 +389,14 @@ enum {
                           /* realization fits (N <= 2^20 on 256 CUs), else streamed  */
                           /* through HBM; 1 = always streamed; 2 = always registers  */
                           /* (SDE_ERR_UNSUPPORTED when N does not fit)               */
-    SDE_OPT_KURA_JSPLIT = 5 /* all-pairs (TILED) sum split over j slices per stage, */
+    SDE_OPT_KURA_JSPLIT = 5, /* all-pairs (TILED) sum split over j slices per stage */
                           /* the small-N remedy of Sec. 6: 0 (default) = automatic  */
                           /* (about 4 workgroups per CU when the plain launch has   */
                           /* fewer than 2), 1 = never, J = 2..65535 = J slices (at   */
                           /* least 64 j per slice)                                   */
+    SDE_OPT_KURA_TILE = 6 /* all-pairs oscillators per lane (tile of 256 x OPT      */
+                          /* phases): 0 (default) = tuned per shape class, or 1, 2, */
+                          /* 4 to force                                              */
 };
 /* Sets an option of the context.  SDE_ERR_INVALID for an unknown option or
  * value. */
@@ -413,6 +416,8 @@ typedef struct {
     int32_t mf_streamed;     /* the last Kuramoto mean-field call streamed the state  */
                              /* through HBM (1) or held it in registers (0)           */
     int32_t kura_jsplit;     /* j slices of the last all-pairs (TILED) call           */
+    int32_t kura_tile;       /* oscillators per lane of the last all-pairs call       */
+    int32_t reserved;
 } sde_stats;
 /* Statistics of the last integration call on `ctx`. */
 int sde_get_stats(const sde_ctx* ctx, sde_stats* out);

@@ -26,7 +26,8 @@ SDE_MEANFIELD, SDE_TILED, SDE_DENSE_FP32, SDE_DENSE_BF16X3, SDE_DENSE_FP16X3 = 0
 SDE_TAG_NOISE, SDE_TAG_INIT = 0, 1
 SDE_POTENTIAL_SIN, SDE_POTENTIAL_SIN2PI = 0, 1
 SDE_OBS_MEAN_F32, SDE_OBS_MEAN_F64, SDE_OBS_MEANSQ_F32, SDE_OBS_ORDER = 0, 1, 2, 3
-SDE_OPT_AUTOTUNE, SDE_OPT_GRAPHS, SDE_OPT_JJ_PPT, SDE_OPT_KURA_MF, SDE_OPT_KURA_JSPLIT = 1, 2, 3, 4, 5
+SDE_OPT_AUTOTUNE, SDE_OPT_GRAPHS, SDE_OPT_JJ_PPT, SDE_OPT_KURA_MF, SDE_OPT_KURA_JSPLIT, SDE_OPT_KURA_TILE = \
+    1, 2, 3, 4, 5, 6
 
 EXPORTS = ["sde_create", "sde_destroy", "sde_strerror", "sde_last_error", "sde_check",
            "sde_jj_integrate", "sde_jj_integrate_f64", "sde_jj_integrate_recorded", "sde_kuramoto_integrate",
@@ -63,7 +64,8 @@ class sde_stats(ctypes.Structure):
     _fields_ = [("graph_replayed", ctypes.c_int32), ("tuned", ctypes.c_int32),
                 ("jj_paths_per_lane", ctypes.c_int32), ("graphs_cached", ctypes.c_int32),
                 ("tune_ms", ctypes.c_double), ("work_items", ctypes.c_uint64),
-                ("mf_streamed", ctypes.c_int32), ("kura_jsplit", ctypes.c_int32)]
+                ("mf_streamed", ctypes.c_int32), ("kura_jsplit", ctypes.c_int32),
+                ("kura_tile", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class sde_surrogate_scaling(ctypes.Structure):

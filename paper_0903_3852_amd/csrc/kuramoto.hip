@@ -21,6 +21,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 
 #include "device_common.h"
@@ -938,24 +939,89 @@ static void tiled_split(const sde_ctx* ctx, uint32_t N, uint32_t R, uint32_t til
     *J = (uint32_t)(((uint64_t)N + len - 1) / len);
 }
 
+static int launch_tiled_opt(sde_ctx* ctx, int opt, const TiledArgs& A, uint32_t J, uint32_t jlen, float* part,
+                            hipStream_t s)
+{
+    return opt == 4 ? launch_tiled<4>(ctx, A, J, jlen, part, s)
+                    : opt == 2 ? launch_tiled<2>(ctx, A, J, jlen, part, s) : launch_tiled<1>(ctx, A, J, jlen, part, s);
+}
+
+// Oscillators per lane of the all-pairs kernel (its tile: 256 x OPT phases
+// in LDS): times one stage of each candidate 1, 2, 4 (with its j split) on
+// copies of the state in the tuning workspace -- the caller's arrays are only
+// read -- and returns the fastest.
+static int tiled_tune(sde_ctx* ctx, const sde_kuramoto_desc* d, const TiledArgs& base, const float* phi,
+                      hipStream_t stream, int* best_opt)
+{
+    const uint64_t NR = (uint64_t)d->N * d->R;
+    uint32_t Jmax = 1;
+    for (int opt : {1, 2, 4}) {
+        uint32_t J, jlen;
+        tiled_split(ctx, d->N, d->R, kTileThreads * opt, &J, &jlen);
+        Jmax = std::max(Jmax, J);
+    }
+    void* ws = nullptr;
+    int st = ensure_ws(ctx, kSlotTune, (size_t)(3 + (Jmax > 1 ? Jmax : 0)) * NR * sizeof(float), &ws);
+    if (st) return st;
+    float* src = static_cast<float*>(ws);
+    float* dst = src + NR;
+    float* F1 = dst + NR;
+    float* part = F1 + NR;
+    SDE_HIP(ctx, hipMemcpyAsync(src, phi, NR * sizeof(float), hipMemcpyDeviceToDevice, stream));
+    TiledArgs A = base;
+    A.src = src;
+    A.base = src;
+    A.dst = dst;
+    A.F1 = F1;
+    A.k = 0;
+    A.stage = 1;
+    A.euler = 0;
+    hipEvent_t e0, e1;
+    SDE_HIP(ctx, hipEventCreate(&e0));
+    SDE_HIP(ctx, hipEventCreate(&e1));
+    double best = 1e300;
+    for (int opt : {1, 2, 4}) {
+        uint32_t J, jlen;
+        tiled_split(ctx, d->N, d->R, kTileThreads * opt, &J, &jlen);
+        float ms = 0.f;
+        for (int rep = 0; rep < 2 && st == SDE_OK; ++rep) {  // the first launch loads the code object
+            if (hipEventRecord(e0, stream) != hipSuccess) st = SDE_ERR_DEVICE;
+            if (!st) st = launch_tiled_opt(ctx, opt, A, J, jlen, part, stream);
+            if (!st && hipEventRecord(e1, stream) != hipSuccess) st = SDE_ERR_DEVICE;
+            if (!st && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms, e0, e1) != hipSuccess))
+                st = SDE_ERR_DEVICE;
+        }
+        if (st) break;
+        if (ms < best) {
+            best = ms;
+            *best_opt = opt;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st == SDE_ERR_DEVICE) return fail(ctx, st, "all-pairs autotuner: HIP event or launch failed");
+    return st;
+}
+
+static int ilog2_u64(uint64_t x)
+{
+    int r = 0;
+    while (x > 1) {
+        x >>= 1;
+        ++r;
+    }
+    return r;
+}
+
 static int run_tiled(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, float* phi,
                      const float* omega, double* r_samples, uint64_t n_samples, uint32_t M,
                      hipStream_t stream)
 {
     const KuraConsts kc = kuramoto_consts(d);
     const uint64_t NR = (uint64_t)d->N * d->R;
-    const int opt = d->N >= 4096 ? 4 : 1;
-    uint32_t J = 1, jlen = d->N;
-    tiled_split(ctx, d->N, d->R, kTileThreads * opt, &J, &jlen);
-    void* work = nullptr;
-    int st = ensure_ws(ctx, kSlotKuraWork, (size_t)(2 + (J > 1 ? J : 0)) * NR * sizeof(float), &work);
-    if (st) return st;
     uint64_t* nbase = nullptr;
-    if ((st = step_counter(ctx, &nbase))) return st;
-    float* tilde = static_cast<float*>(work);
-    float* F1 = tilde + NR;
-    float* part = F1 + NR;
-    ctx->last.kura_jsplit = (int32_t)J;
+    int st = step_counter(ctx, &nbase);
+    if (st) return st;
     TiledArgs A;
     A.omega = omega;
     A.nbase = nbase;
@@ -967,6 +1033,34 @@ static int run_tiled(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* ru
     A.hdt2pi = kc.hdt2pi;
     A.kn = kc.kn;
     A.c2 = kc.c2;
+    // oscillators per lane: forced, cached, or tuned on this call's shape class
+    int opt = ctx->kura_tile;
+    if (!opt) {
+        char key[160];
+        snprintf(key, sizeof key, "tiled|%s|N2^%d|R2^%d|J%d", ctx->arch.c_str(), ilog2_u64(d->N), ilog2_u64(d->R),
+                 ctx->kura_jsplit);
+        if (!tune_lookup(ctx, key, &opt)) {
+            opt = d->N >= 4096 ? 4 : 1;
+            if (ctx->autotune) {
+                const auto t0 = std::chrono::steady_clock::now();
+                launch_step_set(nbase, run->step0, stream);
+                if ((st = tiled_tune(ctx, d, A, phi, stream, &opt))) return st;
+                ctx->last.tuned = 1;
+                ctx->last.tune_ms =
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                tune_store(ctx, key, opt);
+            }
+        }
+    }
+    uint32_t J = 1, jlen = d->N;
+    tiled_split(ctx, d->N, d->R, kTileThreads * opt, &J, &jlen);
+    void* work = nullptr;
+    if ((st = ensure_ws(ctx, kSlotKuraWork, (size_t)(2 + (J > 1 ? J : 0)) * NR * sizeof(float), &work))) return st;
+    float* tilde = static_cast<float*>(work);
+    float* F1 = tilde + NR;
+    float* part = F1 + NR;
+    ctx->last.kura_jsplit = (int32_t)J;
+    ctx->last.kura_tile = opt;
     A.F1 = F1;
     A.euler = run->scheme == SDE_EULER;
     // `count` steps from the device step base, then advance it
@@ -978,7 +1072,7 @@ static int run_tiled(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* ru
             A.src = phi;
             A.base = phi;
             A.dst = tilde;  // every lane reads all of src, so no step writes in place
-            int e = opt == 4 ? launch_tiled<4>(ctx, A, J, jlen, part, s) : launch_tiled<1>(ctx, A, J, jlen, part, s);
+            int e = launch_tiled_opt(ctx, opt, A, J, jlen, part, s);
             if (e) return e;
             if (A.euler) {
                 hipLaunchKernelGGL(copy_f32_kernel, dim3((uint32_t)((NR + 255) / 256)), dim3(256), 0, s, phi, tilde, NR);
@@ -988,7 +1082,7 @@ static int run_tiled(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* ru
             A.src = tilde;
             A.base = phi;
             A.dst = phi;
-            e = opt == 4 ? launch_tiled<4>(ctx, A, J, jlen, part, s) : launch_tiled<1>(ctx, A, J, jlen, part, s);
+            e = launch_tiled_opt(ctx, opt, A, J, jlen, part, s);
             if (e) return e;
         }
         launch_step_advance(nbase, count, s);
@@ -998,9 +1092,9 @@ static int run_tiled(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* ru
     launch_step_set(nbase, run->step0, stream);
     const uint32_t C = chunk_steps(M, d->n_steps, false);
     char key[256];
-    snprintf(key, sizeof key, "tiled|%p|%p|%p|%p|%u|%u|%u|%u|%a|%a|%a|%a|%d|%llu|%u|%llu|J%u/%u", (void*)phi,
+    snprintf(key, sizeof key, "tiled|%p|%p|%p|%p|%u|%u|%u|%u|%a|%a|%a|%a|%d|%llu|%u|%llu|J%u/%u|opt%d", (void*)phi,
              (void*)omega, (void*)r_samples, (void*)work, d->N, d->R, A.key0, A.key1, A.omega_scale, A.hdt2pi, A.kn,
-             A.c2, A.euler, (unsigned long long)run->step0, M, (unsigned long long)n_samples, J, jlen);
+             A.c2, A.euler, (unsigned long long)run->step0, M, (unsigned long long)n_samples, J, jlen, opt);
     const uint64_t full = d->n_steps / C, rem = d->n_steps % C;
     for (uint64_t c = 0; c < full; ++c)
         if ((st = run_recorded(ctx, std::string(key) + "|C" + std::to_string(C), stream,

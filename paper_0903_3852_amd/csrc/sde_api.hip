@@ -312,6 +312,10 @@ int sde_set_option(sde_ctx* ctx, int option, int64_t value)
         if (value < 0 || value > 65535) break;
         ctx->kura_jsplit = (int)value;
         return SDE_OK;
+    case SDE_OPT_KURA_TILE:
+        if (value != 0 && value != 1 && value != 2 && value != 4) break;
+        ctx->kura_tile = (int)value;
+        return SDE_OK;
     default: break;
     }
     return fail(ctx, SDE_ERR_INVALID, "option %d: invalid value %lld", option, (long long)value);

@@ -64,6 +64,7 @@ struct sde_ctx {
     int jj_ppt = 0;               // 0 = tuned
     int kura_mf = 0;              // mean-field variant: 0 auto, 1 streamed, 2 registers
     int kura_jsplit = 0;          // all-pairs j slices: 0 auto, else forced
+    int kura_tile = 0;            // all-pairs oscillators per lane: 0 tuned, else 1, 2, 4
     std::map<std::string, int> tune;
     std::string tune_path;
     sde_stats last{};

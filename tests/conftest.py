@@ -33,6 +33,18 @@ def gpu():
     sde.sde_destroy(ctx)
 
 
+@pytest.fixture(autouse=True)
+def _default_options(request):
+    """The GPU context is shared by the session: put every option a test may
+    set back to its default afterwards."""
+    yield
+    if "gpu" in request.fixturenames:
+        sde, ctx, _ = request.getfixturevalue("gpu")
+        for opt, value in [(sde.SDE_OPT_AUTOTUNE, 1), (sde.SDE_OPT_GRAPHS, 1), (sde.SDE_OPT_JJ_PPT, 0),
+                           (sde.SDE_OPT_KURA_MF, 0), (sde.SDE_OPT_KURA_JSPLIT, 0), (sde.SDE_OPT_KURA_TILE, 0)]:
+            sde.sde_set_option(ctx, opt, value)
+
+
 def rel_err(got, ref):
     """|got - ref| / max(|ref|, 1), elementwise."""
     import numpy as np

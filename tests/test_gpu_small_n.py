@@ -82,3 +82,49 @@ def test_jsplit_option_validation(gpu):
     for bad in (-1, 65536):
         with pytest.raises(sde.SDEError):
             sde.sde_set_option(ctx, sde.SDE_OPT_KURA_JSPLIT, bad)
+
+
+@pytest.mark.parametrize("tile", [1, 2, 4])
+def test_forced_tile_vs_oracle(gpu, tile):
+    """Every all-pairs tile (256 x OPT phases in LDS) against the oracle."""
+    sde, ctx, dev = gpu
+    sde.sde_set_option(ctx, sde.SDE_OPT_KURA_TILE, tile)
+    ph, rs, _, cfg = _tiled(gpu, 3000, 2, 100, 0)
+    assert sde.sde_get_stats(ctx)["kura_tile"] == tile
+    ref, rref = oracle.kuramoto_integrate(3000, 2, cfg["K"], cfg["D"], cfg["dt"], 100, 100, oracle.MEANFIELD, 0, 3,
+                                          cfg["omega"].astype(np.float64))
+    err = _circ_err(ph.cpu().numpy(), ref)
+    print(f"tile {tile}: max phase error {err.max():.2e}")
+    assert err.max() <= 1e-5
+    np.testing.assert_allclose(rs.cpu().numpy(), rref, rtol=0, atol=1e-6)
+
+
+def test_tile_autotuner_reads_only_and_caches(gpu):
+    """The tuner times trial stages on copies: a tuned call equals a call
+    forced to the chosen tile bit for bit, and the next call of the shape
+    class takes the cached choice without tuning."""
+    sde, _, dev = gpu
+    ctx = sde.sde_create(0)  # its own (empty) tune cache
+    try:
+        _tile_autotuner_checks(sde, ctx, dev)
+    finally:
+        sde.sde_destroy(ctx)
+
+
+def _tile_autotuner_checks(sde, ctx, dev):
+    gpu = (sde, ctx, dev)
+    a, ra, _, _ = _tiled(gpu, 8192, 2, 30, 0)
+    st = sde.sde_get_stats(ctx)
+    assert st["tuned"] == 1 and st["kura_tile"] in (1, 2, 4)
+    chosen = st["kura_tile"]
+    print(f"tuned tile {chosen} in {st['tune_ms']:.1f} ms")
+    b, rb, _, _ = _tiled(gpu, 8192, 2, 30, 0)
+    st2 = sde.sde_get_stats(ctx)
+    assert st2["tuned"] == 0 and st2["kura_tile"] == chosen
+    assert torch.equal(a, b) and torch.equal(ra, rb)
+    sde.sde_set_option(ctx, sde.SDE_OPT_KURA_TILE, chosen)
+    c, rc, _, _ = _tiled(gpu, 8192, 2, 30, 0)
+    assert torch.equal(a, c) and torch.equal(ra, rc)
+    for bad in (3, -1, 8):
+        with pytest.raises(sde.SDEError):
+            sde.sde_set_option(ctx, sde.SDE_OPT_KURA_TILE, bad)
