@@ -705,9 +705,9 @@ def main():
                     help="also run a plain 1 GiB device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the JJ scan would shard "
-              "by points across GPUs with no exchange but a final gather, which this build does not "
-              "launch.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library has no "
+              "multi-GPU launch.  The JJ scan would shard by points across GPUs with no exchange but a "
+              "final gather of the per-point sums.", file=sys.stderr)
         sys.exit(2)
 
     import torch
