@@ -87,6 +87,18 @@ def mfs_bytes_per_osc_step(heun):
 
 
 PEAK_HBM = 8.0e12
+# Measured HBM bytes per oscillator-step of the streamed mean field (Fig. 4),
+# from profiles/kuramoto_fig4_hbm_counters.md; valid for that kernel source.
+FIG4_TRAFFIC_PER_OSC_STEP = 28.05
+FIG4_TRAFFIC_SOURCE_SHA1 = "76d7d62508a8bca9b4c3c811577829190842f44b"
+
+
+def _source_sha1(*files):
+    h = hashlib.sha1()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_0903_3852_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
 
 
 # HBM traffic of the JJ kernel per launch, from profiles/jj_scan_hbm_counters.md
@@ -586,11 +598,13 @@ def bench_fig4(args, sde, torch, dev):
     ops, byts = mfs_ops_per_osc_step(True), mfs_bytes_per_osc_step(True)
     hbm = byts * osc_steps / t
     alu = ops * osc_steps / t
+    traffic = (FIG4_TRAFFIC_PER_OSC_STEP * osc_steps
+               if _source_sha1("kuramoto.hip", "device_common.h") == FIG4_TRAFFIC_SOURCE_SHA1 else None)
     return {"workload": "kuramoto_fig4", "N": N, "R": 1, "omega": 0.0, "K": cfg["K"], "D": cfg["D"],
             "dt": cfg["dt"], "steps": n, "scheme": "heun", "streamed_through_hbm": bool(streamed),
             "seconds": t, "osc_steps_per_s": osc_steps / t, "us_per_step": t / n * 1e6,
             "roofline": {"bound": "hbm", "achieved": hbm / 1e9, "peak": PEAK_HBM / 1e9, "unit": "GB/s",
-                         "frac": hbm / PEAK_HBM, "traffic": None, "bytes_per_osc_step": byts},
+                         "frac": hbm / PEAK_HBM, "traffic": traffic, "bytes_per_osc_step": byts},
             "alu": {"achieved": alu / 1e12, "peak": PEAK_FMA_LANES / 1e12, "frac": alu / PEAK_FMA_LANES,
                     "ops_per_osc_step": ops},
             "r_t": [round(float(x), 5) for x in r],
@@ -598,7 +612,7 @@ def bench_fig4(args, sde, torch, dev):
             "density_snapshots": {"every_steps": M, "bins": nb, "seconds_with_snapshots": t_snap,
                                   "same_as_single_call": bool(torch.equal(single, ph)),
                                   "peak_density_at_t": {str(k * M * cfg["dt"]): round(float(h[k].max()), 4)
-                                                        for k in (0, 5, 10, 15, n // M)}},
+                                                        for k in sorted({0, 5, 10, 15, n // M}) if k <= n // M}},
             "paper_reported_s": 20.0}
 
 
