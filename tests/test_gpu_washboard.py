@@ -218,3 +218,28 @@ def test_potential_validation_leaves_outputs(gpu):
             sde.sde_jj_integrate(ctx, arr, sde.make_run(1, sync=1), *st)
         assert e.value.status == sde.SDE_ERR_INVALID
         assert all(torch.count_nonzero(x) == 0 for x in st)
+
+
+def test_fig2_full_size_one_step(gpu):
+    """The Fig. 2 ensemble at its full size (2^19 paths, the benchmark's
+    launch): one step from the oracle's state after 49 steps, every path,
+    FP32 (1e-5) and FP64 (1e-13), against the oracle's step 50."""
+    sde, ctx, dev = gpu
+    pt = dict(sde_inputs.jj_fig2()[0], n_steps=49)
+    seed = sde_inputs.seed_of(20)
+    s49 = oracle.jj_integrate([pt], seed)
+    s50 = oracle.jj_integrate([dict(pt, n_steps=1)], seed, step0=49, state=(s49["phi"], s49["v"], s49["acc"]))
+    n = pt["n_paths"]
+    st = _from_oracle(s49["phi"], s49["v"], dev)
+    st, _ = _run(gpu, [dict(pt, n_steps=1)], seed, step0=49, state=st, sums=False)
+    e32 = max(rel_err(_x(st), s50["phi"]).max(), rel_err(st[2].cpu().double().numpy(), s50["v"]).max())
+    w = np.floor(s49["phi"])
+    st64 = (torch.from_numpy(s49["phi"] - w).to(dev), torch.from_numpy(w.astype(np.int32)).to(dev),
+            torch.from_numpy(s49["v"].copy()).to(dev), torch.zeros(n, dtype=torch.float64, device=dev))
+    sde.sde_jj_integrate_f64(ctx, [dict(pt, n_steps=1)], sde.make_run(seed, step0=49, init=sde.SDE_INIT_FROM_STATE,
+                                                                        sync=1), *st64)
+    x64 = st64[0].cpu().numpy() + st64[1].cpu().numpy().astype(np.float64)
+    e64 = max(rel_err(x64, s50["phi"]).max(), rel_err(st64[2].cpu().numpy(), s50["v"]).max())
+    print(f"Fig. 2 at 2^19 paths, one step: FP32 {e32:.2e}, FP64 {e64:.2e}")
+    assert e32 <= 1e-5
+    assert e64 <= 1e-13
