@@ -45,6 +45,9 @@ struct sde_surrogate {
     size_t work_bytes = 0;
     uint32_t* perm = nullptr;            // device [members][n] sample order of the epoch
     size_t perm_cap = 0;
+    // inference: hidden-layer weights in the FP32 MFMA operand layout
+    float* packed = nullptr;
+    size_t packed_bytes = 0;
 };
 
 namespace sde {
@@ -380,9 +383,7 @@ __global__ void mlp_adam_advance_kernel(uint64_t* t, uint32_t members)
 
 // ------------------------------------------------------------ inference ---
 // Fused ensemble forward for widths w0 -> H -> ... -> H -> 1 with H <= 256.
-constexpr int kInfRows = 128;
 constexpr int kInfH = 256;
-constexpr int kInfK = 16;
 
 struct InferArgs {
     const float* X;          // [n][w0] raw features
@@ -395,98 +396,138 @@ struct InferArgs {
     sde_surrogate_scaling sc;
 };
 
-__global__ __launch_bounds__(256, 1) void mlp_infer_kernel(InferArgs A)
+// FP32 MFMA forward (v_mfma_f32_16x16x4_f32).  Operands of a 16 x 16 block
+// (16 rows or output columns by 16 k) are one 1 KB run: lane l = i % 16 +
+// 16 * (k % 4) holds the float4 of k = k % 4 + {0, 4, 8, 12}, the operands of
+// four consecutive MFMAs.  The hidden weights are packed that way once per
+// call (B(k, c) = W[c][k]); the activations stay in LDS in the same layout, as
+// the A operand of the next layer.
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t frag32_index(uint32_t i, uint32_t k, uint32_t kb16)
+{
+    return (((i >> 4) * kb16 + (k >> 4)) * 64 + ((i & 15u) + 16u * (k & 3u))) * 4 + ((k & 15u) >> 2);
+}
+
+struct PackArgs {
+    const float* params;
+    uint64_t P;
+    uint32_t members, hidden, H, Hp;
+    uint64_t w_off[kMaxLayers];  // of hidden layer 1 + l at index l
+    float* packed;               // [members][hidden][Hp * Hp]
+};
+
+// packed[m][l] (Hp x Hp, zero padded) from the hidden weights W_{l+1} of member m
+__global__ void mlp_pack_hidden_kernel(PackArgs A)
+{
+    const uint64_t per = (uint64_t)A.Hp * A.Hp;
+    const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= (uint64_t)A.members * A.hidden * per) return;
+    const uint32_t m = (uint32_t)(g / (A.hidden * per));
+    const uint32_t l = (uint32_t)((g / per) % A.hidden);
+    const uint32_t e = (uint32_t)(g % per), c = e / A.Hp, k = e % A.Hp;
+    const float* W = A.params + (uint64_t)m * A.P + A.w_off[l];
+    A.packed[((uint64_t)m * A.hidden + l) * per + frag32_index(c, k, A.Hp / 16)] =
+        (c < A.H && k < A.H) ? W[(uint64_t)c * A.H + k] : 0.f;
+}
+
+constexpr uint32_t kInfBlocks = kInfH / 16;  // column blocks of the widest layer
+// Queries per workgroup: one 16-row block per wave, so that two workgroups
+// (68 KB of LDS each) share a CU and one's GELU epilogue overlaps the
+// other's products.
+constexpr uint32_t kInfMRows = 64;
+
+__global__ __launch_bounds__(256, 2) void mlp_infer_mfma_kernel(InferArgs A, const float* packed, uint32_t Hp)
 {
     extern __shared__ float smem[];
-    float* act = smem;                          // [kInfRows][kInfH]
-    float* wt = smem + kInfRows * kInfH;        // [kInfK][kInfH] weight slice (k-major)
-    float* outs = wt + kInfK * kInfH;           // [kInfRows][8] member outputs
-    const uint64_t r0 = (uint64_t)blockIdx.x * kInfRows;
-    const uint32_t tx = threadIdx.x & 15u, ty = threadIdx.x >> 4;  // ty: 8 rows, tx: 16 columns
-    const uint32_t H = A.H;
+    float* act = smem;                      // [kInfMRows x Hp] in the operand layout
+    float* xn = act + kInfMRows * kInfH;    // [kInfMRows][8] normalized features
+    float* outs = xn + kInfMRows * 8;       // [kInfMRows][8] member outputs
+    const uint64_t r0 = (uint64_t)blockIdx.x * kInfMRows;
+    const uint32_t H = A.H, KB = Hp / 16, NB = KB;
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    for (uint32_t e = threadIdx.x; e < kInfMRows * A.w0; e += 256) {
+        const uint32_t row = e / A.w0, j = e % A.w0;
+        const uint64_t gi = r0 + row;
+        xn[row * 8 + j] = gi < A.n ? (A.X[gi * A.w0 + j] - A.sc.in_center[j]) / A.sc.in_scale[j] : 0.f;
+    }
+    __syncthreads();
+    const uint32_t hidden = A.n_layers - 2;
     for (uint32_t mem = 0; mem < A.members; ++mem) {
         const float* prm = A.params + (uint64_t)mem * A.P;
-        // layer 1 from the normalized features
-        {
+        {   // layer 1 from the normalized features
             const float* W = prm + A.w_off[0];
             const float* b = prm + A.b_off[0];
-            for (uint32_t e = threadIdx.x; e < kInfRows * kInfH; e += 256) {
-                const uint32_t row = e / kInfH, col = e % kInfH;
-                const uint64_t gi = r0 + row;
+            for (uint32_t e = threadIdx.x; e < kInfMRows * Hp; e += 256) {
+                const uint32_t row = e / Hp, col = e % Hp;
                 float z = 0.f;
                 if (col < H) {
                     z = b[col];
-                    if (gi < A.n)
-                        for (uint32_t j = 0; j < A.w0; ++j)
-                            z = fmaf(W[col * A.w0 + j], (A.X[gi * A.w0 + j] - A.sc.in_center[j]) / A.sc.in_scale[j], z);
+                    for (uint32_t j = 0; j < A.w0; ++j) z = fmaf(W[col * A.w0 + j], xn[row * 8 + j], z);
                     z = gelu(z);
                 }
-                act[row * kInfH + col] = z;
+                act[frag32_index(row, col, KB)] = z;
             }
             __syncthreads();
         }
-        // hidden layers H -> H, lane block: rows ty*8..+8, columns tx*16..+16
-        for (uint32_t l = 1; l + 1 < A.n_layers; ++l) {
-            const float* W = prm + A.w_off[l];
-            const float* b = prm + A.b_off[l];
-            float acc[8][16];
+        // hidden layers: wave w computes rows 16 w .. 16 w + 15, all columns
+        for (uint32_t l = 0; l < hidden; ++l) {
+            const float* Bp = packed + ((uint64_t)mem * hidden + l) * Hp * Hp;
+            const float* b = prm + A.b_off[l + 1];
+            f32x4_t acc[1][kInfBlocks];
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
+            for (int m = 0; m < 1; ++m)
 #pragma unroll
-                for (int j = 0; j < 16; ++j) acc[i][j] = 0.f;
-            for (uint32_t k0 = 0; k0 < H; k0 += kInfK) {
-                // stage W[:, k0:k0+16] transposed: wt[k][col]
-                for (uint32_t e = threadIdx.x; e < kInfK * H; e += 256) {
-                    const uint32_t col = e / kInfK, kk = e % kInfK;
-                    wt[kk * kInfH + col] = (k0 + kk < H && col < H) ? W[(uint64_t)col * H + k0 + kk] : 0.f;
-                }
-                __syncthreads();
-#pragma unroll 4
-                for (uint32_t kk = 0; kk < (uint32_t)kInfK; ++kk) {
-                    float a[8], w[16];
+                for (int n = 0; n < (int)kInfBlocks; ++n) acc[m][n] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+            for (uint32_t kb = 0; kb < KB; ++kb) {
+                f32x4_t a[1], w[kInfBlocks];
 #pragma unroll
-                    for (int i = 0; i < 8; ++i) a[i] = act[(ty * 8 + i) * kInfH + k0 + kk];
+                for (int m = 0; m < 1; ++m)
+                    a[m] = *reinterpret_cast<const f32x4_t*>(act + (((wave + m) * KB + kb) * 64 + lane) * 4);
 #pragma unroll
-                    for (int j = 0; j < 16; ++j) w[j] = wt[kk * kInfH + tx * 16 + j];
+                for (int n = 0; n < (int)kInfBlocks; ++n)
+                    if ((uint32_t)n < NB)
+                        w[n] = *reinterpret_cast<const f32x4_t*>(Bp + (((uint64_t)n * KB + kb) * 64 + lane) * 4);
 #pragma unroll
-                    for (int i = 0; i < 8; ++i)
+                for (int j = 0; j < 4; ++j)
 #pragma unroll
-                        for (int j = 0; j < 16; ++j) acc[i][j] = fmaf(a[i], w[j], acc[i][j]);
-                }
-                __syncthreads();
+                    for (int m = 0; m < 1; ++m)
+#pragma unroll
+                        for (int n = 0; n < (int)kInfBlocks; ++n)
+                            if ((uint32_t)n < NB)
+                                acc[m][n] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[m][j], w[n][j], acc[m][n], 0, 0, 0);
             }
+            __syncthreads();  // every wave has read this layer's input
 #pragma unroll
-            for (int i = 0; i < 8; ++i)
+            for (int m = 0; m < 1; ++m)
 #pragma unroll
-                for (int j = 0; j < 16; ++j) {
-                    const uint32_t col = tx * 16 + j;
-                    act[(ty * 8 + i) * kInfH + col] = col < H ? gelu(acc[i][j] + b[col]) : 0.f;
+                for (int n = 0; n < (int)kInfBlocks; ++n) {
+                    if ((uint32_t)n >= NB) continue;
+                    const uint32_t col = n * 16 + (lane & 15u);
+                    const float bias = col < H ? b[col] : 0.f;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t row = (wave + m) * 16 + 4 * (lane >> 4) + q;
+                        act[frag32_index(row, col, KB)] = col < H ? gelu(acc[m][n][q] + bias) : 0.f;
+                    }
                 }
             __syncthreads();
         }
-        // output layer H -> 1: 16 lanes per row block, reduced by shuffles
+        // output layer H -> 1: four lanes per row, each a quarter of the columns
         {
             const float* W = prm + A.w_off[A.n_layers - 1];
-            const float b = prm[A.b_off[A.n_layers - 1]];
-            float part[8];
-#pragma unroll
-            for (int i = 0; i < 8; ++i) {
-                part[i] = 0.f;
-                for (int j = 0; j < 16; ++j) {
-                    const uint32_t col = tx * 16 + j;
-                    if (col < H) part[i] = fmaf(act[(ty * 8 + i) * kInfH + col], W[col], part[i]);
-                }
-#pragma unroll
-                for (int off = 8; off >= 1; off >>= 1) part[i] += __shfl_xor(part[i], off, 16);
-            }
-            if (tx == 0)
-#pragma unroll
-                for (int i = 0; i < 8; ++i) outs[(ty * 8 + i) * 8 + mem] = part[i] + b;
+            const float bo = prm[A.b_off[A.n_layers - 1]];
+            const uint32_t row = threadIdx.x >> 2, quarter = threadIdx.x & 3u;
+            float part = 0.f;
+            for (uint32_t col = quarter; col < H; col += 4) part = fmaf(act[frag32_index(row, col, KB)], W[col], part);
+            part += __shfl_xor(part, 1, 4);
+            part += __shfl_xor(part, 2, 4);
+            if (quarter == 0) outs[row * 8 + mem] = part + bo;
             __syncthreads();
         }
     }
     // members' mean and sample standard deviation, in units of <v>
-    if (threadIdx.x < kInfRows) {
+    if (threadIdx.x < kInfMRows) {
         const uint64_t gi = r0 + threadIdx.x;
         if (gi < A.n) {
             const float scale = A.sc.target_over_omega ? A.X[gi * A.w0 + 1] : 1.f;
@@ -849,7 +890,7 @@ void sde_surrogate_destroy(sde_surrogate* s)
     if (!s) return;
     (void)hipDeviceSynchronize();
     for (void* p : {(void*)s->params, (void*)s->grads, (void*)s->adam_m, (void*)s->adam_v, (void*)s->adam_t,
-                    (void*)s->work, (void*)s->perm})
+                    (void*)s->work, (void*)s->perm, (void*)s->packed})
         if (p) (void)hipFree(p);
     delete s;
 }
@@ -1022,14 +1063,39 @@ static int predict_impl(sde_surrogate* s, const float* X, uint64_t n, float* mea
         a.b_off[l] = s->b_off[l];
     }
     a.sc = s->sc;
-    const size_t lds = (size_t)(kInfRows * kInfH + kInfK * kInfH + kInfRows * 8) * sizeof(float);
+    // hidden weights into the MFMA operand layout (Hp = H rounded up to 16)
+    const uint32_t H = a.H, Hp = (H + 15u) & ~15u, hidden = a.n_layers - 2;
+    if (hidden > 0) {
+        const size_t need = (size_t)s->members * hidden * Hp * Hp * sizeof(float);
+        if (s->packed_bytes < need) {
+            if (s->packed) SDE_HIP(ctx, hipFree(s->packed));
+            s->packed = nullptr;
+            s->packed_bytes = 0;
+            SDE_HIP(ctx, hipMalloc(&s->packed, need));
+            s->packed_bytes = need;
+        }
+        PackArgs pk{};
+        pk.params = s->params;
+        pk.P = s->P;
+        pk.members = s->members;
+        pk.hidden = hidden;
+        pk.H = H;
+        pk.Hp = Hp;
+        for (uint32_t l = 0; l < hidden; ++l) pk.w_off[l] = s->w_off[l + 1];
+        pk.packed = s->packed;
+        const uint64_t total = (uint64_t)s->members * hidden * Hp * Hp;
+        hipLaunchKernelGGL(mlp_pack_hidden_kernel, dim3((uint32_t)((total + 255) / 256)), dim3(256), 0, st, pk);
+        SDE_HIP(ctx, hipGetLastError());
+    }
+    const size_t lds = (size_t)(kInfMRows * kInfH + 2 * kInfMRows * 8) * sizeof(float);
     static bool attr_set = false;
     if (!attr_set) {
-        SDE_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(mlp_infer_kernel),
+        SDE_HIP(ctx, hipFuncSetAttribute(reinterpret_cast<const void*>(mlp_infer_mfma_kernel),
                                          hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
         attr_set = true;
     }
-    hipLaunchKernelGGL(mlp_infer_kernel, dim3((uint32_t)((n + kInfRows - 1) / kInfRows)), dim3(256), lds, st, a);
+    hipLaunchKernelGGL(mlp_infer_mfma_kernel, dim3((uint32_t)((n + kInfMRows - 1) / kInfMRows)), dim3(256), lds, st, a,
+                       static_cast<const float*>(s->packed), Hp);
     SDE_HIP(ctx, hipGetLastError());
     return SDE_OK;
 }
@@ -1038,7 +1104,7 @@ int sde_surrogate_predict(sde_surrogate* s, const float* X, uint64_t n, float* m
 {
     if (check_s(s)) return SDE_ERR_INVALID;
     s->ctx->last_error.clear();
-    if (!X || !mean || !spread || n == 0 || (n + kInfRows - 1) / kInfRows > 0x7fffffffull)
+    if (!X || !mean || !spread || n == 0 || (n + kInfMRows - 1) / kInfMRows > 0x7fffffffull)
         return fail(s->ctx, SDE_ERR_INVALID, "predict: bad arguments");
     if (!aligned(X, 4) || !aligned(mean, 4) || !aligned(spread, 4))
         return fail(s->ctx, SDE_ERR_INVALID, "predict: misaligned pointer");
