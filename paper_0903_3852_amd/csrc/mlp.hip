@@ -118,6 +118,8 @@ __global__ void mlp_normalize_kernel(NormArgs A)
 //  DX:  opA = dZ[m][k] (ld = K), opB = W[k][n] (ld = N); epilogue
 //       dZ_prev = acc * GELU'(Z_prev)
 enum { kFwd = 0, kDW = 1, kDX = 2 };
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
 constexpr int kGT = 64;   // tile
 constexpr int kGK = 16;   // k step
 
@@ -155,10 +157,14 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(GemmArgs g)
     const float* A = g.A + mem * g.a_mstride;
     const float* B = g.B + mem * g.b_mstride;
     const uint32_t m0 = blockIdx.y * kGT, n0 = blockIdx.x * kGT;
-    const uint32_t tx = threadIdx.x & 15u, ty = threadIdx.x >> 4;
+    const uint32_t lane = threadIdx.x & 63u, wave = threadIdx.x >> 6, wm = wave >> 1, wn = wave & 1u;
     uint32_t kb = 0, ke = g.K;
     if (MODE == kDW) k_range(g.K, ksl, ks, kb, ke);
-    float acc[4][4] = {};
+    f32x4_t acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = f32x4_t{0.f, 0.f, 0.f, 0.f};
     for (uint32_t k0 = kb; k0 < ke; k0 += kGK) {
         // 64 x 16 elements of each operand, 4 per lane
 #pragma unroll
@@ -191,41 +197,47 @@ __global__ __launch_bounds__(256) void mlp_gemm_kernel(GemmArgs g)
             }
         }
         __syncthreads();
+        // wave (wm, wn) takes the 32 x 32 quarter of the tile: 2 x 2 blocks of
+        // v_mfma_f32_16x16x4_f32, lane l reading A[m = l % 16][k = l / 16] and
+        // B[k = l / 16][n = l % 16] of each 4-k group from the LDS slices
 #pragma unroll
-        for (int k = 0; k < kGK; ++k) {
-            float a[4], b[4];
+        for (int kg = 0; kg < kGK / 4; ++kg) {
+            const uint32_t k = kg * 4 + (lane >> 4);
+            float a[2], b[2];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                a[i] = As[k][ty * 4 + i];
-                b[i] = Bs[k][tx * 4 + i];
+            for (int i = 0; i < 2; ++i) {
+                a[i] = As[k][wm * 32 + i * 16 + (lane & 15u)];
+                b[i] = Bs[k][wn * 32 + i * 16 + (lane & 15u)];
             }
 #pragma unroll
-            for (int i = 0; i < 4; ++i)
+            for (int i = 0; i < 2; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) acc[i][j] = fmaf(a[i], b[j], acc[i][j]);
+                for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b[j], acc[i][j], 0, 0, 0);
         }
         __syncthreads();
     }
+    // lane l holds rows 4 (l / 16) + q, column l % 16 of each block
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        const uint32_t m = m0 + ty * 4 + i;
-        if (m >= g.M) continue;
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-            const uint32_t n = n0 + tx * 4 + j;
-            if (n >= g.N) continue;
-            const uint64_t o = (uint64_t)m * g.N + n;
-            if (MODE == kFwd) {
-                const float z = acc[i][j] + g.bias[mem * g.bias_mstride + n];
-                g.C[mem * g.c_mstride + o] = z;
-                g.C2[mem * g.c2_mstride + o] = g.last ? z : gelu(z);
-            } else if (MODE == kDW) {
-                g.C[mem * g.c_mstride + (uint64_t)ks * g.M * g.N + o] = acc[i][j];
-            } else {
-                g.C[mem * g.c_mstride + o] = acc[i][j] * gelu_grad(g.Zp[mem * g.zp_mstride + o]);
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const uint32_t m = m0 + wm * 32 + i * 16 + 4 * (lane >> 4) + q;
+                const uint32_t n = n0 + wn * 32 + j * 16 + (lane & 15u);
+                if (m >= g.M || n >= g.N) continue;
+                const uint64_t o = (uint64_t)m * g.N + n;
+                const float v = acc[i][j][q];
+                if (MODE == kFwd) {
+                    const float z = v + g.bias[mem * g.bias_mstride + n];
+                    g.C[mem * g.c_mstride + o] = z;
+                    g.C2[mem * g.c2_mstride + o] = g.last ? z : gelu(z);
+                } else if (MODE == kDW) {
+                    g.C[mem * g.c_mstride + (uint64_t)ks * g.M * g.N + o] = v;
+                } else {
+                    g.C[mem * g.c_mstride + o] = v * gelu_grad(g.Zp[mem * g.zp_mstride + o]);
+                }
             }
-        }
-    }
 }
 
 // dW of the first layer: dW[o][j] = sum_b dZ[b][o] Xn[rows[b]][j] (gathered input rows).
@@ -402,8 +414,6 @@ struct InferArgs {
 // four consecutive MFMAs.  The hidden weights are packed that way once per
 // call (B(k, c) = W[c][k]); the activations stay in LDS in the same layout, as
 // the A operand of the next layer.
-typedef float f32x4_t __attribute__((ext_vector_type(4)));
-
 __device__ __forceinline__ uint32_t frag32_index(uint32_t i, uint32_t k, uint32_t kb16)
 {
     return (((i >> 4) * kb16 + (k >> 4)) * 64 + ((i & 15u) + 16u * (k & 3u))) * 4 + ((k & 15u) >> 2);
