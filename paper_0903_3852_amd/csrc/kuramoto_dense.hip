@@ -205,22 +205,37 @@ __device__ __forceinline__ void dense_tile_stage(const DenseArgs& A, uint32_t mt
             th[e] = r < A.R && i < A.N ? A.base[(uint64_t)r * A.N + i] : 0.f;
         }
     }
+    // The lane's 16 updates are independent: read all sums first and compute
+    // them branch-free (lanes outside R x N draw noise nobody uses), so the
+    // compiler can interleave their Philox chains; only the stores are
+    // predicated.  Each (rl, il) belongs to one lane, so reading all before
+    // writing any is safe.
+    float S[kPer], C[kPer], t[kPer];
+#pragma unroll
+    for (uint32_t e = 0; e < kPer; ++e) {
+        const uint32_t idx = threadIdx.x + e * kDenseThreads;
+        S[e] = tS[idx / kRowTile][idx % kRowTile];
+        C[e] = tC[idx / kRowTile][idx % kRowTile];
+    }
+#pragma unroll
+    for (uint32_t e = 0; e < kPer; ++e) {
+        const uint32_t idx = threadIdx.x + e * kDenseThreads;
+        const uint32_t r = nt * kRealTile + idx / kRowTile, i = mt * kRowTile + idx % kRowTile;
+        t[e] = dense_stage(A, n, i, r, S[e], C[e], ts[e], th[e], om[e], cy[e]);
+    }
 #pragma unroll
     for (uint32_t e = 0; e < kPer; ++e) {
         const uint32_t idx = threadIdx.x + e * kDenseThreads;
         const uint32_t rl = idx / kRowTile, il = idx % kRowTile;
         const uint32_t r = nt * kRealTile + rl, i = mt * kRowTile + il;
-        float sv = 0.f, cv = 0.f;  // rows k >= N of the operand stay zero
-        if (r < A.R && i < A.N) {
+        const bool ok = r < A.R && i < A.N;
+        if (ok) {
             const uint64_t gi = (uint64_t)r * A.N + i;
-            const float t = dense_stage(A, n, i, r, tS[rl][il], tC[rl][il], ts[e], th[e], om[e], cy[e]);
             if (!corrector && !A.euler) A.F1[gi] = cy[e];
-            A.dst[gi] = t;
-            sv = sin_rev(t);
-            cv = cos_rev(t);
+            A.dst[gi] = t[e];
         }
-        tS[rl][il] = sv;
-        tC[rl][il] = cv;
+        tS[rl][il] = ok ? sin_rev(t[e]) : 0.f;  // rows k >= N of the operand stay zero
+        tC[rl][il] = ok ? cos_rev(t[e]) : 0.f;
     }
     __syncthreads();
 }
