@@ -7,14 +7,17 @@
 //  * MEANFIELD (Eq. 3): per realization and stage only two sums, S = sum_j
 //    sin phi_j and C = sum_j cos phi_j, then F_i = omega_i + (K/N)(cos phi_i S
 //    - sin phi_i C).  One cooperative persistent launch runs every step: the
-//    G workgroups of a realization hold its oscillators in registers, write
-//    FP64 partial sums, meet at a per-realization barrier, and read all G
-//    partials in a fixed order (bitwise reproducible).  Workgroups are mapped
-//    so that each realization sits on one XCD (workgroups are dealt to the 8
-//    XCDs round robin), keeping its barrier traffic in that XCD's L2.
+//    G workgroups of a realization hold its oscillators in registers (or,
+//    beyond register capacity, stream them through HBM), publish FP64
+//    partial sums as tagged words without fences, and add all G partials in
+//    a fixed order (bitwise reproducible) -- directly, or through 8 group
+//    leaders when G is large.  Workgroups are mapped so that each realization
+//    sits on one XCD when the realizations divide evenly over the 8 XCDs
+//    (workgroups are dealt to them round robin).
 //  * TILED (Alg. 3, Fig. 3): all N^2 terms sin(2 pi (theta_j - theta_i)),
 //    theta_j staged through LDS in tiles and read by every lane (broadcast),
-//    one hardware v_sin_f32 per pair.  One launch per Heun stage; the stage
+//    one hardware v_sin_f32 per pair; tile size tuned, and for small N the j
+//    range split over workgroups.  One launch per Heun stage; the stage
 //    boundary is the global synchronization.
 // The noise of oscillator i in realization r at step n is component n & 3 of
 // the Box-Muller Gaussians of Philox(ctr = (n >> 2, i, r, NOISE)).
