@@ -33,10 +33,12 @@
 //                    16 rows by 16 k in one contiguous 1 KB block, a lane's
 //                    float4 holding the k of four consecutive MFMAs.
 // A workgroup owns 128 rows x 32 realizations (64 columns), so every lane
-// holds S and C of the same (i, r) in its accumulators.  Workgroups are
-// dealt to XCDs so that each XCD sweeps a contiguous band of rows over all
-// columns: its slice of K is read from HBM/MALL once per product and the
-// whole B stays in its L2.
+// holds S and C of the same (i, r) in its accumulators; its waves split the
+// k loop (8 waves for the 16-bit variants, 4 for FP32) and sum their partial
+// tiles through LDS in a fixed order.  Workgroups are dealt to XCDs so that
+// each XCD sweeps a contiguous band of rows over all columns: its slice of K
+// is read from HBM/MALL once per product, B once per XCD, and the workgroups
+// that share a K slab or a B column block hit in the XCD's L2.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -167,8 +169,8 @@ __device__ __forceinline__ f32x4 mfma16(V a, V b, f32x4 c)
 }
 
 // Stage update of a 128-row x 32-realization tile whose S and C sit in LDS
-// as tS[realization][row], tC[realization][row] (already unscaled).  Lane t
-// takes the oscillators t, t + 256, ... of the tile in row-fastest order, so
+// as tS[realization][row], tC[realization][row] (already unscaled), by NT
+// threads.  Lane t takes the oscillators t, t + NT, ... of the tile in row-fastest order, so
 // a wave's phase loads and stores cover 64 consecutive oscillators of one
 // realization (256 contiguous bytes; with 8 rows per lane the lanes sit 32
 // bytes apart and the L1 serves them one by one).  All of a lane's loads come
@@ -176,17 +178,18 @@ __device__ __forceinline__ f32x4 mfma16(V a, V b, f32x4 c)
 // compiler could not move a load above a store.  sin and cos of the new
 // phase replace S and C in the tile (zero outside R x N), for the store of
 // the next operand that follows.
+template <uint32_t NT = kDenseThreads>
 __device__ __forceinline__ void dense_tile_stage(const DenseArgs& A, uint32_t mt, uint32_t nt,
                                                  float (*tS)[kRowTile + 1], float (*tC)[kRowTile + 1])
 {
-    constexpr uint32_t kPer = kRowTile * kRealTile / kDenseThreads;  // oscillators per lane
-    static_assert(kRowTile % kWave == 0 && kDenseThreads % kRowTile == 0, "a wave stays in one realization");
+    constexpr uint32_t kPer = kRowTile * kRealTile / NT;  // oscillators per lane
+    static_assert(kRowTile % kWave == 0 && NT % kRowTile == 0, "a wave stays in one realization");
     const uint64_t n = load_uniform(A.nbase) + A.k;
     const bool corrector = A.stage != 1;
     float ts[kPer], th[kPer], cy[kPer], om[kPer];
 #pragma unroll
     for (uint32_t e = 0; e < kPer; ++e) {
-        const uint32_t idx = threadIdx.x + e * kDenseThreads;
+        const uint32_t idx = threadIdx.x + e * NT;
         const uint32_t r = nt * kRealTile + idx / kRowTile, i = mt * kRowTile + idx % kRowTile;
         const bool ok = r < A.R && i < A.N;
         const uint64_t gi = ok ? (uint64_t)r * A.N + i : 0;
@@ -200,7 +203,7 @@ __device__ __forceinline__ void dense_tile_stage(const DenseArgs& A, uint32_t mt
     } else {
 #pragma unroll
         for (uint32_t e = 0; e < kPer; ++e) {
-            const uint32_t idx = threadIdx.x + e * kDenseThreads;
+            const uint32_t idx = threadIdx.x + e * NT;
             const uint32_t r = nt * kRealTile + idx / kRowTile, i = mt * kRowTile + idx % kRowTile;
             th[e] = r < A.R && i < A.N ? A.base[(uint64_t)r * A.N + i] : 0.f;
         }
@@ -213,19 +216,19 @@ __device__ __forceinline__ void dense_tile_stage(const DenseArgs& A, uint32_t mt
     float S[kPer], C[kPer], t[kPer];
 #pragma unroll
     for (uint32_t e = 0; e < kPer; ++e) {
-        const uint32_t idx = threadIdx.x + e * kDenseThreads;
+        const uint32_t idx = threadIdx.x + e * NT;
         S[e] = tS[idx / kRowTile][idx % kRowTile];
         C[e] = tC[idx / kRowTile][idx % kRowTile];
     }
 #pragma unroll
     for (uint32_t e = 0; e < kPer; ++e) {
-        const uint32_t idx = threadIdx.x + e * kDenseThreads;
+        const uint32_t idx = threadIdx.x + e * NT;
         const uint32_t r = nt * kRealTile + idx / kRowTile, i = mt * kRowTile + idx % kRowTile;
         t[e] = dense_stage(A, n, i, r, S[e], C[e], ts[e], th[e], om[e], cy[e]);
     }
 #pragma unroll
     for (uint32_t e = 0; e < kPer; ++e) {
-        const uint32_t idx = threadIdx.x + e * kDenseThreads;
+        const uint32_t idx = threadIdx.x + e * NT;
         const uint32_t rl = idx / kRowTile, il = idx % kRowTile;
         const uint32_t r = nt * kRealTile + rl, i = mt * kRowTile + il;
         const bool ok = r < A.R && i < A.N;
@@ -244,15 +247,15 @@ __device__ __forceinline__ void dense_tile_stage(const DenseArgs& A, uint32_t mt
 // j sends lane -> (column c % 16, 8-row group of the 32-row block) of the
 // fragment (column block, k block) = ((u >> 6) & 3, u >> 8), so a wave writes
 // one whole 1 KB packed fragment (hi) and its lo part per pass.
-template <typename T, typename V>
+template <typename T, typename V, uint32_t NT>
 __device__ __forceinline__ void dense_tile_store(const DenseArgs& A, uint32_t mt, uint32_t nt,
                                                  const float (*tS)[kRowTile + 1], const float (*tC)[kRowTile + 1])
 {
     const uint32_t KB = A.Np / kKStep;
     T* B = static_cast<T*>(A.Bnext);
 #pragma unroll
-    for (uint32_t j = 0; j < 2 * kRealTile * kRowTile / 8 / kDenseThreads; ++j) {
-        const uint32_t u = threadIdx.x + j * kDenseThreads;
+    for (uint32_t j = 0; j < 2 * kRealTile * kRowTile / 8 / NT; ++j) {
+        const uint32_t u = threadIdx.x + j * NT;
         const uint32_t cb = (u >> 6) & 3u, kind = cb >> 1;
         const uint32_t rl = (cb & 1u) * 16 + (u & 15u), il0 = (u >> 8) * kKStep + ((u >> 4) & 3u) * 8;
         const uint32_t r = nt * kRealTile + rl, i0 = mt * kRowTile + il0;
@@ -331,26 +334,38 @@ __device__ __forceinline__ void dense_reduce_tile(const f32x4 (&acc)[8][4], f32x
 }
 
 // Split-precision product and stage update of one 128-row x 32-realization
-// tile.  The output (N x 2R = 4096 x 512 at the benchmark size) is too small
-// to give each SIMD a large tile of its own, so the k loop is split instead:
-// every wave of the workgroup computes the whole 128 x 64 tile over every
-// fourth 32-k block.  Per block a wave loads 16 K and 8 B fragments (24 KB,
-// prefetched one block ahead) for 96 MFMAs, and no fragment is loaded twice
-// within the CU: 64 B per clock per CU at the MFMA rate, half of what a 2 x 2
-// grid of 64 x 32 wave tiles needs (there the L1 bounds the loop).  The four
-// partial tiles are summed through LDS in a fixed order, then the stage
-// update runs on the sum.
+// tile by 8 waves, two per SIMD.  The output (N x 2R = 4096 x 512 at the
+// benchmark size) is too small to give each SIMD a large tile of its own, so
+// the k loop is split instead: every wave computes the whole 128 x 64 tile
+// (128 accumulators) over every eighth 32-k block.  Per block a wave loads
+// 16 K and 8 B fragments (24 KB) for 96 MFMAs, and no fragment is loaded
+// twice within the CU: 64 B per clock per CU at the MFMA rate, half of what a
+// 2 x 2 grid of 64 x 32 wave tiles needs (there the L1 bounds the loop).
+// Accumulators and one block of fragments fill a wave's 256 registers, so
+// there is no second register set for a prefetch; instead the next block's K
+// fragments of row block m load into the registers of row block m as soon
+// as its 12 MFMAs are issued, the B fragments after the last row block, and
+// the SIMD's other wave computes while one waits.  Per accumulator the
+// products still enter in the order hi*hi, hi*lo, lo*hi of each k block.
+constexpr int kDense16Threads = 512;
+constexpr uint32_t kSplitK16 = 8;
 
 template <typename T, typename V>
-__global__ __launch_bounds__(kDenseThreads, 1) void dense_mfma_kernel(DenseArgs A)
+__global__ __launch_bounds__(kDense16Threads, 1) void dense_mfma_kernel(DenseArgs A)
 {
-    // partials of waves 1..3: [wave - 1][32 accumulator quads][64 lanes] x 4
-    // floats (96 KB), and the summed tile transposed to [realization][row]
-    __shared__ f32x4 red[kSplitK - 1][32][kWave];
-    __shared__ float tS[kRealTile][kRowTile + 1], tC[kRealTile][kRowTile + 1];
+    // Partial tiles are summed in two rounds: waves 4-7 hand theirs to waves
+    // 0-3 (red[0..2] and slot3), then waves 1-3 hand the pair sums to the
+    // tile (red[0..2]).  The transposed tile [realization][row] overlays
+    // slot3, whose contents are consumed before the tile is written.
+    __shared__ f32x4 red[3][32][kWave];
+    __shared__ __attribute__((aligned(16))) float tile[2 * kRealTile * (kRowTile + 1)];
+    static_assert(sizeof(tile) >= sizeof(f32x4) * 32 * kWave, "slot3 fits under the tile");
+    f32x4 (*slot3)[kWave] = reinterpret_cast<f32x4 (*)[kWave]>(tile);
+    float (*tS)[kRowTile + 1] = reinterpret_cast<float (*)[kRowTile + 1]>(tile);
+    float (*tC)[kRowTile + 1] = reinterpret_cast<float (*)[kRowTile + 1]>(tile + kRealTile * (kRowTile + 1));
     uint32_t mt, nt;
     tile_of(blockIdx.x, A.Mp / kRowTile, A.Rp / kRealTile, mt, nt);
-    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63u;
     const uint32_t KB = A.Np / kKStep;
     const uint64_t frag = 2 * 64 * 8;              // elements per k block (hi + lo)
     const uint64_t stream = (uint64_t)KB * frag;  // elements per 16-row block
@@ -363,57 +378,98 @@ __global__ __launch_bounds__(kDenseThreads, 1) void dense_mfma_kernel(DenseArgs 
 #pragma unroll
         for (int n = 0; n < 4; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
     V ah[8], al[8], bh[4], bl[4];
-    auto load = [&](uint64_t o) {
-#pragma unroll
-        for (int m = 0; m < 8; ++m) {
-            ah[m] = *reinterpret_cast<const V*>(pa + m * stream + o);
-            al[m] = *reinterpret_cast<const V*>(pa + m * stream + o + kFragLo);
-        }
+    auto load_b = [&](uint64_t o) {
 #pragma unroll
         for (int n = 0; n < 4; ++n) {
             bh[n] = *reinterpret_cast<const V*>(pb + n * stream + o);
             bl[n] = *reinterpret_cast<const V*>(pb + n * stream + o + kFragLo);
         }
     };
-    uint32_t kb = wave;
-    if (kb < KB) load((uint64_t)kb * frag);
-    for (; kb < KB; kb += kSplitK) {
-        V cah[8], cal[8], cbh[4], cbl[4];
+    if (wave < KB) {
+        const uint64_t o = (uint64_t)wave * frag;
+        load_b(o);
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
-            cah[m] = ah[m];
-            cal[m] = al[m];
+            ah[m] = *reinterpret_cast<const V*>(pa + m * stream + o);
+            al[m] = *reinterpret_cast<const V*>(pa + m * stream + o + kFragLo);
         }
-#pragma unroll
-        for (int n = 0; n < 4; ++n) {
-            cbh[n] = bh[n];
-            cbl[n] = bl[n];
-        }
-        if (kb + kSplitK < KB) load((uint64_t)(kb + kSplitK) * frag);  // prefetch this wave's next block
-#pragma unroll
-        for (int m = 0; m < 8; ++m)
-#pragma unroll
-            for (int n = 0; n < 4; ++n) acc[m][n] = mfma16<T, V>(cah[m], cbh[n], acc[m][n]);
-#pragma unroll
-        for (int m = 0; m < 8; ++m)
-#pragma unroll
-            for (int n = 0; n < 4; ++n) acc[m][n] = mfma16<T, V>(cah[m], cbl[n], acc[m][n]);
-#pragma unroll
-        for (int m = 0; m < 8; ++m)
-#pragma unroll
-            for (int n = 0; n < 4; ++n) acc[m][n] = mfma16<T, V>(cal[m], cbh[n], acc[m][n]);
     }
-    dense_reduce_tile(acc, red, tS, tC, A.scale[1]);
-    dense_tile_stage(A, mt, nt, tS, tC);
-    dense_tile_store<T, V>(A, mt, nt, tS, tC);
+    for (uint32_t kb = wave; kb < KB; kb += kSplitK16) {
+        const bool more = kb + kSplitK16 < KB;
+        const uint64_t on = (uint64_t)(more ? kb + kSplitK16 : kb) * frag;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = mfma16<T, V>(ah[m], bh[n], acc[m][n]);
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = mfma16<T, V>(ah[m], bl[n], acc[m][n]);
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = mfma16<T, V>(al[m], bh[n], acc[m][n]);
+            if (more) {
+                ah[m] = *reinterpret_cast<const V*>(pa + m * stream + on);
+                al[m] = *reinterpret_cast<const V*>(pa + m * stream + on + kFragLo);
+            }
+        }
+        if (more) load_b(on);
+    }
+    // round 1: wave w < 4 adds wave w + 4's partial
+    if (wave >= 4) {
+        f32x4 (*dst)[kWave] = wave == 7 ? slot3 : red[wave - 4];
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) dst[m * 4 + n][lane] = acc[m][n];
+    }
+    __syncthreads();
+    if (wave < 4) {
+        const f32x4 (*src)[kWave] = wave == 3 ? slot3 : red[wave];
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] += src[m * 4 + n][lane];
+    }
+    __syncthreads();
+    // round 2: p0 + ((p1 + p2) + p3) into the tile, transposed, times the
+    // exact power of two that undoes the scaling of K
+    const float inv = A.scale[1];
+    if (wave >= 1 && wave < 4) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) red[wave - 1][m * 4 + n][lane] = acc[m][n];
+    } else if (wave == 0) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                float(*t)[kRowTile + 1] = (n >> 1) ? tC : tS;
+                const uint32_t rl = (n & 1) * 16 + (lane & 15u);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) t[rl][m * 16 + 4 * (lane >> 4) + q] = acc[m][n][q] * inv;
+            }
+    }
+    __syncthreads();
+    for (uint32_t p = threadIdx.x; p < 32 * kWave; p += kDense16Threads) {
+        const uint32_t quad = p / kWave, l = p % kWave;
+        const f32x4 sum = (red[0][quad][l] + red[1][quad][l]) + red[2][quad][l];
+        const uint32_t m = quad / 4, n = quad % 4;
+        float(*t)[kRowTile + 1] = (n >> 1) ? tC : tS;
+        const uint32_t rl = (n & 1) * 16 + (l & 15u);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) t[rl][m * 16 + 4 * (l >> 4) + q] += sum[q] * inv;
+    }
+    __syncthreads();
+    dense_tile_stage<kDense16Threads>(A, mt, nt, tS, tC);
+    dense_tile_store<T, V, kDense16Threads>(A, mt, nt, tS, tC);
 }
 
 // ------------------------------------------------------------- FP32 MFMA --
-// The FP32 product on v_mfma_f32_16x16x4_f32 with the same split of the k
-// loop: every wave computes the whole 128 x 64 tile over every fourth 16-k
-// block.  Per block a wave loads 8 K and 4 B float4 fragments (12 KB) and
-// issues 4 x 32 MFMAs (about 4096 cycles), so one block of prefetch covers
-// the memory latency.
+// The FP32 product on v_mfma_f32_16x16x4_f32, split over the k loop the
+// same way but by 4 waves (one per SIMD): every wave computes the whole
+// 128 x 64 tile over every fourth 16-k block.  Per block a wave loads 8 K and
+// 4 B float4 fragments (12 KB) and issues 4 x 32 MFMAs (about 4096 cycles),
+// so one block of register prefetch covers the memory latency; a second
+// wave per SIMD gains nothing here.
 __global__ __launch_bounds__(kDenseThreads, 1) void dense_mfma32_kernel(DenseArgs A)
 {
     __shared__ f32x4 red[kSplitK - 1][32][kWave];
@@ -587,9 +643,9 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
         if constexpr (sizeof(T) == 4)
             hipLaunchKernelGGL(dense_mfma32_kernel, grid, dim3(kDenseThreads), 0, s, A);
         else if constexpr (__is_same(T, __bf16))
-            hipLaunchKernelGGL((dense_mfma_kernel<__bf16, bf16x8>), grid, dim3(kDenseThreads), 0, s, A);
+            hipLaunchKernelGGL((dense_mfma_kernel<__bf16, bf16x8>), grid, dim3(kDense16Threads), 0, s, A);
         else
-            hipLaunchKernelGGL((dense_mfma_kernel<_Float16, f16x8>), grid, dim3(kDenseThreads), 0, s, A);
+            hipLaunchKernelGGL((dense_mfma_kernel<_Float16, f16x8>), grid, dim3(kDense16Threads), 0, s, A);
         SDE_HIP(ctx, hipGetLastError());
         return SDE_OK;
     };
