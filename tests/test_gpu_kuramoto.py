@@ -119,6 +119,24 @@ def test_dense_first_100_steps(gpu, coupling, tol):
     np.testing.assert_allclose(rs.cpu().numpy(), rref, rtol=0, atol=10 * tol)
 
 
+@pytest.mark.parametrize("coupling,tol", [(2, 1e-5), (3, 1e-4), (4, 1e-5)])
+@pytest.mark.parametrize("N,R,scheme", [(520, 40, 1), (1, 1, 0), (33, 3, 1), (200, 70, 0)])
+def test_dense_euler_and_small_shapes(gpu, coupling, tol, N, R, scheme):
+    """Euler-Maruyama (updated in place) and shapes below one 32-k block per
+    wave of the split k loop: N = 1 (a lone oscillator: drift omega plus
+    noise), N = 33 and 200 (2 and 7 k blocks), R = 70 (three realization
+    tiles, the last ragged)."""
+    Kmat = sde_inputs.dense_coupling(N, 4.0, 21)
+    omega = sde_inputs.kuramoto_omega(N, 0.5, 22)
+    ph, rs = _run(gpu, N, R, 4.0, 0.05, 0.005, 100, coupling, scheme, 23, omega, Kmat)
+    ref, rref = oracle.kuramoto_integrate(N, R, 4.0, 0.05, 0.005, 100, 100, oracle.DENSE, scheme, 23,
+                                          omega.astype(np.float64), Kmat=Kmat.astype(np.float64))
+    err = _circ_err(ph.cpu().numpy(), ref)
+    print(f"dense coupling {coupling}, N {N}, R {R}, scheme {scheme}: max phase error {err.max():.2e}")
+    assert err.max() <= tol
+    np.testing.assert_allclose(rs.cpu().numpy(), rref, rtol=0, atol=10 * tol)
+
+
 def test_dense_full_size_sampled(gpu):
     """The dense workload at its size -- N = 4096, 256 realizations, the
     BF16x3 product -- for 200 steps, realizations 0..3 checked against the
