@@ -294,7 +294,7 @@ __device__ __forceinline__ void dense_tile_store_f32(const DenseArgs& A, uint32_
     }
 }
 
-// Sum of the four waves' partial 128 x 64 tiles in a fixed order, times the
+// Sum of the FP32 kernel's four partial 128 x 64 tiles in a fixed order, times the
 // exact power of two `inv`, transposed into tS/tC: waves 1..3 go through red,
 // wave 0 writes its own straight into the tile, then all lanes add
 // ((p1 + p2) + p3).
