@@ -633,7 +633,8 @@ def bench_sweep(args, sde, torch, dev):
     with and without the small-N remedy of Sec. 6: JJ paths of one point
     (remedy: many parameter points at once, 2^20 paths in all), the
     all-pairs sum for one realization (remedy: j split over workgroups), the
-    mean field for one realization (remedy: 16 realizations per launch).
+    mean field for one realization (remedy: 16 realizations per launch), the
+    dense BF16x3 product at 256 realizations (remedy: N R = 2^20 per launch).
     GFLOPS use the paper's operation counts per particle-step: 79 (JJ),
     44 + 6 N (all pairs), 66 (mean field)."""
     ctx = sde.sde_create(0)
@@ -695,6 +696,30 @@ def bench_sweep(args, sde, torch, dev):
         rows.append(rec)
         print(f"sweep mean field N={N}: {rec['osc_steps_per_s']:.3g} osc-steps/s", file=sys.stderr, flush=True)
     out["kuramoto_mean_field"] = rows
+    # dense K_ij, BF16x3 product, 256 realizations; remedy for small N: more
+    # realizations per launch (N R = 2^20, the benchmark's product width)
+    rows = []
+    for N in (512, 1024, 2048, 4096, 8192):
+        n = 200 if N <= 4096 else 50
+        Kt = torch.from_numpy(sde_inputs.dense_coupling(N, 4.0, sde_inputs.seed_of(31))).to(dev)
+        om = torch.from_numpy(sde_inputs.kuramoto_omega(N, 0.5, sde_inputs.seed_of(32))).to(dev)
+        rec = {"N": N, "steps": n}
+        for key, R in (("R256", 256), ("filled", max(256, (1 << 20) // N))):
+            if key == "filled" and R == 256:
+                continue
+            ph = torch.empty((R, N), dtype=torch.float32, device=dev)
+            desc = sde.sde_kuramoto_desc(N, R, 4.0, 0.05, 0.005, n, sde.SDE_DENSE_BF16X3, 0)
+            run = sde.make_run(sde_inputs.seed_of(33))
+            t = _timed(torch, lambda: sde.sde_kuramoto_integrate(ctx, desc, run, ph, om, Kt, None))
+            executed = 3 * 2.0 * N * N * 2 * R * n * 2
+            rec[key] = {"R": R, "osc_steps_per_s": N * R * n / t, "us_per_stage": t / (2 * n) * 1e6,
+                        "mfma_frac": executed / t / PEAK_MFMA_16BIT}
+            del ph
+        rows.append(rec)
+        print(f"sweep dense N={N}: R=256 {rec['R256']['osc_steps_per_s']:.3g} osc-steps/s "
+              f"({100 * rec['R256']['mfma_frac']:.1f} % MFMA)", file=sys.stderr, flush=True)
+        del Kt
+    out["kuramoto_dense_bf16x3"] = rows
     sde.sde_check(ctx)
     sde.sde_destroy(ctx)
     return {"workload": "sweep", "sweep": out}
