@@ -13,7 +13,8 @@ of them under "kuramoto".
 
 Prints one JSON line: throughput, the roofline fraction of the dominant
 kernel (timed with HIP events on the stream it runs on) and the FP64 CPU
-oracle timed on a bounded sample of the same workload.
+oracle timed on a bounded sample of the same workload; each Kuramoto leg
+carries the oracle timed on a sample of its own configuration.
 """
 import argparse
 import hashlib
@@ -483,6 +484,35 @@ KURA = {
 }
 
 
+def kuramoto_cpu_oracle(spec, cfg):
+    """The FP64 oracle timed beside a Kuramoto leg on a bounded sample of its
+    configuration (a few seconds on the host's threads): the mean field on
+    all realizations for 50 steps, the direct all-pairs sum for one
+    realization and one step, the dense coupling on realizations 0-7 for 100
+    steps."""
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    N, R = cfg["N"], cfg["R"]
+    om = cfg["omega"].astype(np.float64)
+    coupling = spec["coupling"]
+    if coupling == 0:
+        n, rr, kind, Km = 50, R, oracle.MEANFIELD, None
+    elif coupling == 1:
+        n, rr, kind, Km = 1, 1, oracle.DIRECT, None
+    else:
+        n, rr, kind, Km = 100, 8, oracle.DENSE, cfg["Kmat"].astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.kuramoto_integrate(N, R, cfg["K"], cfg["D"], cfg["dt"], n, 0, kind, spec["scheme"], cfg["seed"], om,
+                              Kmat=Km, r_first=0, r_count=rr, n_threads=threads)
+    dt = time.perf_counter() - t0
+    sample = f"{rr} realization(s) x N = {N} x {n} step(s), FP64, {dt:.1f} s"
+    if coupling == 1:
+        stages = 2 if spec["scheme"] == 0 else 1
+        return {"value": float(N) * N * rr * n * stages / dt, "unit": "pair terms/s", "cores": threads,
+                "kind": "oracle", "sample": sample + " (direct double loop)"}
+    return {"value": N * rr * n / dt, "unit": "osc-steps/s", "cores": threads, "kind": "oracle", "sample": sample}
+
+
 def bench_kuramoto(name, args, sde, torch, dev, steps=None, reps=1):
     spec = KURA[name]
     cfg = sde_inputs.kuramoto_uniform() if spec["cfg"] == "uniform" else sde_inputs.kuramoto_dense()
@@ -540,6 +570,10 @@ def bench_kuramoto(name, args, sde, torch, dev, steps=None, reps=1):
             rec["gemm_equivalent_tflops"] = gemm_flop / t / 1e12
             rec["roofline"] = {"bound": "mfma", "achieved": executed / t / 1e12, "peak": PEAK_MFMA_16BIT / 1e12,
                                "unit": "TFLOP/s", "frac": executed / t / PEAK_MFMA_16BIT, "traffic": None}
+    if not getattr(args, "no_cpu_baseline", True):
+        cpu = kuramoto_cpu_oracle(spec, cfg)
+        gpu_rate = rec["pairs_per_s"] if spec["coupling"] == 1 else rec["osc_steps_per_s"]
+        rec["cpu_oracle"] = dict(cpu, gpu_over_cpu=gpu_rate / cpu["value"])
     return rec
 
 
