@@ -237,12 +237,26 @@ def bench_jj_batch(args, sde, torch, dev):
     sde.sde_destroy(ctx)
     t = s.elapsed_time(e) / 1e3
     ops = jj_ops_per_path_step()
-    return {"workload": "jj_batch", "points": len(pts_l), "path_steps": work, "seconds": t,
-            "path_steps_per_s": work / t, "paths_per_lane": st["jj_paths_per_lane"],
-            "work_items": st["work_items"], "graph_replayed": st["graph_replayed"],
-            "roofline": {"bound": "alu", "achieved": ops * work / t / 1e12, "peak": PEAK_FMA_LANES / 1e12,
-                         "unit": "T FP32-FMA-equivalent lane-ops/s", "frac": ops * work / t / PEAK_FMA_LANES,
-                         "traffic": None}}
+    rec = {"workload": "jj_batch", "points": len(pts_l), "path_steps": work, "seconds": t,
+           "path_steps_per_s": work / t, "paths_per_lane": st["jj_paths_per_lane"],
+           "work_items": st["work_items"], "graph_replayed": st["graph_replayed"],
+           "roofline": {"bound": "alu", "achieved": ops * work / t / 1e12, "peak": PEAK_FMA_LANES / 1e12,
+                        "unit": "T FP32-FMA-equivalent lane-ops/s", "frac": ops * work / t / PEAK_FMA_LANES,
+                        "traffic": None}}
+    if not getattr(args, "no_cpu_baseline", True):
+        # the FP64 oracle beside it: the first 8 points, 128 paths each, all their steps, under their
+        # batch indices (the same noise streams as the GPU's paths 0..127 of those points)
+        import oracle
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+        sample = [dict(p, n_paths=128) for p in pts_l[:8]]
+        t0 = time.perf_counter()
+        oracle.jj_integrate(sample, sde_inputs.seed_of(5), point_ids=list(range(8)), n_threads=threads)
+        dt = time.perf_counter() - t0
+        w = sum(p["n_paths"] * p["n_steps"] for p in sample)
+        rec["cpu_oracle"] = {"value": w / dt, "unit": "path-steps/s", "cores": threads, "kind": "oracle",
+                             "sample": f"8 batch points x 128 paths x their 5e4-4e5 steps, FP64, {dt:.1f} s",
+                             "gpu_over_cpu": work / t / (w / dt)}
+    return rec
 
 
 SURR_CENTER = [4.0, 5.0, 0.25, -2.5, 1.0]   # features (a, omega, f, log10 D, gamma) -> [-1, 1]
