@@ -253,7 +253,7 @@ def bench_jj_batch(args, sde, torch, dev):
         oracle.jj_integrate(sample, sde_inputs.seed_of(5), point_ids=list(range(8)), n_threads=threads)
         dt = time.perf_counter() - t0
         w = sum(p["n_paths"] * p["n_steps"] for p in sample)
-        rec["cpu_oracle"] = {"value": w / dt, "unit": "path-steps/s", "cores": threads, "kind": "oracle",
+        rec["cpu_baseline"] = {"value": w / dt, "unit": "path-steps/s", "cores": threads, "kind": "oracle",
                              "sample": f"8 batch points x 128 paths x their 5e4-4e5 steps, FP64, {dt:.1f} s",
                              "gpu_over_cpu": work / t / (w / dt)}
     return rec
@@ -587,7 +587,7 @@ def bench_kuramoto(name, args, sde, torch, dev, steps=None, reps=1):
     if not getattr(args, "no_cpu_baseline", True):
         cpu = kuramoto_cpu_oracle(spec, cfg)
         gpu_rate = rec["pairs_per_s"] if spec["coupling"] == 1 else rec["osc_steps_per_s"]
-        rec["cpu_oracle"] = dict(cpu, gpu_over_cpu=gpu_rate / cpu["value"])
+        rec["cpu_baseline"] = dict(cpu, gpu_over_cpu=gpu_rate / cpu["value"])
     return rec
 
 
