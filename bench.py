@@ -498,7 +498,7 @@ KURA = {
 }
 
 
-def kuramoto_cpu_oracle(spec, cfg):
+def kuramoto_cpu_baseline(spec, cfg):
     """The FP64 oracle timed beside a Kuramoto leg on a bounded sample of its
     configuration (a few seconds on the host's threads): the mean field on
     all realizations for 50 steps, the direct all-pairs sum for one
@@ -585,7 +585,7 @@ def bench_kuramoto(name, args, sde, torch, dev, steps=None, reps=1):
             rec["roofline"] = {"bound": "mfma", "achieved": executed / t / 1e12, "peak": PEAK_MFMA_16BIT / 1e12,
                                "unit": "TFLOP/s", "frac": executed / t / PEAK_MFMA_16BIT, "traffic": None}
     if not getattr(args, "no_cpu_baseline", True):
-        cpu = kuramoto_cpu_oracle(spec, cfg)
+        cpu = kuramoto_cpu_baseline(spec, cfg)
         gpu_rate = rec["pairs_per_s"] if spec["coupling"] == 1 else rec["osc_steps_per_s"]
         rec["cpu_baseline"] = dict(cpu, gpu_over_cpu=gpu_rate / cpu["value"])
     return rec
