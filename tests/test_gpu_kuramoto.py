@@ -153,6 +153,23 @@ def test_dense_full_size_sampled(gpu):
     assert err.max() <= 2e-4
 
 
+@pytest.mark.parametrize("coupling,tol", [(2, 1e-5), (3, 2e-5), (4, 1e-5)])
+def test_dense_twice_the_benchmark_size_sampled(gpu, coupling, tol):
+    """N = 8192 (32 k blocks per wave of the split loop), R = 32, 20 Heun
+    steps; realizations 0 and 1 against the oracle.  BF16x3 bound: the drift
+    error bound 1.5 K 2^-15 per unit time (independent of N: a row of K sums
+    to at most 1.5 K) over 20 steps of dt = 0.005, 1.8e-5."""
+    N, R, n = 8192, 32, 20
+    Kmat = sde_inputs.dense_coupling(N, 4.0, 41)
+    omega = sde_inputs.kuramoto_omega(N, 0.5, 42)
+    ph, _ = _run(gpu, N, R, 4.0, 0.05, 0.005, n, coupling, 0, 43, omega, Kmat, samples=False)
+    ref, _ = oracle.kuramoto_integrate(N, R, 4.0, 0.05, 0.005, n, 0, oracle.DENSE, 0, 43,
+                                       omega.astype(np.float64), Kmat=Kmat.astype(np.float64), r_first=0, r_count=2)
+    err = _circ_err(ph.cpu().numpy()[:2], ref)
+    print(f"dense coupling {coupling} at N = 8192: max phase error {err.max():.2e}")
+    assert err.max() <= tol
+
+
 def test_dense_uniform_matrix_equals_meanfield(gpu):
     """K_ij = K/N off the diagonal (zero diagonal) is the uniform model."""
     N, R = 1024, 32
