@@ -34,8 +34,14 @@
 namespace sde {
 
 // ---------------------------------------------------------------- MF ------
-constexpr int kMFThreads = 1024;
-constexpr uint32_t kMaxMFGroups = kMFThreads / 4;  // workgroups per realization (one polling lane per word)
+// Lanes per workgroup: 8 waves for the register-resident kernel (fewer
+// waves per barrier and more oscillators per lane run its stage faster than
+// 16), 16 for the streamed kernel (more loads in flight).  A realization has
+// at most lanes / 4 workgroups: one polling lane per exchange word.
+constexpr int kMFThreads = 512;
+constexpr int kMFSThreads = 1024;
+constexpr uint32_t kMaxMFGroups = kMFThreads / 4;
+constexpr uint32_t kMaxMFSGroups = kMFSThreads / 4;
 
 struct MFArgs {
     float* theta;            // [R][N] revolutions, in/out (this launch's realizations)
@@ -134,7 +140,7 @@ __device__ __forceinline__ void mf_sum_words(const uint32_t* words, uint32_t n, 
     }
 }
 
-template <typename Args>
+template <int NT, typename Args>
 __device__ __forceinline__ bool mf_exchange(const Args& A, uint32_t r, uint32_t w, uint32_t epoch, double s,
                                             double c, double* lds, uint32_t* words, int* lds_ok, double& S,
                                             double& C)
@@ -152,7 +158,7 @@ __device__ __forceinline__ bool mf_exchange(const Args& A, uint32_t r, uint32_t 
     if (threadIdx.x == 0) {
         double Sw = 0.0, Cw = 0.0;
 #pragma unroll
-        for (int k = 0; k < kMFThreads / kWave; ++k) {
+        for (int k = 0; k < NT / kWave; ++k) {
             Sw += lds[2 * k];
             Cw += lds[2 * k + 1];
         }
@@ -178,7 +184,7 @@ __device__ __forceinline__ bool mf_exchange(const Args& A, uint32_t r, uint32_t 
             mf_publish(slot2 + (uint64_t)x * kMFWordsPerGroup, tag, Sx, Cx);
         }
     }
-    uint32_t* w2 = words + kMFWordsPerGroup * kMaxMFGroups / 2;
+    uint32_t* w2 = words + kMFWordsPerGroup * (NT / 4) / 2;
     if (!mf_poll(A, 8 * kMFWordsPerGroup, [&](uint32_t t) { return slot2 + t; }, tag, w2, lds_ok)) return false;
     mf_sum_words(w2, 8, S, C);
     __syncthreads();
@@ -236,7 +242,7 @@ __global__ __launch_bounds__(kMFThreads, 1) void kuramoto_mf_kernel(MFArgs A)
             }
         }
         double S, C;
-        if (!mf_exchange(A, r, w, epoch, s, c, lds, words, &lds_ok, S, C)) return false;
+        if (!mf_exchange<kMFThreads>(A, r, w, epoch, s, c, lds, words, &lds_ok, S, C)) return false;
         ++epoch;
         Sd = S;
         Cd = C;
@@ -336,14 +342,14 @@ struct MFSArgs {
 };
 
 // Each pass takes kMFSBatch oscillators per lane per iteration (stride
-// kMFThreads), all loads first, to keep several memory requests in flight.
+// kMFSThreads), all loads first, to keep several memory requests in flight.
 constexpr int kMFSBatch = 4;
 
 template <int SCHEME>
-__global__ __launch_bounds__(kMFThreads, 1) void kuramoto_mfs_kernel(MFSArgs A)
+__global__ __launch_bounds__(kMFSThreads, 1) void kuramoto_mfs_kernel(MFSArgs A)
 {
-    __shared__ double lds[2 * kMFThreads / kWave];
-    __shared__ uint32_t words[kMFWordsPerGroup * kMaxMFGroups];
+    __shared__ double lds[2 * kMFSThreads / kWave];
+    __shared__ uint32_t words[kMFWordsPerGroup * kMaxMFSGroups];
     __shared__ int lds_ok;
     if (threadIdx.x == 0) lds_ok = 1;  // made visible by the exchange's first barrier
     const uint32_t r = blockIdx.x / A.G, w = blockIdx.x % A.G;
@@ -353,10 +359,10 @@ __global__ __launch_bounds__(kMFThreads, 1) void kuramoto_mfs_kernel(MFSArgs A)
     float* tl = A.tilde + (uint64_t)r * N;
     float* cy = A.carry + (uint64_t)r * N;
     const uint32_t rr = A.r_base + r;
-    constexpr uint64_t kStep = (uint64_t)kMFSBatch * kMFThreads;
+    constexpr uint64_t kStep = (uint64_t)kMFSBatch * kMFSThreads;
     uint32_t epoch = 0;
     auto exchange = [&](double s, double c, double& S, double& C) -> bool {
-        if (!mf_exchange(A, r, w, epoch, s, c, lds, words, &lds_ok, S, C)) return false;
+        if (!mf_exchange<kMFSThreads>(A, r, w, epoch, s, c, lds, words, &lds_ok, S, C)) return false;
         ++epoch;
         return true;
     };
@@ -365,12 +371,12 @@ __global__ __launch_bounds__(kMFThreads, 1) void kuramoto_mfs_kernel(MFSArgs A)
         float t[kMFSBatch];
 #pragma unroll
         for (int k = 0; k < kMFSBatch; ++k) {
-            const uint64_t i = b + (uint64_t)k * kMFThreads;
+            const uint64_t i = b + (uint64_t)k * kMFSThreads;
             t[k] = i < i1 ? th[i] : 0.f;
         }
 #pragma unroll
         for (int k = 0; k < kMFSBatch; ++k)
-            if (b + (uint64_t)k * kMFThreads < i1) {
+            if (b + (uint64_t)k * kMFSThreads < i1) {
                 s += (double)sin_rev(t[k]);
                 c += (double)cos_rev(t[k]);
             }
@@ -392,13 +398,13 @@ __global__ __launch_bounds__(kMFThreads, 1) void kuramoto_mfs_kernel(MFSArgs A)
             float t0[kMFSBatch], om[kMFSBatch];
 #pragma unroll
             for (int k = 0; k < kMFSBatch; ++k) {
-                const uint64_t i = b + (uint64_t)k * kMFThreads;
+                const uint64_t i = b + (uint64_t)k * kMFSThreads;
                 t0[k] = i < i1 ? th[i] : 0.f;
                 om[k] = i < i1 ? A.omega[i] : 0.f;
             }
 #pragma unroll
             for (int k = 0; k < kMFSBatch; ++k) {
-                const uint64_t i = b + (uint64_t)k * kMFThreads;
+                const uint64_t i = b + (uint64_t)k * kMFSThreads;
                 if (i >= i1) continue;
                 const float F1 = fmaf(A.kn, fmaf(cos_rev(t0[k]), Sf, -sin_rev(t0[k]) * Cf), om[k]);
                 const float ns =
@@ -427,13 +433,13 @@ __global__ __launch_bounds__(kMFThreads, 1) void kuramoto_mfs_kernel(MFSArgs A)
                 float tt[kMFSBatch], cv[kMFSBatch];
 #pragma unroll
                 for (int k = 0; k < kMFSBatch; ++k) {
-                    const uint64_t i = b + (uint64_t)k * kMFThreads;
+                    const uint64_t i = b + (uint64_t)k * kMFSThreads;
                     tt[k] = i < i1 ? tl[i] : 0.f;
                     cv[k] = i < i1 ? cy[i] : 0.f;
                 }
 #pragma unroll
                 for (int k = 0; k < kMFSBatch; ++k) {
-                    const uint64_t i = b + (uint64_t)k * kMFThreads;
+                    const uint64_t i = b + (uint64_t)k * kMFSThreads;
                     if (i >= i1) continue;
                     const float t = fmaf(A.hdt2pi, A.kn * fmaf(cos_rev(tt[k]), Sf, -sin_rev(tt[k]) * Cf), cv[k]);
                     const float u = t - floorf(t);
@@ -448,7 +454,7 @@ __global__ __launch_bounds__(kMFThreads, 1) void kuramoto_mfs_kernel(MFSArgs A)
         ++local;
     }
     bool bad = false;
-    for (uint64_t i = i0 + threadIdx.x; i < i1; i += kMFThreads) bad |= !isfinite(th[i]);
+    for (uint64_t i = i0 + threadIdx.x; i < i1; i += kMFSThreads) bad |= !isfinite(th[i]);
     if (__ballot(bad) != 0 && (threadIdx.x & (kWave - 1)) == 0) atomicOr(A.flag, 1);
 }
 
@@ -760,7 +766,7 @@ static void* mf_kernel_ptr()
 }
 
 // The streamed mean field: G workgroups per realization (as many as fit
-// co-resident, at most kMaxMFGroups), each owning a contiguous slice.
+// co-resident, at most kMaxMFSGroups), each owning a contiguous slice.
 static int run_meanfield_streamed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, float* phi,
                                   const float* omega, double* r_samples, uint64_t n_samples, uint32_t M,
                                   hipStream_t stream)
@@ -770,13 +776,13 @@ static int run_meanfield_streamed(sde_ctx* ctx, const sde_kuramoto_desc* d, cons
     void* kern = heun ? reinterpret_cast<void*>(kuramoto_mfs_kernel<SDE_HEUN>)
                       : reinterpret_cast<void*>(kuramoto_mfs_kernel<SDE_EULER>);
     int per_cu = 0;
-    SDE_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kMFThreads, 0));
+    SDE_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kMFSThreads, 0));
     const uint64_t capacity = (uint64_t)std::max(per_cu, 0) * ctx->n_cu;
     if (capacity == 0) return fail(ctx, SDE_ERR_UNSUPPORTED, "streamed mean-field kernel does not fit a CU");
     const uint32_t r_per_launch = (uint32_t)std::min<uint64_t>(d->R, capacity);
-    const uint64_t by_lanes = ((uint64_t)d->N + kMFThreads - 1) / kMFThreads;
+    const uint64_t by_lanes = ((uint64_t)d->N + kMFSThreads - 1) / kMFSThreads;
     const uint32_t G = (uint32_t)std::max<uint64_t>(
-        1, std::min<uint64_t>({(uint64_t)kMaxMFGroups, capacity / r_per_launch, by_lanes}));
+        1, std::min<uint64_t>({(uint64_t)kMaxMFSGroups, capacity / r_per_launch, by_lanes}));
     const uint32_t chunk = (uint32_t)(((uint64_t)d->N + G - 1) / G);
     const uint64_t NR = (uint64_t)d->N * d->R;
     if (run->init == SDE_INIT_PHILOX) {
@@ -823,7 +829,7 @@ static int run_meanfield_streamed(sde_ctx* ctx, const sde_kuramoto_desc* d, cons
         A.c2 = kc.c2;
         A.spin_limit = 1u << 26;
         void* args[] = {&A};
-        SDE_HIP(ctx, hipLaunchCooperativeKernel(kern, dim3(nr * G), dim3(kMFThreads), args, 0, stream));
+        SDE_HIP(ctx, hipLaunchCooperativeKernel(kern, dim3(nr * G), dim3(kMFSThreads), args, 0, stream));
     }
     ctx->last.mf_streamed = 1;
     return SDE_OK;
@@ -834,12 +840,10 @@ static int run_meanfield(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run
                          hipStream_t stream)
 {
     const KuraConsts kc = kuramoto_consts(d);
-    // oscillators per lane: smallest power of two so that one realization
-    // needs at most 16 workgroups of 1024 lanes
-    // oscillators per lane: smallest of 1, 2, 4 that needs at most 16
-    // workgroups of 1024 lanes per realization (more workgroups if N is larger)
+    // oscillators per lane: the smallest of 1, 2, ..., 16 that needs at most
+    // 16 workgroups per realization (more workgroups if N is larger)
     int opt = 1;
-    while (opt < 4 && (uint64_t)d->N > (uint64_t)16 * kMFThreads * opt) opt *= 2;
+    while (opt < 16 && (uint64_t)d->N > (uint64_t)16 * kMFThreads * opt) opt *= 2;
     const uint64_t G64 = (d->N + (uint64_t)kMFThreads * opt - 1) / ((uint64_t)kMFThreads * opt);
     const uint32_t G = (uint32_t)G64;
     void* kern = nullptr;
@@ -847,7 +851,9 @@ static int run_meanfield(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run
     switch (opt) {
     case 1: kern = heun ? mf_kernel_ptr<1, SDE_HEUN>() : mf_kernel_ptr<1, SDE_EULER>(); break;
     case 2: kern = heun ? mf_kernel_ptr<2, SDE_HEUN>() : mf_kernel_ptr<2, SDE_EULER>(); break;
-    default: kern = heun ? mf_kernel_ptr<4, SDE_HEUN>() : mf_kernel_ptr<4, SDE_EULER>(); break;
+    case 4: kern = heun ? mf_kernel_ptr<4, SDE_HEUN>() : mf_kernel_ptr<4, SDE_EULER>(); break;
+    case 8: kern = heun ? mf_kernel_ptr<8, SDE_HEUN>() : mf_kernel_ptr<8, SDE_EULER>(); break;
+    default: kern = heun ? mf_kernel_ptr<16, SDE_HEUN>() : mf_kernel_ptr<16, SDE_EULER>(); break;
     }
     int per_cu = 0;
     SDE_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kMFThreads, 0));
