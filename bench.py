@@ -91,7 +91,7 @@ PEAK_HBM = 8.0e12
 # Measured HBM bytes per oscillator-step of the streamed mean field (Fig. 4),
 # from profiles/kuramoto_fig4_hbm_counters.md; valid for that kernel source.
 FIG4_TRAFFIC_PER_OSC_STEP = 28.05
-FIG4_TRAFFIC_SOURCE_SHA1 = "7e3fab94c0f740d8911287908b67ffcda65c3c49"
+FIG4_TRAFFIC_SOURCE_SHA1 = "82fa5aac87989d0a864b0ddad5c1b282e932dd53"
 
 
 def _source_sha1(*files):
