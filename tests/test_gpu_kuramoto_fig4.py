@@ -73,12 +73,13 @@ def test_streamed_first_100_steps(gpu, scheme, N, R):
     np.testing.assert_allclose(rs.cpu().numpy(), rref, rtol=0, atol=1e-6)
 
 
-@pytest.mark.parametrize("streamed", [True, False])
-def test_tree_exchange_vs_oracle(gpu, streamed):
-    """N = 2^17, 2 realizations: 32 (registers) or 128 (streamed) workgroups
-    per realization, so the sums go through the two-level exchange (group
-    leaders, then the 8 group sums); first 100 steps against the oracle."""
-    N, R = 1 << 17, 2
+@pytest.mark.parametrize("streamed,N", [(True, 1 << 17), (False, 1 << 18)])
+def test_tree_exchange_vs_oracle(gpu, streamed, N):
+    """2 realizations of N = 2^17 streamed (128 workgroups per realization)
+    or N = 2^18 in registers (32 workgroups of 512 lanes x 16 oscillators),
+    so the sums go through the two-level exchange (group leaders, then the
+    8 group sums); first 100 steps against the oracle."""
+    R = 2
     cfg = sde_inputs.kuramoto_uniform(N=N, R=R)
     for scheme in (0, 1):
         ph, rs = _run(gpu, N, R, cfg["K"], cfg["D"], cfg["dt"], 100, scheme, cfg["seed"], cfg["omega"],
@@ -87,6 +88,24 @@ def test_tree_exchange_vs_oracle(gpu, streamed):
                                               scheme, cfg["seed"], cfg["omega"].astype(np.float64))
         err = _circ_err(ph.cpu().numpy(), ref)
         print(f"tree exchange, streamed {streamed}, scheme {scheme}: max phase error {err.max():.2e}")
+        assert err.max() <= 1e-5
+        np.testing.assert_allclose(rs.cpu().numpy(), rref, rtol=0, atol=1e-6)
+
+
+@pytest.mark.parametrize("N", [12289, 30001, 65535, 100003])
+def test_register_resident_lane_counts(gpu, N):
+    """The register-resident kernel at each count of oscillators per lane
+    (2, 4, 8, 16 for these N, at most 16 workgroups per realization; the
+    last workgroup ragged), Heun and Euler-Maruyama, 3 realizations."""
+    R = 3
+    cfg = sde_inputs.kuramoto_uniform(N=N, R=R)
+    for scheme in (0, 1):
+        ph, rs = _run(gpu, N, R, cfg["K"], cfg["D"], cfg["dt"], 100, scheme, cfg["seed"], cfg["omega"],
+                      streamed=False)
+        ref, rref = oracle.kuramoto_integrate(N, R, cfg["K"], cfg["D"], cfg["dt"], 100, 100, oracle.MEANFIELD,
+                                              scheme, cfg["seed"], cfg["omega"].astype(np.float64))
+        err = _circ_err(ph.cpu().numpy(), ref)
+        print(f"registers, N {N}, scheme {scheme}: max phase error {err.max():.2e}")
         assert err.max() <= 1e-5
         np.testing.assert_allclose(rs.cpu().numpy(), rref, rtol=0, atol=1e-6)
 
