@@ -170,10 +170,11 @@ __device__ __forceinline__ f32x4 mfma16(V a, V b, f32x4 c)
 
 // Stage update of a 128-row x 32-realization tile whose S and C sit in LDS
 // as tS[realization][row], tC[realization][row] (already unscaled), by NT
-// threads.  Lane t takes the oscillators t, t + NT, ... of the tile in row-fastest order, so
-// a wave's phase loads and stores cover 64 consecutive oscillators of one
-// realization (256 contiguous bytes; with 8 rows per lane the lanes sit 32
-// bytes apart and the L1 serves them one by one).  All of a lane's loads come
+// threads.  Lane t takes the oscillators t, t + NT, ... of the tile in
+// row-fastest order, so a wave's phase loads and stores cover 64 consecutive
+// oscillators of one realization (256 contiguous bytes; giving each lane 8
+// consecutive rows instead would put the lanes 32 bytes apart, and the L1
+// would serve them one by one).  All of a lane's loads come
 // before its first store: dst may be src (the in-place Euler step), so the
 // compiler could not move a load above a store.  sin and cos of the new
 // phase replace S and C in the tile (zero outside R x N), for the store of
