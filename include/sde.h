@@ -74,7 +74,7 @@ enum { SDE_TAG_NOISE = 0, SDE_TAG_INIT = 1 };
 enum {
     SDE_POTENTIAL_SIN = 0,    /* force -sin(phi), coordinate phi in radians: the        */
                               /* Josephson-junction (Stewart-McCumber) form             */
-    SDE_POTENTIAL_SIN2PI = 1  /* the paper's V(x) = sin(2 pi x) (Sec. 2): force         */
+    SDE_POTENTIAL_SIN2PI = 1  /* the paper's V(x) = sin(2 pi x) (Sec. 3): force         */
                               /* -2 pi cos(2 pi x), coordinate x in potential periods   */
 };
 
@@ -243,7 +243,7 @@ enum {
  * result is bitwise reproducible.  Writes host_out[g][0..1].  Synchronizes
  * `hip_stream`.  The standard error uses the n-1 sample variance (0 when
  * counts[g] < 2).  Example: <v> +- SE of each point from the per-path
- * `v` array of sde_jj_integrate (ensemble average, Sec. 3 and Sec. 5).
+ * `v` array of sde_jj_integrate (ensemble average, Sec. 4 and Sec. 5).
  */
 int sde_observables(sde_ctx* ctx, int kind, const void* dev_in /* [device] */,
                     const uint32_t* counts /* [host] */, uint32_t n_groups,

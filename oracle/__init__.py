@@ -11,9 +11,11 @@ their definitions, in double precision.
 Parity status of each routine:
   philox / gauss          pinned (rocRAND's Philox4x32-10, pure-Python
                           restatement, moment and KS tests)
-  jj_integrate            pinned (Boltzmann equilibrium moments, overdamped
-                          tilted-washboard velocity, order-2 convergence
-                          of the deterministic drive)
+  jj_integrate            pinned (Boltzmann equilibrium moments with inertia
+                          and in the overdamped limit at gamma != 1,
+                          overdamped relaxation variance from a well's
+                          bottom, overdamped tilted-washboard velocity,
+                          order-2 convergence of the deterministic drive)
   ou_integrate            pinned (exact stationary variance of the discrete
                           Heun / Euler schemes, continuum moments)
   kuramoto_integrate      pinned (free diffusion 2Dt, identical-oscillator
@@ -52,30 +54,36 @@ def lib():
         if not os.path.exists(LIBPATH):
             from . import build as _b
             _b.build()
-        L = ctypes.CDLL(LIBPATH)
-        P = ctypes.POINTER
-        d, u32, u64, i32 = ctypes.c_double, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
-        pd = P(d)
-        L.oracle_philox.argtypes = [u64, P(u32), P(u32)]
-        L.oracle_philox.restype = None
-        L.oracle_philox_stream.argtypes = [u64, u32, u32, u32, u64, u64, P(u32)]
-        L.oracle_philox_stream.restype = None
-        L.oracle_gauss.argtypes = [u64, u32, u32, u32, u64]
-        L.oracle_gauss.restype = d
-        L.oracle_gauss_stream.argtypes = [u64, u32, u32, u32, u64, u64, pd]
-        L.oracle_gauss_stream.restype = None
-        L.oracle_jj_integrate.argtypes = [P(JJPoint), u32, P(u32), u64, u64, i32, i32, pd, pd, pd, pd,
-                                          u32, pd, pd, i32]
-        L.oracle_jj_integrate.restype = i32
-        L.oracle_ou_integrate.argtypes = [d, d, d, u64, i32, u64, u32, pd, i32]
-        L.oracle_ou_integrate.restype = i32
-        L.oracle_kuramoto_integrate.argtypes = [u32, u32, d, d, d, u64, u32, i32, i32, u64, u64,
-                                                i32, pd, pd, pd, pd, u32, u32, i32]
-        L.oracle_kuramoto_integrate.restype = i32
-        L.oracle_kuramoto_rhs.argtypes = [u32, d, i32, pd, pd, pd, pd]
-        L.oracle_kuramoto_rhs.restype = None
-        _lib = L
+        _lib = load(LIBPATH)
     return _lib
+
+
+def load(path):
+    """Open an oracle shared object at `path` and declare its signatures
+    (the tests also load deliberately broken copies this way)."""
+    L = ctypes.CDLL(path)
+    P = ctypes.POINTER
+    d, u32, u64, i32 = ctypes.c_double, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+    pd = P(d)
+    L.oracle_philox.argtypes = [u64, P(u32), P(u32)]
+    L.oracle_philox.restype = None
+    L.oracle_philox_stream.argtypes = [u64, u32, u32, u32, u64, u64, P(u32)]
+    L.oracle_philox_stream.restype = None
+    L.oracle_gauss.argtypes = [u64, u32, u32, u32, u64]
+    L.oracle_gauss.restype = d
+    L.oracle_gauss_stream.argtypes = [u64, u32, u32, u32, u64, u64, pd]
+    L.oracle_gauss_stream.restype = None
+    L.oracle_jj_integrate.argtypes = [P(JJPoint), u32, P(u32), u64, u64, i32, i32, pd, pd, pd, pd,
+                                      u32, pd, pd, i32]
+    L.oracle_jj_integrate.restype = i32
+    L.oracle_ou_integrate.argtypes = [d, d, d, u64, i32, u64, u32, pd, i32]
+    L.oracle_ou_integrate.restype = i32
+    L.oracle_kuramoto_integrate.argtypes = [u32, u32, d, d, d, u64, u32, i32, i32, u64, u64,
+                                            i32, pd, pd, pd, pd, u32, u32, i32]
+    L.oracle_kuramoto_integrate.restype = i32
+    L.oracle_kuramoto_rhs.argtypes = [u32, d, i32, pd, pd, pd, pd]
+    L.oracle_kuramoto_rhs.restype = None
+    return L
 
 
 def _pd(a):

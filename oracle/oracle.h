@@ -67,7 +67,7 @@ void oracle_gauss_stream(uint64_t seed, uint32_t tag, uint32_t a, uint32_t b,
  *   ORC_POT_SIN    m phi'' + gamma phi' = -sin phi + a cos wt + f + noise
  *                  (the Josephson-junction form; coordinate phi in radians)
  *   ORC_POT_SIN2PI m x'' + gamma x' = -V'(x) + a cos wt + f + noise with the
- *                  paper's V(x) = sin(2 pi x) (Sec. 2; x in potential periods)
+ *                  paper's V(x) = sin(2 pi x) (Sec. 3; x in potential periods)
  * noise = sqrt(2 gamma D) xi(t) in both. */
 enum { ORC_POT_SIN = 0, ORC_POT_SIN2PI = 1 };
 
@@ -100,8 +100,10 @@ typedef struct {
  *                 larger batch draws the same random numbers as in the batch.
  * Returns 0, or -1 on invalid arguments.
  * Parity: pinned, for both potentials, by the equilibrium (Boltzmann)
- * moments, the overdamped washboard velocity and the deterministic order-2
- * convergence.
+ * moments with and without inertia (the overdamped limit at gamma != 1, so
+ * the drift's and the noise's powers of gamma both matter), the relaxation
+ * variance of the overdamped limit from the bottom of a well, the
+ * overdamped washboard velocity and the deterministic order-2 convergence.
  */
 int oracle_jj_integrate(const oracle_jj_point* pts, uint32_t n_pts, const uint32_t* point_ids,
                         uint64_t seed, uint64_t step0, int scheme, int init_from_state,

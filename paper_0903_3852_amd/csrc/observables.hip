@@ -1,5 +1,5 @@
 // observables.hip -- ensemble averages of per-path / per-oscillator arrays
-// (the quantities of interest of Sec. 3: averages over realizations, the
+// (the quantities of interest of Sec. 4: averages over realizations, the
 // asymptotic velocity of Sec. 5, the Kuramoto order parameter).
 //
 // One workgroup per group.  Thread t takes elements t, t + 256, ... in FP64;

@@ -1,5 +1,5 @@
 """GPU parity of the paper's own form of Eq. 1 -- V(x) = sin(2 pi x), x in
-potential periods (Sec. 2, Fig. 2) -- and of the coarse-grained position
+potential periods (Sec. 3, Fig. 2) -- and of the coarse-grained position
 histogram (one bin per period), through the C ABI.
 
 Tolerances:

@@ -167,7 +167,7 @@ def test_jj_euler_order_one(orc):
     assert np.all(np.abs(slopes - 1) < 0.2), (errs, slopes)
 
 
-# ---- the paper's own potential V(x) = sin(2 pi x), x in periods (Sec. 2) ----
+# ---- the paper's own potential V(x) = sin(2 pi x), x in periods (Sec. 3) ----
 P2 = sde_inputs.POT_SIN2PI
 
 
@@ -233,7 +233,7 @@ def test_jj_sin2pi_deterministic_order_two(orc):
 
 def test_jj_sin2pi_absolute_negative_mobility(orc):
     """The Fig. 2 parameters (a = 4.2, gamma = 0.9, omega = 4.9, D = 0.001)
-    lie in the anomalous-response regime the paper names (Sec. 2): a small
+    lie in the anomalous-response regime the paper names (Sec. 3): a small
     bias f = +0.1 drives a negative mean velocity, f = -0.1 a positive one,
     each more than 5 standard errors from zero (512 paths, 100 periods of
     transient, 300 averaged).  Only the sign is pinned; the magnitude still
