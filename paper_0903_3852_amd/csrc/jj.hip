@@ -517,6 +517,29 @@ static int jj_record(sde_ctx* ctx, const JJLaunch& L, hipStream_t s)
     return SDE_OK;
 }
 
+// The graph cache key of one call: every value the recorded launches bake
+// in -- each field of the kernel arguments (the per-kind item range and queue
+// word are derived from kind_begin and the counters, whose moves bump the
+// workspace generation), the kernel choice, the grids and the point-sum
+// launch.  A field left out would let a later call replay a graph recorded
+// with a stale value.
+static std::string jj_graph_key(const char* prec, const JJLaunch& L)
+{
+    const JJArgs& A = L.A;
+    char buf[640];
+    snprintf(buf, sizeof buf,
+             "jj|%s|pts%p|it%p|lut%p|fl%p|th%p|wd%p|v%p|acc%p|pa%p|rec%p/%llu/%u|n0%llu|k%u.%u|ni%u|M%u|ini%d|"
+             "ppt%d|sch%d|np%u|ps%p",
+             prec, A.pts, (const void*)A.items, A.lut, (void*)A.flag, A.theta, (void*)A.winding, A.v, (void*)A.acc,
+             (void*)A.partials, (void*)A.rec, (unsigned long long)A.rec_pitch, A.rec_every,
+             (unsigned long long)A.step0, A.key0, A.key1, L.n_items, A.M, A.init_from_state, L.ppt, L.scheme,
+             L.n_pts, (void*)L.point_sums);
+    std::string k = buf;
+    for (int kind = 0; kind < kJJKinds; ++kind)
+        k += "|" + std::to_string(L.kind_begin[kind + 1]) + "/" + std::to_string(L.grid[kind]);
+    return k;
+}
+
 template <typename R>
 static int jj_upload_plan(sde_ctx* ctx, const JJPlan<R>& plan, hipStream_t stream, JJLaunch& L)
 {
@@ -750,18 +773,8 @@ static int jj_integrate_t(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts,
     ctx->last.jj_paths_per_lane = ppt;
     ctx->last.work_items = plan.items.size();
 
-    // everything baked into the recorded launches
-    char key[512];
-    snprintf(key, sizeof key, "jj|%s|%p|%p|%p|%p|%p|%p|%p|%llu|%u|%u|%u|%d|%d|%d|%u|%u", prec, L.A.pts,
-             (const void*)L.A.items, L.A.lut, (void*)theta, (void*)winding, (void*)v, (void*)acc,
-             (unsigned long long)run->step0, L.A.key0, L.A.key1, M, L.A.init_from_state, ppt, run->scheme,
-             L.n_items, L.n_pts);
-    std::string k = key;
-    for (int kind = 0; kind < kJJKinds; ++kind)
-        k += "|" + std::to_string(L.kind_begin[kind + 1]) + "/" + std::to_string(L.grid[kind]);
-    k += point_sums ? "|ps" + std::to_string((uintptr_t)point_sums) : "|ps0";
-    if (rec) k += "|rec" + std::to_string((uintptr_t)rec) + "/" + std::to_string(rec_every);
-    if ((st = run_recorded(ctx, k, stream, [&](hipStream_t s) { return jj_record<R>(ctx, L, s); }))) return st;
+    if ((st = run_recorded(ctx, jj_graph_key(prec, L), stream, [&](hipStream_t s) { return jj_record<R>(ctx, L, s); })))
+        return st;
     if (run->sync) return sync_and_check(ctx, stream);
     return SDE_OK;
 }

@@ -205,3 +205,37 @@ def test_recorded_invalid_arguments_leave_outputs(gpu):
     w = torch.zeros((2, 8), dtype=torch.int32, device=dev)
     with pytest.raises(sde.SDEError):
         sde.sde_position_histograms(ctx, w, 0, 10, counts, n=9)  # pitch < n with several rows
+
+
+def test_recorded_graph_follows_the_path_count(gpu):
+    """Graphs on (the default), the same buffers, 2 paths per lane (one
+    128-path chunk): recorded calls at 128, 100 and again 128 paths.  The
+    row pitch is the call's path count, so the 100-path call must not replay
+    the 128-path graph; each call equals the same call with graphs off, the
+    record buffer of the 100-path call is exactly rows x 100, and what lies
+    beyond it in the storage keeps its contents.  The third call replays the
+    first one's graph."""
+    sde, ctx, dev = gpu
+    sde.sde_set_option(ctx, sde.SDE_OPT_JJ_PPT, 2)
+    every, seed, n_steps = 8, 41, 64
+    rows = n_steps // every
+    store = torch.full((rows * 128 + 512,), -5, dtype=torch.int32, device=dev)
+    st = _state(128, dev)
+    replayed = []
+    for n in (128, 100, 128):
+        pt = [sde_inputs.jj_point(n_paths=n, n_steps=n_steps, D=0.01, steps_per_period=200)]
+        assert _rows_needed(pt[0], 0, every) == rows
+        store.fill_(-5)
+        rec = store[:rows * n].view(rows, n)
+        sde.sde_set_option(ctx, sde.SDE_OPT_GRAPHS, 1)
+        sde.sde_jj_integrate_recorded(ctx, pt, sde.make_run(seed, sync=1), every, rec, *(x[:n] for x in st))
+        replayed.append(sde.sde_get_stats(ctx)["graph_replayed"])
+        sde.sde_set_option(ctx, sde.SDE_OPT_GRAPHS, 0)
+        rec_e = torch.full((rows, n), -5, dtype=torch.int32, device=dev)
+        st_e = _state(n, dev)
+        sde.sde_jj_integrate_recorded(ctx, pt, sde.make_run(seed, sync=1), every, rec_e, *st_e)
+        assert torch.equal(rec, rec_e), n
+        for x, y in zip(st, st_e):
+            assert torch.equal(x[:n], y), n
+        assert bool((store[rows * n:] == -5).all()), n
+    assert replayed[2] == 1, replayed
