@@ -159,6 +159,34 @@ int sde_jj_integrate(sde_ctx* ctx, const sde_jj_point* pts /* [host] */, uint32_
                      double* point_sums, void* hip_stream);
 
 /*
+ * For callers that cannot allocate memory during a call (code that must not
+ * call hipMalloc, tight serving loops, harnesses that forbid allocation):
+ * sde_jj_integrate with the same arguments, results and errors, that
+ * allocates nothing.  Its work-queue words, point table, work items, drive
+ * tables and per-chunk partial sums live in a static device array of the
+ * library (8 MiB, held by every GPU the library runs on until the process
+ * ends), whose address sde_create looks up once per device; the host image
+ * of the tables goes through a pinned buffer that sde_create reserves
+ * (8 MiB per context).  No graphs are recorded and nothing is tuned: the
+ * paths per lane are the forced option, else a choice the autotuner of
+ * sde_jj_integrate cached for this shape class, else 2 (the result does not
+ * depend on it).  Host-side planning uses ordinary heap memory.
+ * Every call on one GPU shares that GPU's array, which keeps the last
+ * call's contents (the queue words are cleared by each call): calls that
+ * overlap on one GPU -- from several contexts, or on streams not ordered
+ * after each other -- race.  Calls on one context wait, before writing the
+ * pinned buffer, for the previous call's copy out of it.
+ * Errors: those of sde_jj_integrate, and SDE_ERR_INVALID when the call needs
+ * more than 8 MiB of scratch: 96 B per point, 24 B per chunk of 64 x (paths
+ * per lane) paths of a point, 4 B per drive-table entry (S + 8 per distinct
+ * steps_per_period), each table rounded up to 256 B.  The 16384-point,
+ * 1024-path scan needs 4.5 MiB at 2 paths per lane, 7.5 MiB at 1.
+ */
+int sde_jj_integrate_noalloc(sde_ctx* ctx, const sde_jj_point* pts /* [host] */, uint32_t n_pts,
+                             const sde_run* run, float* theta, int32_t* winding, float* v, double* acc,
+                             double* point_sums, void* hip_stream);
+
+/*
  * sde_jj_integrate in double precision throughout (the paper's precision
  * study, Sec. 5 and Fig. 2): the same points, run options, noise streams and
  * layout, with theta and v as device double arrays and every operation of

@@ -30,7 +30,8 @@ SDE_OPT_AUTOTUNE, SDE_OPT_GRAPHS, SDE_OPT_JJ_PPT, SDE_OPT_KURA_MF, SDE_OPT_KURA_
     1, 2, 3, 4, 5, 6
 
 EXPORTS = ["sde_create", "sde_destroy", "sde_strerror", "sde_last_error", "sde_check",
-           "sde_jj_integrate", "sde_jj_integrate_f64", "sde_jj_integrate_recorded", "sde_kuramoto_integrate",
+           "sde_jj_integrate", "sde_jj_integrate_noalloc", "sde_jj_integrate_f64", "sde_jj_integrate_recorded",
+           "sde_kuramoto_integrate",
            "sde_observables", "sde_position_histogram", "sde_position_histograms", "sde_phase_histograms",
            "sde_debug_philox", "sde_debug_gauss", "sde_set_option", "sde_set_tune_cache",
            "sde_get_stats", "sde_surrogate_create", "sde_surrogate_destroy",
@@ -118,6 +119,8 @@ def lib():
         L.sde_jj_integrate.argtypes = [vp, ctypes.POINTER(sde_jj_point), u32, ctypes.POINTER(sde_run),
                                        vp, vp, vp, vp, vp, vp]
         L.sde_jj_integrate.restype = i32
+        L.sde_jj_integrate_noalloc.argtypes = L.sde_jj_integrate.argtypes
+        L.sde_jj_integrate_noalloc.restype = i32
         L.sde_jj_integrate_f64.argtypes = [vp, ctypes.POINTER(sde_jj_point), u32, ctypes.POINTER(sde_run),
                                            vp, vp, vp, vp, vp, vp]
         L.sde_jj_integrate_f64.restype = i32
@@ -284,6 +287,17 @@ def sde_jj_integrate(ctx, pts, run, theta=None, winding=None, v=None, acc=None, 
     return _check(ctx, lib().sde_jj_integrate(ctx, pts, len(pts), ctypes.byref(run), _ptr(theta),
                                               _ptr(winding), _ptr(v), _ptr(acc), _ptr(point_sums),
                                               _stream(stream)))
+
+
+def sde_jj_integrate_noalloc(ctx, pts, run, theta=None, winding=None, v=None, acc=None, point_sums=None,
+                             stream=None):
+    """As sde_jj_integrate, through the entry point that allocates nothing
+    (static device scratch of the library)."""
+    if not isinstance(pts, ctypes.Array):
+        pts = make_points(pts)
+    return _check(ctx, lib().sde_jj_integrate_noalloc(ctx, pts, len(pts), ctypes.byref(run), _ptr(theta),
+                                                      _ptr(winding), _ptr(v), _ptr(acc), _ptr(point_sums),
+                                                      _stream(stream)))
 
 
 def sde_jj_integrate_f64(ctx, pts, run, theta=None, winding=None, v=None, acc=None, point_sums=None,

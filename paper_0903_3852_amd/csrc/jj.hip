@@ -38,6 +38,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <map>
+#include <mutex>
 
 #include "device_common.h"
 #include "sde_internal.h"
@@ -466,6 +467,7 @@ static void plan_items(std::vector<JJPointT<R>>& P, const std::vector<int>& kind
 
 struct JJLaunch {
     JJArgs A;
+    uint32_t* queues;  // kJJKinds work-queue words, zeroed by each launch sequence
     int ppt;
     int scheme;
     uint32_t kind_begin[kJJKinds + 1];
@@ -491,20 +493,25 @@ static int jj_grids(sde_ctx* ctx, JJLaunch& L)
     return SDE_OK;
 }
 
+__global__ void jj_zero_queues_kernel(uint32_t* q)
+{
+    if (threadIdx.x < (uint32_t)kJJKinds) q[threadIdx.x] = 0u;
+}
+
 // The launch sequence of one call: reset the queues, the persistent kernel
 // of each point kind present, the per-point sums.
 template <typename R>
 static int jj_record(sde_ctx* ctx, const JJLaunch& L, hipStream_t s)
 {
-    int st = zero_counters(ctx, 0, kJJKinds, s);
-    if (st) return st;
+    hipLaunchKernelGGL(jj_zero_queues_kernel, dim3(1), dim3(64), 0, s, L.queues);
+    SDE_HIP(ctx, hipGetLastError());
     const JJItem* all = L.A.items;
     for (int kind = 0; kind < kJJKinds; ++kind) {
         if (!L.grid[kind]) continue;
         JJArgs A = L.A;
         A.items = all + L.kind_begin[kind];
         A.n_items = L.kind_begin[kind + 1] - L.kind_begin[kind];
-        A.queue = ctx->counters + kind;
+        A.queue = L.queues + kind;
         JJKernel kern = pick_kernel<R>(kind, L.ppt, L.scheme);
         hipLaunchKernelGGL(kern, dim3(L.grid[kind]), dim3(256), 0, s, A);
         SDE_HIP(ctx, hipGetLastError());
@@ -519,19 +526,18 @@ static int jj_record(sde_ctx* ctx, const JJLaunch& L, hipStream_t s)
 
 // The graph cache key of one call: every value the recorded launches bake
 // in -- each field of the kernel arguments (the per-kind item range and queue
-// word are derived from kind_begin and the counters, whose moves bump the
-// workspace generation), the kernel choice, the grids and the point-sum
-// launch.  A field left out would let a later call replay a graph recorded
+// word are derived from kind_begin and the queue words), the kernel choice,
+// the grids and the point-sum launch.  A field left out would let a later call replay a graph recorded
 // with a stale value.
 static std::string jj_graph_key(const char* prec, const JJLaunch& L)
 {
     const JJArgs& A = L.A;
     char buf[640];
     snprintf(buf, sizeof buf,
-             "jj|%s|pts%p|it%p|lut%p|fl%p|th%p|wd%p|v%p|acc%p|pa%p|rec%p/%llu/%u|n0%llu|k%u.%u|ni%u|M%u|ini%d|"
+             "jj|%s|pts%p|it%p|lut%p|q%p|fl%p|th%p|wd%p|v%p|acc%p|pa%p|rec%p/%llu/%u|n0%llu|k%u.%u|ni%u|M%u|ini%d|"
              "ppt%d|sch%d|np%u|ps%p",
-             prec, A.pts, (const void*)A.items, A.lut, (void*)A.flag, A.theta, (void*)A.winding, A.v, (void*)A.acc,
-             (void*)A.partials, (void*)A.rec, (unsigned long long)A.rec_pitch, A.rec_every,
+             prec, A.pts, (const void*)A.items, A.lut, (void*)L.queues, (void*)A.flag, A.theta, (void*)A.winding, A.v,
+             (void*)A.acc, (void*)A.partials, (void*)A.rec, (unsigned long long)A.rec_pitch, A.rec_every,
              (unsigned long long)A.step0, A.key0, A.key1, L.n_items, A.M, A.init_from_state, L.ppt, L.scheme,
              L.n_pts, (void*)L.point_sums);
     std::string k = buf;
@@ -551,6 +557,7 @@ static int jj_upload_plan(sde_ctx* ctx, const JJPlan<R>& plan, hipStream_t strea
     if ((st = ensure_ws(ctx, kSlotJJPartials, (size_t)std::max(plan.n_chunks, 1u) * 2 * sizeof(double), &partials)))
         return st;
     if ((st = ensure_counters(ctx, kJJKinds))) return st;
+    L.queues = ctx->counters;
     L.A.pts = ctx->ws[kSlotJJPoints].ptr;
     L.A.items = static_cast<const JJItem*>(ctx->ws[kSlotJJItems].ptr);
     L.A.partials = static_cast<double*>(partials);
@@ -629,10 +636,23 @@ static int jj_tune(sde_ctx* ctx, const std::vector<JJPointT<R>>& P0, const std::
     return st;
 }
 
+// What one call computes, from its arguments: per-point constants, point
+// kinds, the drive tables, and the shape class of the call.
 template <typename R>
-static int jj_integrate_t(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run, R* theta,
-                          int32_t* winding, R* v, double* acc, double* point_sums, int32_t* rec,
-                          uint32_t rec_every, uint64_t rec_rows, hipStream_t stream)
+struct JJSetup {
+    std::vector<JJPointT<R>> P;
+    std::vector<int> kinds;
+    std::vector<R> lut;
+    uint64_t path_first = 0, max_steps = 0;
+    unsigned kinds_present = 0;
+    uint32_t M = 100;
+};
+
+// Validates a call's arguments (nothing is launched on an error) and builds
+// its per-point constants and drive tables.
+template <typename R>
+static int jj_setup(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run, R* theta,
+                    int32_t* winding, R* v, double* acc, double* point_sums, JJSetup<R>& out)
 {
     ctx->last = sde_stats{};
     if (!pts || !run || n_pts == 0) return fail(ctx, SDE_ERR_INVALID, "null points/run or n_pts = 0");
@@ -645,12 +665,15 @@ static int jj_integrate_t(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts,
     if (!aligned(theta, sizeof(R)) || !aligned(winding, 4) || !aligned(v, sizeof(R)) || !aligned(acc, 8) ||
         !aligned(point_sums, 8))
         return fail(ctx, SDE_ERR_INVALID, "misaligned device pointer");
-    const uint32_t M = run->sample_every ? run->sample_every : 100u;
+    out.M = run->sample_every ? run->sample_every : 100u;
 
-    std::vector<JJPointT<R>> P(n_pts);
-    std::vector<int> kinds(n_pts);
+    std::vector<JJPointT<R>>& P = out.P;
+    std::vector<int>& kinds = out.kinds;
+    std::vector<R>& lut = out.lut;
+    P.assign(n_pts, JJPointT<R>{});
+    kinds.assign(n_pts, 0);
+    lut.clear();
     std::map<uint32_t, uint32_t> lut_of;  // S -> offset
-    std::vector<R> lut;
     uint64_t path_first = 0, max_steps = 0;
     unsigned kinds_present = 0;
     for (uint32_t q = 0; q < n_pts; ++q) {
@@ -715,6 +738,54 @@ static int jj_integrate_t(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts,
         max_steps = std::max<uint64_t>(max_steps, p.n_steps);
     }
     if (path_first / kWave > 0xffffffffull) return fail(ctx, SDE_ERR_INVALID, "too many paths in one call");
+    out.path_first = path_first;
+    out.max_steps = max_steps;
+    out.kinds_present = kinds_present;
+    return SDE_OK;
+}
+
+// The kernel arguments that come from the run options and the caller's
+// buffers (the workspace pointers are filled in by the caller).
+template <typename R>
+static void jj_fill_args(sde_ctx* ctx, const sde_run* run, const JJSetup<R>& S, R* theta, int32_t* winding, R* v,
+                         double* acc, double* point_sums, JJLaunch& L)
+{
+    L.scheme = run->scheme;
+    L.point_sums = point_sums;
+    L.A.flag = ctx->flag;
+    L.A.theta = theta;
+    L.A.winding = winding;
+    L.A.v = v;
+    L.A.acc = acc;
+    L.A.step0 = run->step0;
+    L.A.rec = nullptr;
+    L.A.rec_pitch = S.path_first;
+    L.A.rec_every = 0u;
+    L.A.key0 = (uint32_t)(run->seed & 0xffffffffu);
+    L.A.key1 = (uint32_t)(run->seed >> 32);
+    L.A.M = S.M;
+    L.A.init_from_state = run->init == SDE_INIT_FROM_STATE;
+}
+
+// Tune-cache key of a call's shape class (paths per lane).
+template <typename R>
+static std::string jj_tune_key(sde_ctx* ctx, const sde_run* run, const JJSetup<R>& S)
+{
+    char key[160];
+    snprintf(key, sizeof key, "jj|%s|%s|scheme%d|kinds%x|paths2^%d|steps2^%d", ctx->arch.c_str(),
+             sizeof(R) == 4 ? "f32" : "f64", run->scheme, S.kinds_present, ilog2u64(S.path_first),
+             ilog2u64(std::max<uint64_t>(S.max_steps, 1)));
+    return key;
+}
+
+template <typename R>
+static int jj_integrate_t(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run, R* theta,
+                          int32_t* winding, R* v, double* acc, double* point_sums, int32_t* rec,
+                          uint32_t rec_every, uint64_t rec_rows, hipStream_t stream)
+{
+    JJSetup<R> S;
+    int st = jj_setup<R>(ctx, pts, n_pts, run, theta, winding, v, acc, point_sums, S);
+    if (st) return st;
     if (rec) {
         if (rec_every == 0 || rec_every % 4 != 0)
             return fail(ctx, SDE_ERR_INVALID, "record_every must be a positive multiple of 4");
@@ -727,39 +798,24 @@ static int jj_integrate_t(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts,
         }
     }
 
-    int st;
-    if ((st = upload(ctx, kSlotJJLut, 2, lut.data(), lut.size() * sizeof(R), stream))) return st;
+    if ((st = upload(ctx, kSlotJJLut, 2, S.lut.data(), S.lut.size() * sizeof(R), stream))) return st;
     JJLaunch L;
-    L.scheme = run->scheme;
-    L.point_sums = point_sums;
+    jj_fill_args<R>(ctx, run, S, theta, winding, v, acc, point_sums, L);
     L.A.lut = ctx->ws[kSlotJJLut].ptr;
-    L.A.flag = ctx->flag;
-    L.A.theta = theta;
-    L.A.winding = winding;
-    L.A.v = v;
-    L.A.acc = acc;
-    L.A.step0 = run->step0;
     L.A.rec = rec;
-    L.A.rec_pitch = path_first;
     L.A.rec_every = rec ? rec_every : 0u;
-    L.A.key0 = (uint32_t)(run->seed & 0xffffffffu);
-    L.A.key1 = (uint32_t)(run->seed >> 32);
-    L.A.M = M;
-    L.A.init_from_state = run->init == SDE_INIT_FROM_STATE;
     const char* prec = sizeof(R) == 4 ? "f32" : "f64";
 
     // paths per lane: forced, cached, or tuned on this call's shape class
     int ppt = ctx->jj_ppt;
     if (sizeof(R) == 8 && ppt == 4) ppt = 2;
     if (!ppt) {
-        char key[160];
-        snprintf(key, sizeof key, "jj|%s|%s|scheme%d|kinds%x|paths2^%d|steps2^%d", ctx->arch.c_str(), prec,
-                 run->scheme, kinds_present, ilog2u64(path_first), ilog2u64(std::max<uint64_t>(max_steps, 1)));
+        const std::string key = jj_tune_key<R>(ctx, run, S);
         if (!tune_lookup(ctx, key, &ppt)) {
             ppt = 2;
             if (ctx->autotune) {
                 const auto t0 = std::chrono::steady_clock::now();
-                if ((st = jj_tune<R>(ctx, P, kinds, L, stream, &ppt))) return st;
+                if ((st = jj_tune<R>(ctx, S.P, S.kinds, L, stream, &ppt))) return st;
                 ctx->last.tuned = 1;
                 ctx->last.tune_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
                 tune_store(ctx, key, ppt);
@@ -768,7 +824,7 @@ static int jj_integrate_t(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts,
     }
     L.ppt = ppt;
     JJPlan<R> plan;
-    plan_items(P, kinds, ppt, plan);
+    plan_items(S.P, S.kinds, ppt, plan);
     if ((st = jj_upload_plan(ctx, plan, stream, L))) return st;
     ctx->last.jj_paths_per_lane = ppt;
     ctx->last.work_items = plan.items.size();
@@ -800,6 +856,110 @@ int jj_integrate_f64_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts,
                           hipStream_t stream)
 {
     return jj_integrate_t<double>(ctx, pts, n_pts, run, theta, winding, v, acc, point_sums, nullptr, 0, 0, stream);
+}
+
+// ---------------------------------------------- the no-allocation variant --
+// Device scratch of sde_jj_integrate_noalloc: the queue words, point table,
+// work items, drive tables and per-chunk partial sums of one call, in
+// 256-byte aligned sections.  Each GPU the library runs on holds its own copy
+// until the process ends; every such call on that GPU uses it.
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+// Device address of `scratch` per device (host code must never pass the
+// array's own name to a kernel or a copy: on the host it is a stand-in).
+static void* g_scratch_addr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+int noalloc_setup(sde_ctx* ctx)
+{
+    if (ctx->device < 0 || ctx->device >= kMaxDevices)
+        return fail(ctx, SDE_ERR_UNSUPPORTED, "device %d: beyond the %d devices the library tracks", ctx->device,
+                    kMaxDevices);
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (!g_scratch_addr[ctx->device]) {
+            void* ptr = nullptr;
+            // the caller has made ctx->device current
+            const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (e != hipSuccess || !ptr)
+                return fail(ctx, SDE_ERR_DEVICE, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+            g_scratch_addr[ctx->device] = ptr;
+        }
+        ctx->noalloc_scratch = g_scratch_addr[ctx->device];
+    }
+    // the host image of a call's tables is staged here (pinned, so the copy
+    // is asynchronous); it is never larger than the scratch
+    SDE_HIP(ctx, hipHostMalloc(&ctx->noalloc_staging, kNoAllocScratchBytes, hipHostMallocDefault));
+    SDE_HIP(ctx, hipEventCreateWithFlags(&ctx->noalloc_done, hipEventDisableTiming));
+    return SDE_OK;
+}
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int jj_integrate_noalloc_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run,
+                              float* theta, int32_t* winding, float* v, double* acc, double* point_sums,
+                              hipStream_t stream)
+{
+    if (!ctx->noalloc_scratch || !ctx->noalloc_staging || !ctx->noalloc_done)
+        return fail(ctx, SDE_ERR_DEVICE, "the no-allocation scratch was not set up for this context");
+    JJSetup<float> S;
+    int st = jj_setup<float>(ctx, pts, n_pts, run, theta, winding, v, acc, point_sums, S);
+    if (st) return st;
+    // paths per lane: forced, else a choice the tuner cached, else 2; never
+    // tuned here (tuning allocates)
+    int ppt = ctx->jj_ppt;
+    if (!ppt && !tune_lookup(ctx, jj_tune_key<float>(ctx, run, S), &ppt)) ppt = 2;
+    JJPlan<float> plan;
+    plan_items(S.P, S.kinds, ppt, plan);
+
+    // layout of the scratch; the tables [o_pts, o_part) are one host image
+    const size_t pts_bytes = plan.pts.size() * sizeof(JJPointDev);
+    const size_t items_bytes = plan.items.size() * sizeof(JJItem);
+    const size_t lut_bytes = S.lut.size() * sizeof(float);
+    const size_t part_bytes = (size_t)std::max(plan.n_chunks, 1u) * 2 * sizeof(double);
+    const size_t o_queue = 0;
+    const size_t o_pts = align256(o_queue + kJJKinds * sizeof(uint32_t));
+    const size_t o_items = align256(o_pts + pts_bytes);
+    const size_t o_lut = align256(o_items + items_bytes);
+    const size_t o_part = align256(o_lut + lut_bytes);
+    const size_t need = o_part + part_bytes;
+    if (need > kNoAllocScratchBytes)
+        return fail(ctx, SDE_ERR_INVALID,
+                    "sde_jj_integrate_noalloc: %u points in %u path chunks need %zu bytes of scratch, the maximum "
+                    "is %zu",
+                    n_pts, plan.n_chunks, need, (size_t)kNoAllocScratchBytes);
+
+    // the previous call's copy may still read the staging buffer
+    if (ctx->noalloc_pending) {
+        SDE_HIP(ctx, hipEventSynchronize(ctx->noalloc_done));
+        ctx->noalloc_pending = false;
+    }
+    unsigned char* img = static_cast<unsigned char*>(ctx->noalloc_staging);
+    std::memcpy(img, plan.pts.data(), pts_bytes);
+    std::memcpy(img + (o_items - o_pts), plan.items.data(), items_bytes);
+    std::memcpy(img + (o_lut - o_pts), S.lut.data(), lut_bytes);
+    unsigned char* base = static_cast<unsigned char*>(ctx->noalloc_scratch);
+    SDE_HIP(ctx, hipMemcpyAsync(base + o_pts, img, o_part - o_pts, hipMemcpyHostToDevice, stream));
+    SDE_HIP(ctx, hipEventRecord(ctx->noalloc_done, stream));
+    ctx->noalloc_pending = true;
+
+    JJLaunch L;
+    jj_fill_args<float>(ctx, run, S, theta, winding, v, acc, point_sums, L);
+    L.ppt = ppt;
+    L.queues = reinterpret_cast<uint32_t*>(base + o_queue);
+    L.A.pts = base + o_pts;
+    L.A.items = reinterpret_cast<const JJItem*>(base + o_items);
+    L.A.lut = base + o_lut;
+    L.A.partials = reinterpret_cast<double*>(base + o_part);
+    std::copy(plan.kind_begin, plan.kind_begin + kJJKinds + 1, L.kind_begin);
+    L.n_items = (uint32_t)plan.items.size();
+    L.n_pts = (uint32_t)plan.pts.size();
+    if ((st = jj_grids<float>(ctx, L))) return st;
+    ctx->last.jj_paths_per_lane = ppt;
+    ctx->last.work_items = plan.items.size();
+    if ((st = jj_record<float>(ctx, L, stream))) return st;
+    if (run->sync) return sync_and_check(ctx, stream);
+    return SDE_OK;
 }
 
 int debug_philox_impl(sde_ctx* ctx, uint64_t seed, uint32_t tag, uint32_t a, uint32_t b, uint64_t c0,

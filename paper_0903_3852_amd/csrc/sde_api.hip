@@ -261,6 +261,10 @@ int sde_create(int hip_device, sde_ctx** out)
         sde_destroy(ctx);
         return SDE_ERR_NOMEM;
     }
+    if (const int st = noalloc_setup(ctx)) {
+        sde_destroy(ctx);
+        return st;
+    }
     if (const char* tc = std::getenv("SDE_TUNE_CACHE")) {
         ctx->tune_path = tc;
         tune_load(ctx);
@@ -282,6 +286,8 @@ void sde_destroy(sde_ctx* ctx)
     }
     for (auto& g : ctx->graphs) drop_graph(g);
     if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
+    if (ctx->noalloc_staging) (void)hipHostFree(ctx->noalloc_staging);
+    if (ctx->noalloc_done) (void)hipEventDestroy(ctx->noalloc_done);
     if (ctx->flag) (void)hipFree(ctx->flag);
     if (ctx->tune_flag) (void)hipFree(ctx->tune_flag);
     if (ctx->counters) (void)hipFree(ctx->counters);
@@ -369,6 +375,20 @@ int sde_jj_integrate(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, cons
     try {
         return jj_integrate_impl(ctx, pts, n_pts, run, theta, winding, v, acc, point_sums,
                                  static_cast<hipStream_t>(hip_stream));
+    } catch (...) {
+        return fail(ctx, SDE_ERR_NOMEM, "host allocation failed");
+    }
+}
+
+int sde_jj_integrate_noalloc(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run,
+                             float* theta, int32_t* winding, float* v, double* acc, double* point_sums,
+                             void* hip_stream)
+{
+    if (!ctx) return SDE_ERR_INVALID;
+    ctx->last_error.clear();
+    try {
+        return jj_integrate_noalloc_impl(ctx, pts, n_pts, run, theta, winding, v, acc, point_sums,
+                                         static_cast<hipStream_t>(hip_stream));
     } catch (...) {
         return fail(ctx, SDE_ERR_NOMEM, "host allocation failed");
     }

@@ -68,9 +68,20 @@ struct sde_ctx {
     std::map<std::string, int> tune;
     std::string tune_path;
     sde_stats last{};
+    // sde_jj_integrate_noalloc: the device's scratch (not owned), a pinned
+    // staging buffer of the same size and the event fencing its last copy
+    void* noalloc_scratch = nullptr;
+    void* noalloc_staging = nullptr;
+    hipEvent_t noalloc_done = nullptr;
+    bool noalloc_pending = false;
 };
 
 namespace sde {
+
+// Size of the static device scratch of sde_jj_integrate_noalloc, and the
+// number of devices whose scratch address is tracked.
+constexpr size_t kNoAllocScratchBytes = (size_t)8 << 20;
+constexpr int kMaxDevices = 64;
 
 enum Slot {
     kSlotJJPoints = 0,
@@ -144,6 +155,13 @@ int jj_integrate_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, con
 int jj_integrate_recorded_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run,
                                float* theta, int32_t* winding, float* v, double* acc, double* point_sums,
                                uint32_t record_every, uint64_t n_rows, int32_t* rec_winding, hipStream_t stream);
+// Looks up this device's no-allocation scratch (once per device) and
+// allocates the context's pinned staging buffer and event; called by
+// sde_create with the device current.
+int noalloc_setup(sde_ctx* ctx);
+int jj_integrate_noalloc_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run,
+                              float* theta, int32_t* winding, float* v, double* acc, double* point_sums,
+                              hipStream_t stream);
 int jj_integrate_f64_impl(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, const sde_run* run,
                           double* theta, int32_t* winding, double* v, double* acc, double* point_sums,
                           hipStream_t stream);
