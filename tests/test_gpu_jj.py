@@ -75,7 +75,10 @@ def test_gaussians_match_oracle(gpu):
     ref = oracle.gauss_array(123, 0, 5, 7, 3, n)
     err = np.abs(got - ref) / np.maximum(np.abs(ref), 1.0)
     print(f"gaussian max err {err.max():.3e}, 99.99% {np.quantile(err, 0.9999):.3e}")
-    assert err.max() <= 4e-6
+    # 2e-6 max(1, |g|): the uniforms are exact in FP32; log2, sqrt, sin and
+    # cos each round to about 1 ulp (2^-24 relative), the radius and the
+    # products add a few more
+    assert err.max() <= 2e-6
 
 
 def test_jj_single_point_first_100_steps_per_path(gpu):

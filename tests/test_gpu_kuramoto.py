@@ -92,6 +92,28 @@ def test_tiled_first_100_steps(gpu, scheme):
     np.testing.assert_allclose(rs.cpu().numpy(), rref, rtol=0, atol=1e-6)
 
 
+def test_tiled_full_size_sampled(gpu):
+    """The all-pairs sum at the uniform-coupling workload's own shape (N =
+    65536, 16 realizations, one j slice, the tuned tile) for 20 Heun steps,
+    realizations 0 and 15 against the oracle's Eq. 3 sums per oscillator."""
+    sde, ctx, dev = gpu
+    cfg = sde_inputs.kuramoto_uniform()
+    N, R = cfg["N"], cfg["R"]
+    sde.sde_set_option(ctx, sde.SDE_OPT_KURA_JSPLIT, 1)
+    ph, rs = _run(gpu, N, R, cfg["K"], cfg["D"], cfg["dt"], 20, 1, 0, cfg["seed"], cfg["omega"], M=10)
+    st = sde.sde_get_stats(ctx)
+    assert st["kura_jsplit"] == 1
+    print(f"tiled full size: tile {st['kura_tile']} oscillators per lane", flush=True)
+    got = ph.cpu().numpy()
+    for r in (0, 15):
+        ref, rref = oracle.kuramoto_integrate(N, R, cfg["K"], cfg["D"], cfg["dt"], 20, 10, oracle.MEANFIELD, 0,
+                                              cfg["seed"], cfg["omega"].astype(np.float64), r_first=r, r_count=1)
+        err = _circ_err(got[r], ref[0])
+        print(f"tiled N = {N}, realization {r}: max phase error {err.max():.2e}")
+        assert err.max() <= 1e-5
+        np.testing.assert_allclose(rs.cpu().numpy()[r], rref[0], rtol=0, atol=1e-6)
+
+
 def test_tiled_matches_meanfield_on_gpu(gpu):
     N, R = 4096, 2
     omega = sde_inputs.kuramoto_omega(N, 1.0, 3)
