@@ -31,30 +31,43 @@ sys.path.insert(0, ROOT)
 import sde_inputs  # noqa: E402
 
 # ---------------------------------------------------------------------------
-# ALU roofline.  Peak: the FP32 vector rate, 256 CUs x 128 FP32 lanes x
-# 2.4 GHz = 7.86e13 FMA lane-operations per second (157.3 TFLOP/s).  On
-# gfx950 a 32-bit integer operation (xor, shift, add, v_mad_u64_u32,
-# conversions) issues at half that rate and a transcendental (v_sin, v_cos,
-# v_log, v_sqrt) at a quarter, so algorithmic work is counted in FP32-FMA
-# equivalents: FP32 add/mul/fma = 1, integer op or FP64 op = 2,
-# transcendental = 4.
+# ALU roofline.  Peak: the FP32 vector rate, 256 CUs x 4 SIMDs x 32 FP32 lanes
+# x 2.4 GHz = 7.86e13 lane-operations per second (157.3 TFLOP/s as FMAs).
+# gfx950 reaches it without packed instructions: a wave64 v_add_f32 /
+# v_fma_f32 / v_xor_b32 with VGPR or constant operands issues in 2 SIMD
+# cycles.  The same instruction with an SGPR operand, v_mad_u64_u32,
+# v_mul_hi_u32, conversions, floor and FP64 add/fma take 4 cycles, the
+# transcendentals (v_sin, v_cos, v_log, v_sqrt) 8 (bench.py --workload
+# valu_costs measures each form).  Algorithmic work is therefore counted in
+# units of one 2-cycle lane-operation: W_FULL = 1, W_HALF = 2, W_TRANS = 4,
+# each operation the method needs counted once in its cheapest form.
 # ---------------------------------------------------------------------------
-PEAK_FMA_LANES = 256 * 128 * 2.4e9
+PEAK_FMA_LANES = 256 * 4 * 32 * 2.4e9
 PEAK_MFMA_16BIT = 2.5e15           # dense bf16 / fp16 MFMA FLOP/s
 PEAK_MFMA_FP32 = 157.3e12          # FP32 MFMA FLOP/s
-W_INT = 2.0
+W_FULL = 1.0
+W_HALF = 2.0
 W_TRANS = 4.0
-# Noise per path (or oscillator) and step: Philox4x32-10 (20 wide
-# multiplies + 40 xor per four steps) and Box-Muller (per two Gaussians 5
-# integer, 5 FP32 operations, log2, sqrt, sin, cos).
-NOISE_OPS = (20 + 40) * W_INT / 4 + (5 * W_INT + 5 + 4 * W_TRANS) / 2
+# Philox4x32-10 per block of four steps: 10 rounds x (2 v_mad_u64_u32 + 4 xor).
+PHILOX_BLOCK = 10 * (2 * W_HALF + 4 * W_FULL)
+# Box-Muller per pair of Gaussians: u1 = shift, add, convert, scale; u2 =
+# shift, convert, scale; log2, times c2, sqrt; cos, sin and two products.
+BOX_MULLER_PAIR = (3 * W_FULL + W_HALF) + (2 * W_FULL + W_HALF) + (2 * W_TRANS + W_FULL) + (2 * W_TRANS + 2 * W_FULL)
+# Noise per path (or oscillator) and step: a quarter of a Philox block, half a pair.
+NOISE_OPS = PHILOX_BLOCK / 4 + BOX_MULLER_PAIR / 2
 
 
 def jj_ops_per_path_step():
     """One stochastic-Heun path-step of Eq. 1: noise, 2 sin + 13 FP32 (two
     drift evaluations, predictor, corrector, window sum), phase wrap per four
-    steps (floor, sub, convert, add)."""
-    return NOISE_OPS + 13 + 2 * W_TRANS + (2 + 2 * W_INT) / 4
+    steps (floor, subtract, convert, add)."""
+    return NOISE_OPS + 13 * W_FULL + 2 * W_TRANS + (2 * W_HALF + 2 * W_FULL) / 4
+
+
+def jj_valu_instr_per_path_step():
+    """VALU instructions per path-step the method needs (a transcendental
+    counts 1): Philox 15, Box-Muller 7, Heun 15, wrap 1."""
+    return 60 / 4 + 14 / 2 + 15 + 4 / 4
 
 
 def jj_flops_per_path_step():
@@ -63,20 +76,22 @@ def jj_flops_per_path_step():
 
 
 def mf_ops_per_osc_step(heun):
-    """Mean-field Kuramoto per oscillator-step: noise; per stage sin + cos,
-    two FP64 conversions and adds, drift (4 FP32), update (2 FP32); wrap."""
-    stage = 2 * W_TRANS + 2 * W_INT + 2 * W_INT + 4 + 2
-    return NOISE_OPS + stage * (2 if heun else 1) + 2
+    """Mean-field Kuramoto per oscillator-step: noise; per stage sin + cos
+    and one add into each of the two sums; drift (3) and update (2 + 3 in
+    the corrector); wrap (floor, subtract)."""
+    stage = 2 * W_TRANS + 2 * W_FULL
+    if heun:
+        return NOISE_OPS + 2 * stage + 3 + 2 + 3 + 3 + W_HALF + W_FULL
+    return NOISE_OPS + stage + 3 + 2 + W_HALF + W_FULL
 
 
 def mfs_ops_per_osc_step(heun):
     """Streamed mean field per oscillator-step: Philox every step and one
-    Gaussian (log, sqrt, sin or cos); per stage sin + cos at its input and two
-    FP64 conversions and adds; Heun evaluates sin/cos of theta, tt (twice)
-    and theta'; drift, update and wrap."""
-    noise = 60 * W_INT + 5 * W_INT + 3 + 3 * W_TRANS
+    Gaussian; sin + cos evaluated 4 times (Heun: theta, tt twice, theta') or
+    twice (Euler), two adds into the sums per stage; drift, update and wrap."""
+    noise = PHILOX_BLOCK + (3 * W_FULL + W_HALF) + (2 * W_FULL + W_HALF) + (2 * W_TRANS + W_FULL) + W_TRANS + W_FULL
     trans = (8 if heun else 4) * W_TRANS
-    sums = (2 if heun else 1) * 2 * 2 * W_INT
+    sums = (2 if heun else 1) * 2 * W_FULL
     return noise + trans + sums + (12 if heun else 7)
 
 
@@ -103,10 +118,14 @@ def _source_sha1(*files):
 
 
 # HBM traffic of the JJ kernel per launch, from profiles/jj_scan_hbm_counters.md
-# (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, copy-calibrated).  Only valid for
-# the kernel source it was measured on.
-JJ_TRAFFIC_BYTES = (9848 + 6826) * 1024
-JJ_TRAFFIC_SOURCE_SHA1 = "e65c71464620b3268634a409af59a15086af724b"
+# (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, copy-calibrated), and its VALU
+# counters per path-step, from profiles/jj_scan_valu_counters.md.  Only valid
+# for the kernel source they were measured on.
+JJ_TRAFFIC_BYTES = (2 * 4267.56 + 6933.09) * 1024
+JJ_TRAFFIC_SOURCE_SHA1 = "9fefda8393829f33a889aab136f3f716b7f9e050"
+JJ_VALU_COUNTERS = {"valu_instructions_per_path_step": 37.54, "transcendental_per_path_step": 4.00,
+                    "salu_instructions_per_path_step": 8.08, "valu_instructions_per_simd_cycle": 0.269,
+                    "source": "profiles/jj_scan_valu_counters.md"}
 
 
 def _jj_source_sha1():
@@ -202,7 +221,8 @@ def bench_jj(args, sde, torch, dev):
     print(f"timed {args.steps} steps: {ms} ms per step, wall {wall:.2f} s", file=sys.stderr, flush=True)
     ops = jj_ops_per_path_step()
     achieved = ops * path_steps / kernel_s
-    traffic = JJ_TRAFFIC_BYTES if (_jj_source_sha1() == JJ_TRAFFIC_SOURCE_SHA1 and n_steps == 200000) else None
+    same_source = _jj_source_sha1() == JJ_TRAFFIC_SOURCE_SHA1
+    traffic = JJ_TRAFFIC_BYTES if (same_source and n_steps == 200000) else None
     out = {
         "metric": "path-steps/s (Josephson-junction scan, stochastic Heun)",
         "value": path_steps * args.steps / wall, "unit": "path-steps/s", "n_gpus": 1,
@@ -213,8 +233,10 @@ def bench_jj(args, sde, torch, dev):
                    "heun_steps": n_steps, "transient": n_steps // 2, "dt": "2pi/omega/200",
                    "path_steps_per_step": path_steps},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_FMA_LANES / 1e12,
-                     "unit": "T FP32-FMA-equivalent lane-ops/s", "frac": achieved / PEAK_FMA_LANES,
+                     "unit": "T lane-op units/s", "frac": achieved / PEAK_FMA_LANES,
                      "traffic": traffic, "ops_per_path_step": ops,
+                     "valu_instructions_per_path_step_method": jj_valu_instr_per_path_step(),
+                     "counters": JJ_VALU_COUNTERS if same_source else None,
                      "kernel": f"jj_persistent_kernel<float, {stats['jj_paths_per_lane']}, HEUN, inertial, sin>"},
         "launch": {"paths_per_lane": stats["jj_paths_per_lane"], "graph_replayed": stats["graph_replayed"],
                    "work_items": stats["work_items"]},
@@ -269,7 +291,7 @@ def bench_jj_batch(args, sde, torch, dev):
            "path_steps_per_s": work / t, "paths_per_lane": st["jj_paths_per_lane"],
            "work_items": st["work_items"], "graph_replayed": st["graph_replayed"],
            "roofline": {"bound": "alu", "achieved": ops * work / t / 1e12, "peak": PEAK_FMA_LANES / 1e12,
-                        "unit": "T FP32-FMA-equivalent lane-ops/s", "frac": ops * work / t / PEAK_FMA_LANES,
+                        "unit": "T lane-op units/s", "frac": ops * work / t / PEAK_FMA_LANES,
                         "traffic": None}}
     if not getattr(args, "no_cpu_baseline", True):
         # the FP64 oracle beside it: the first 8 points, 128 paths each, all their steps, under their
@@ -677,17 +699,17 @@ def bench_kuramoto(name, args, sde, torch, dev, steps=None, reps=1):
     if spec["coupling"] == 0:
         ops = mf_ops_per_osc_step(heun)
         rec["roofline"] = {"bound": "alu", "achieved": ops * osc_steps / t / 1e12,
-                           "peak": PEAK_FMA_LANES / 1e12, "unit": "T FP32-FMA-equivalent lane-ops/s",
+                           "peak": PEAK_FMA_LANES / 1e12, "unit": "T lane-op units/s",
                            "frac": ops * osc_steps / t / PEAK_FMA_LANES, "traffic": None}
         rec["us_per_stage"] = t / (n * (2 if heun else 1)) * 1e6
     elif spec["coupling"] == 1:
         pairs = float(N) * N * R * n * (2 if heun else 1)
-        ops = 1 + W_TRANS + 1
+        ops = W_FULL + W_TRANS + W_FULL
         rec["pairs_per_s"] = pairs / t
         rec["tile_oscillators_per_lane"] = st["kura_tile"]
         rec["j_slices"] = st["kura_jsplit"]
         rec["roofline"] = {"bound": "alu", "achieved": ops * pairs / t / 1e12, "peak": PEAK_FMA_LANES / 1e12,
-                           "unit": "T FP32-FMA-equivalent lane-ops/s", "frac": ops * pairs / t / PEAK_FMA_LANES,
+                           "unit": "T lane-op units/s", "frac": ops * pairs / t / PEAK_FMA_LANES,
                            "traffic": None}
     else:
         gemm_flop = 2.0 * N * N * 2 * R * n * (2 if heun else 1)
@@ -913,6 +935,33 @@ def bench_sweep(args, sde, torch, dev):
     return {"workload": "sweep", "sweep": out}
 
 
+# Instruction forms of the issue-cost probe (paper_0903_3852_amd/probe/valu_issue.hip), in its mode order.
+VALU_FORMS = ["v_add_f32 v,v", "v_add_f32 v,s", "v_fma_f32 v,v,v", "v_fma_f32 s,v,v", "v_mul_f32 v,v",
+              "v_xor_b32 v,v", "v_xor_b32 v,s", "v_add_u32 v,v", "v_lshrrev_b32 8,v", "v_mad_u64_u32 v,s,v",
+              "v_mul_hi_u32 v,v", "v_cvt_f32_u32", "v_floor_f32", "v_add_f64", "v_fma_f64", "v_cvt_f64_f32",
+              "v_sin_f32", "v_cos_f32", "v_log_f32", "v_sqrt_f32", "v_mov_b32_dpp row_shr", "v_mov_b32 v"]
+
+
+def bench_valu_costs(args):
+    """Issue cost of single VALU instruction forms (SIMD cycles per wave64
+    instruction at 8 waves per SIMD, 8 independent chains per lane, at the
+    2.4 GHz peak clock): the cost model behind the ALU rooflines."""
+    import ctypes
+    lib = ctypes.CDLL(os.path.join(ROOT, "paper_0903_3852_amd", "libvaluprobe.so"))
+    lib.valu_issue_time.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float)]
+    lib.valu_issue_time.restype = ctypes.c_int
+    assert lib.valu_issue_modes() == len(VALU_FORMS)
+    iters = 20000
+    out = {}
+    for mode, name in enumerate(VALU_FORMS):
+        ms = ctypes.c_float()
+        if lib.valu_issue_time(mode, iters, ctypes.byref(ms)) != 0:
+            raise RuntimeError(f"valu probe mode {mode} failed")
+        instr = 2048 * 4.0 * iters * 8.0
+        out[name] = round(1024 * 2.4e9 * ms.value * 1e-3 / instr, 3)
+    return {"workload": "valu_costs", "unit": "SIMD cycles per wave64 instruction", "cycles": out}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -920,7 +969,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="jj_scan",
                     choices=["jj_scan", "jj_batch", "jj_surrogate", "jj_surrogate_anm", "jj_fig2", "kuramoto_fig4",
-                             "sweep"] + sorted(KURA))
+                             "sweep", "valu_costs"] + sorted(KURA))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kuramoto", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
@@ -968,6 +1017,8 @@ def main():
         out = bench_fig4(args, sde, torch, dev)
     elif args.workload == "sweep":
         out = bench_sweep(args, sde, torch, dev)
+    elif args.workload == "valu_costs":
+        out = bench_valu_costs(args)
     else:
         out = bench_kuramoto(args.workload, args, sde, torch, dev, steps=args.kura_steps, reps=args.steps)
     if args.calibrate_copy:

@@ -48,8 +48,27 @@ def _compile(src, verbose):
     return obj
 
 
+PROBE_SRC = os.path.join(HERE, "probe", "valu_issue.hip")
+PROBE_LIB = os.path.join(HERE, "libvaluprobe.so")
+
+
+def build_probe(verbose=False):
+    """Compile the VALU issue-cost probe (bench.py --workload valu_costs)
+    into its own small library; libsde does not contain it."""
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [hipcc()] + HIPFLAGS + ["-shared", PROBE_SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("hipcc failed on valu_issue.hip:\n" + r.stdout + r.stderr)
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
+
+
 def build(verbose=False, jobs=None):
-    """Compile every csrc/*.hip and link libsde.so (always rebuilds)."""
+    """Compile every csrc/*.hip and link libsde.so (always rebuilds), then
+    the issue-cost probe."""
     os.makedirs(OBJDIR, exist_ok=True)
     srcs = sources()
     jobs = jobs or min(len(srcs), os.cpu_count() or 4, 8)
@@ -61,6 +80,7 @@ def build(verbose=False, jobs=None):
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
     os.replace(tmp, LIB)
+    build_probe(verbose)
     return LIB
 
 
