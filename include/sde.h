@@ -414,7 +414,7 @@ enum {
     SDE_OPT_JJ_PPT = 3,   /* Josephson-junction paths per lane: 0 (default) = tuned, */
                           /* or 1, 2, 4 to force                                     */
     SDE_OPT_KURA_MF = 4,  /* mean-field variant: 0 (default) = registers when the    */
-                          /* realization fits (N <= 2^20 on 256 CUs), else streamed  */
+                          /* realization fits (N <= 2^19 on 256 CUs), else streamed  */
                           /* through HBM; 1 = always streamed; 2 = always registers  */
                           /* (SDE_ERR_UNSUPPORTED when N does not fit)               */
     SDE_OPT_KURA_JSPLIT = 5, /* all-pairs (TILED) sum split over j slices per stage */
@@ -422,9 +422,13 @@ enum {
                           /* (about 4 workgroups per CU when the plain launch has   */
                           /* fewer than 2), 1 = never, J = 2..65535 = J slices (at   */
                           /* least 64 j per slice)                                   */
-    SDE_OPT_KURA_TILE = 6 /* all-pairs oscillators per lane (tile of 256 x OPT      */
+    SDE_OPT_KURA_TILE = 6, /* all-pairs oscillators per lane (tile of 256 x OPT     */
                           /* phases): 0 (default) = tuned per shape class, or 1, 2, */
                           /* 4 to force                                              */
+    SDE_OPT_KURA_XCD_LOCAL = 7 /* register-resident mean field: 1 (default) = the  */
+                          /* workgroups of a realization that run on one XCD        */
+                          /* exchange their sums through that XCD's L2 (checked at  */
+                          /* the start of every launch); 0 = always at device scope */
 };
 /* Sets an option of the context.  SDE_ERR_INVALID for an unknown option or
  * value. */

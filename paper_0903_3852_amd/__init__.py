@@ -28,6 +28,7 @@ SDE_POTENTIAL_SIN, SDE_POTENTIAL_SIN2PI = 0, 1
 SDE_OBS_MEAN_F32, SDE_OBS_MEAN_F64, SDE_OBS_MEANSQ_F32, SDE_OBS_ORDER = 0, 1, 2, 3
 SDE_OPT_AUTOTUNE, SDE_OPT_GRAPHS, SDE_OPT_JJ_PPT, SDE_OPT_KURA_MF, SDE_OPT_KURA_JSPLIT, SDE_OPT_KURA_TILE = \
     1, 2, 3, 4, 5, 6
+SDE_OPT_KURA_XCD_LOCAL = 7
 
 EXPORTS = ["sde_create", "sde_destroy", "sde_strerror", "sde_last_error", "sde_check",
            "sde_jj_integrate", "sde_jj_integrate_noalloc", "sde_jj_integrate_f64", "sde_jj_integrate_recorded",

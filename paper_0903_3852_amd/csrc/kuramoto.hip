@@ -60,6 +60,7 @@ struct MFArgs {
     float c2;                // -2 ln2 sigma^2, sigma = sqrt(2 D dt) / (2 pi)
     int32_t init_from_state;
     int32_t xcd_map;         // 1: realization r lives on XCD r / (R / 8)
+    int32_t xcd_local;       // 1: exchange through the XCD's L2 where a realization's workgroups share it
     uint32_t spin_limit;     // barrier give-up bound (iterations of s_sleep)
     uint32_t tree;           // two-level exchange (G a multiple of 8)
 };
@@ -191,13 +192,227 @@ __device__ __forceinline__ bool mf_exchange(const Args& A, uint32_t r, uint32_t 
     return true;
 }
 
+// ------------------------------------------------ MF, register-resident --
+// Sum over the 64 lanes of a wave by DPP moves: swaps within quads, the
+// half-row and row mirrors (every lane then holds its row's sum) and the two
+// row broadcasts.  The order is fixed, the total lands in lane 63.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ float dpp_term(float x)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, ROW_MASK, 0xF,
+                                                                  false));
+}
+
+__device__ __forceinline__ float wave_sum_dpp(float x)
+{
+    x += dpp_term<0xB1, 0xF>(x);   // quad_perm [1,0,3,2]
+    x += dpp_term<0x4E, 0xF>(x);   // quad_perm [2,3,0,1]
+    x += dpp_term<0x141, 0xF>(x);  // row_half_mirror
+    x += dpp_term<0x140, 0xF>(x);  // row_mirror
+    x += dpp_term<0x142, 0xA>(x);  // row_bcast:15 into rows 1 and 3
+    x += dpp_term<0x143, 0xC>(x);  // row_bcast:31 into rows 2 and 3
+    return x;
+}
+
+constexpr int kMFWaves = kMFThreads / kWave;
+
+// Word w of realization r's exchange (flat: [parity][R][G][4]).
+__device__ __forceinline__ uint64_t* mf_word(const MFArgs& A, uint64_t* base, uint32_t per_r, uint32_t r,
+                                             uint32_t epoch, uint32_t w)
+{
+    return base + ((uint64_t)(epoch & 1u) * A.R + r) * per_r + w;
+}
+
+// Publishes (S, C) as four tagged words.  XCD-local exchanges store at
+// workgroup scope: the words land in the shared L2 of the XCD, where the
+// other workgroups' agent-scope loads find them; otherwise at agent scope.
+__device__ __forceinline__ void mf2_publish(uint64_t* dst, uint64_t tag, double S, double C, bool local)
+{
+    const uint64_t bs = (uint64_t)__double_as_longlong(S), bc = (uint64_t)__double_as_longlong(C);
+    const uint64_t v[4] = {tag | (bs & 0xffffffffull), tag | (bs >> 32), tag | (bc & 0xffffffffull),
+                           tag | (bc >> 32)};
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        if (local)
+            __hip_atomic_store(dst + k, v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+            __hip_atomic_store(dst + k, v[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// The same four words stored by lanes 0..3 of the calling wave, one each.
+__device__ __forceinline__ void mf2_publish_lanes(uint64_t* dst, uint64_t tag, double S, double C, bool local)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    if (lane < kMFWordsPerGroup) {
+        const uint64_t b = (uint64_t)__double_as_longlong(lane < 2 ? S : C);
+        const uint64_t v = tag | ((lane & 1u) ? (b >> 32) : (b & 0xffffffffull));
+        if (local)
+            __hip_atomic_store(dst + lane, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        else
+            __hip_atomic_store(dst + lane, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Lane t < n of the calling wave waits for the word at p(t) to carry `tag`
+// and returns its 32 data bits; false once any lane's wait exceeded the
+// spin bound (the error flag is then set).  Agent-scope loads: they see both
+// agent-scope stores and, within one XCD, workgroup-scope stores.
+template <typename Addr>
+__device__ __forceinline__ bool mf2_poll(const MFArgs& A, uint32_t n, Addr p, uint64_t tag, uint32_t& data)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    bool ok = true;
+    data = 0u;
+    if (lane < n) {
+        const uint64_t* q = p(lane);
+        uint32_t spins = 0;
+        uint64_t v;
+        while (((v = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) & 0xffffffff00000000ull) !=
+               tag) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > A.spin_limit) {
+                ok = false;
+                break;
+            }
+        }
+        data = (uint32_t)v;
+    }
+    if (__ballot(!ok) != 0) {
+        if (lane == 0) atomicOr(A.flag, 2);
+        return false;
+    }
+    return true;
+}
+
+// The (S, C) pairs the polling wave holds as words, lane 4g + j holding word
+// j of pair g (zero words beyond the last pair): staged through LDS, where
+// each pair reads as two doubles, and added over g = 0 .. 15 in a fixed
+// pairwise order (zero pairs change nothing); every lane of the wave gets S
+// and C, and every workgroup adds the same numbers to the same bits.
+__device__ __forceinline__ void mf2_sum_words(uint32_t data, uint32_t* words, double& S, double& C)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    words[lane] = data;
+    // the wave's own LDS writes are complete before its reads below
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const double2* pairs = reinterpret_cast<const double2*>(words);
+    double s4[4], c4[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const double2 p0 = pairs[4 * q], p1 = pairs[4 * q + 1], p2 = pairs[4 * q + 2], p3 = pairs[4 * q + 3];
+        s4[q] = (p0.x + p1.x) + (p2.x + p3.x);
+        c4[q] = (p0.y + p1.y) + (p2.y + p3.y);
+    }
+    S = (s4[0] + s4[1]) + (s4[2] + s4[3]);
+    C = (c4[0] + c4[1]) + (c4[2] + c4[3]);
+}
+
+// Shared state of one workgroup of the register-resident kernel.
+struct MF2Shared {
+    float ws[kMFWaves], wc[kMFWaves];  // per-wave FP32 partial sums of the stage
+    double S, C;                       // the realization's sums of the stage
+    int ok;
+    int local;                         // the realization's workgroups share one XCD
+    __attribute__((aligned(8))) uint32_t words[kWave];  // the polled words of wave 0
+};
+
+// The exchange among the G workgroups of realization r, run by one wave after
+// the per-wave partials are in `sh`: the workgroup's FP64 sum of its waves
+// (in wave order) is published, the G workgroup sums (flat) or the 8 group
+// sums of the tree (workgroup w in group w mod 8; the group's first
+// workgroup adds its members in order) are collected and added in order,
+// and the wave leaves S and C in `sh`.  Every workgroup of a realization adds
+// the same numbers in the same order, so all get the same bits.
+__device__ __forceinline__ void mf2_exchange_wave(const MFArgs& A, uint32_t r, uint32_t w, uint32_t epoch,
+                                                   MF2Shared& sh)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    static_assert(kMFWaves == 8, "the pairwise order below is written for 8 waves");
+    auto d = [](float x) { return (double)x; };
+    const double Sw = ((d(sh.ws[0]) + d(sh.ws[1])) + (d(sh.ws[2]) + d(sh.ws[3]))) +
+                      ((d(sh.ws[4]) + d(sh.ws[5])) + (d(sh.ws[6]) + d(sh.ws[7])));
+    const double Cw = ((d(sh.wc[0]) + d(sh.wc[1])) + (d(sh.wc[2]) + d(sh.wc[3]))) +
+                      ((d(sh.wc[4]) + d(sh.wc[5])) + (d(sh.wc[6]) + d(sh.wc[7])));
+    const bool local = sh.local != 0;
+    const uint64_t tag = (uint64_t)(epoch + 1) << 32;
+    const uint32_t per1 = A.G * kMFWordsPerGroup;
+    mf2_publish_lanes(mf_word(A, A.slots, per1, r, epoch, w * kMFWordsPerGroup), tag, Sw, Cw, local);
+    double S, C;
+    uint32_t data;
+    if (!A.tree) {
+        if (!mf2_poll(A, per1, [&](uint32_t t) { return mf_word(A, A.slots, per1, r, epoch, t); }, tag, data)) {
+            if (lane == 0) sh.ok = 0;
+            return;
+        }
+        mf2_sum_words(data, sh.words, S, C);
+    } else {
+        const uint32_t x = w & 7u, m = A.G >> 3;
+        const uint32_t per2 = 8 * kMFWordsPerGroup;
+        if (w < 8) {  // group leader: members x, x + 8, x + 16, ...
+            if (!mf2_poll(A, m * kMFWordsPerGroup,
+                          [&](uint32_t t) {
+                              return mf_word(A, A.slots, per1, r, epoch, (x + 8 * (t >> 2)) * kMFWordsPerGroup + (t & 3u));
+                          },
+                          tag, data)) {
+                if (lane == 0) sh.ok = 0;
+                return;
+            }
+            double Sx, Cx;
+            mf2_sum_words(data, sh.words, Sx, Cx);
+            mf2_publish_lanes(mf_word(A, A.slots2, per2, r, epoch, x * kMFWordsPerGroup), tag, Sx, Cx, local);
+        }
+        if (!mf2_poll(A, per2, [&](uint32_t t) { return mf_word(A, A.slots2, per2, r, epoch, t); }, tag, data)) {
+            if (lane == 0) sh.ok = 0;
+            return;
+        }
+        mf2_sum_words(data, sh.words, S, C);
+    }
+    if (lane == 0) {
+        sh.S = S;
+        sh.C = C;
+    }
+}
+
+// Whether all G workgroups of realization r run on one XCD: each publishes
+// its XCD id (epoch 0, agent scope) and reads everyone's.  Run by wave 0;
+// the answer is the same in every workgroup of the realization.
+__device__ __forceinline__ void mf2_locality(const MFArgs& A, uint32_t r, uint32_t w, MF2Shared& sh)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const uint32_t xcc = __builtin_amdgcn_s_getreg((20) | (0 << 6) | ((4 - 1) << 11));  // HW_REG_XCC_ID[3:0]
+    const uint64_t tag = 1ull << 32;
+    const uint32_t per1 = A.G * kMFWordsPerGroup;
+    if (lane == 0) mf2_publish(mf_word(A, A.slots, per1, r, 0, w * kMFWordsPerGroup), tag, (double)xcc, 0.0, false);
+    bool same = true;
+    for (uint32_t base = 0; base < A.G; base += kWave / kMFWordsPerGroup) {
+        const uint32_t cnt = min(A.G - base, (uint32_t)(kWave / kMFWordsPerGroup));
+        uint32_t data;
+        if (!mf2_poll(A, cnt * kMFWordsPerGroup,
+                      [&](uint32_t t) { return mf_word(A, A.slots, per1, r, 0, base * kMFWordsPerGroup + t); }, tag,
+                      data)) {
+            if (lane == 0) sh.ok = 0;
+            return;
+        }
+        for (uint32_t g = 0; g < cnt; ++g) {
+            const uint32_t s0 = __builtin_amdgcn_readlane(data, 4 * g), s1 = __builtin_amdgcn_readlane(data, 4 * g + 1);
+            same &= __longlong_as_double((long long)(((uint64_t)s1 << 32) | s0)) == (double)xcc;
+        }
+    }
+    if (lane == 0) sh.local = (same && A.xcd_local) ? 1 : 0;
+}
+
 template <int OPT, int SCHEME>
 __global__ __launch_bounds__(kMFThreads, 1) void kuramoto_mf_kernel(MFArgs A)
 {
-    __shared__ double lds[2 * kMFThreads / kWave];
-    __shared__ uint32_t words[kMFWordsPerGroup * kMaxMFGroups];
-    __shared__ int lds_ok;
-    if (threadIdx.x == 0) lds_ok = 1;  // made visible by the exchange's first barrier
+    __shared__ MF2Shared sh;
+    const uint32_t lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    if (threadIdx.x == 0) {
+        sh.ok = 1;
+        sh.local = 0;
+    }
     // workgroup -> (realization r, slice w)
     uint32_t r, w;
     if (A.xcd_map) {
@@ -209,7 +424,7 @@ __global__ __launch_bounds__(kMFThreads, 1) void kuramoto_mf_kernel(MFArgs A)
         w = blockIdx.x % A.G;
     }
     const uint32_t N = A.N;
-    float th[OPT], F1[OPT], om[OPT];
+    float th[OPT], F1[OPT], om[OPT], sn[OPT], cs[OPT];
     uint32_t idx[OPT];
     bool live[OPT];
 #pragma unroll
@@ -217,8 +432,6 @@ __global__ __launch_bounds__(kMFThreads, 1) void kuramoto_mf_kernel(MFArgs A)
         idx[k] = (w * OPT + k) * kMFThreads + threadIdx.x;
         live[k] = idx[k] < N;
         const uint32_t i = live[k] ? idx[k] : 0u;
-        // omega stays in registers: each barrier's acquire invalidates the
-        // L2, so a per-stage load would wait out a memory round trip
         om[k] = live[k] ? A.omega[i] : 0.f;
         if (A.init_from_state) {
             th[k] = live[k] ? A.theta[(uint64_t)r * N + i] : 0.f;
@@ -227,67 +440,107 @@ __global__ __launch_bounds__(kMFThreads, 1) void kuramoto_mf_kernel(MFArgs A)
             th[k] = (float)(x.x >> 8) * 0x1p-24f;
         }
     }
+    __syncthreads();
+    if (wid == 0) mf2_locality(A, r, w, sh);
 
-    uint32_t epoch = 0;
+    uint32_t epoch = 1;
     const double invN = 1.0 / (double)N;
-    // sums of sin and cos over the realization at phases t[]; FP32 terms,
-    // FP64 accumulation
+    static_assert(OPT <= 8, "at most 8 oscillators per lane");
+    // Noise: sigma * the Gaussians of the current block of 4 steps (g, block
+    // gblk) and of the next one (gn, block gblk + 1), the latter generated
+    // oscillator by oscillator while the wave waits for an exchange it does
+    // not run (the exchanges rotate over the waves, so each wave has idle
+    // windows); gn_done oscillators of gn are ready (wave-uniform).
+    float g[OPT][4], gn[OPT][4];
+    uint64_t gblk = ~0ull;
+    uint32_t gn_done = 0;
+    constexpr uint32_t kPrefetch = SCHEME == SDE_HEUN ? (OPT + 6) / 7 : (OPT + 2) / 3;
+    auto prefetch = [&]() {
+        if (gblk == ~0ull || gn_done >= (uint32_t)OPT) return;
+        const uint32_t nb = (uint32_t)(gblk + 1), lo = gn_done, hi = gn_done + kPrefetch;
+#pragma unroll
+        for (int k = 0; k < OPT; ++k)
+            if ((uint32_t)k >= lo && (uint32_t)k < hi)
+                gauss4_scaled(U4{nb, idx[k], A.r_base + r, (uint32_t)SDE_TAG_NOISE}, A.key0, A.key1, A.c2, gn[k]);
+        gn_done = hi < (uint32_t)OPT ? hi : (uint32_t)OPT;
+    };
+
+    // sin and cos of the phases t[] (kept for the drift) and the realization's
+    // sums of them: FP32 within a lane and a wave, FP64 across waves and
+    // workgroups.  Exchange e is run by wave e mod 8.
     auto reduce = [&](const float (&t)[OPT], float& Sf, float& Cf, double& Sd, double& Cd) -> bool {
-        double s = 0.0, c = 0.0;
+        float s = 0.f, c = 0.f;
 #pragma unroll
         for (int k = 0; k < OPT; ++k) {
-            if (live[k]) {
-                s += (double)sin_rev(t[k]);
-                c += (double)cos_rev(t[k]);
-            }
+            sn[k] = live[k] ? sin_rev(t[k]) : 0.f;
+            cs[k] = live[k] ? cos_rev(t[k]) : 0.f;
+            s += sn[k];
+            c += cs[k];
         }
-        double S, C;
-        if (!mf_exchange<kMFThreads>(A, r, w, epoch, s, c, lds, words, &lds_ok, S, C)) return false;
+        s = wave_sum_dpp(s);
+        c = wave_sum_dpp(c);
+        if (lane == kWave - 1) {
+            sh.ws[wid] = s;
+            sh.wc[wid] = c;
+        }
+        __syncthreads();
+        if (wid == (epoch & (kMFWaves - 1))) {
+            if (sh.ok) mf2_exchange_wave(A, r, w, epoch, sh);
+        } else {
+            prefetch();
+        }
+        __syncthreads();
+        if (!sh.ok) return false;
         ++epoch;
-        Sd = S;
-        Cd = C;
-        Sf = (float)S;
-        Cf = (float)C;
+        Sd = sh.S;
+        Cd = sh.C;
+        Sf = (float)Sd;
+        Cf = (float)Cd;
         return true;
     };
 
     uint64_t n = A.step0;
     const uint64_t n_end = A.step0 + A.n_steps;
     uint64_t local = 0;
-    bool ok = true;
-    float g[OPT][4];                 // sigma * Gaussians of the current block of 4 steps
-    uint64_t gblk = ~0ull;
     for (;;) {
         // one stage-1 reduction at theta_n: the drift and, every M steps, r
         float S, C;
         double Sd, Cd;
-        if (!(ok = reduce(th, S, C, Sd, Cd))) break;
+        if (!reduce(th, S, C, Sd, Cd)) break;
         if (A.r_samples && local % A.M == 0 && w == 0 && threadIdx.x == 0)
             A.r_samples[(uint64_t)r * A.n_samples + local / A.M] = std::sqrt(Sd * Sd + Cd * Cd) * invN;
         if (n == n_end) break;
         if ((n >> 2) != gblk) {
-            gblk = n >> 2;
+            const uint64_t b = n >> 2;
+            if (gblk != ~0ull && b == gblk + 1 && gn_done == (uint32_t)OPT) {
 #pragma unroll
-            for (int k = 0; k < OPT; ++k)
-                gauss4_scaled(U4{(uint32_t)gblk, idx[k], A.r_base + r, (uint32_t)SDE_TAG_NOISE}, A.key0, A.key1,
-                              A.c2, g[k]);
+                for (int k = 0; k < OPT; ++k)
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) g[k][q] = gn[k][q];
+            } else {
+#pragma unroll
+                for (int k = 0; k < OPT; ++k)
+                    gauss4_scaled(U4{(uint32_t)b, idx[k], A.r_base + r, (uint32_t)SDE_TAG_NOISE}, A.key0, A.key1,
+                                  A.c2, g[k]);
+            }
+            gblk = b;
+            gn_done = 0;
         }
         const uint32_t j = (uint32_t)n & 3u;
         auto noise = [&](int k) { return j == 0 ? g[k][0] : j == 1 ? g[k][1] : j == 2 ? g[k][2] : g[k][3]; };
-        auto omega_of = [&](int k) { return om[k]; };
         float tt[OPT];
 #pragma unroll
         for (int k = 0; k < OPT; ++k) {
-            F1[k] = fmaf(A.kn, fmaf(cos_rev(th[k]), S, -sin_rev(th[k]) * C), omega_of(k));
+            F1[k] = fmaf(A.kn, fmaf(cs[k], S, -sn[k] * C), om[k]);
             tt[k] = fmaf(A.omega_scale, F1[k], th[k]) + noise(k);
         }
         if (SCHEME == SDE_HEUN) {
             float S2, C2;
             double S2d, C2d;
-            if (!(ok = reduce(tt, S2, C2, S2d, C2d))) break;
+            if (!reduce(tt, S2, C2, S2d, C2d)) break;
 #pragma unroll
             for (int k = 0; k < OPT; ++k) {
-                const float F2 = fmaf(A.kn, fmaf(cos_rev(tt[k]), S2, -sin_rev(tt[k]) * C2), omega_of(k));
+                const float F2 = fmaf(A.kn, fmaf(cs[k], S2, -sn[k] * C2), om[k]);
                 const float t = fmaf(A.hdt2pi, F1[k] + F2, th[k]) + noise(k);
                 th[k] = t - floorf(t);
             }
@@ -306,8 +559,7 @@ __global__ __launch_bounds__(kMFThreads, 1) void kuramoto_mf_kernel(MFArgs A)
             bad |= !isfinite(th[k]);
         }
     }
-    if (__ballot(bad) != 0 && (threadIdx.x & (kWave - 1)) == 0) atomicOr(A.flag, 1);
-    (void)ok;
+    if (__ballot(bad) != 0 && lane == 0) atomicOr(A.flag, 1);
 }
 
 // ------------------------------------------------------ MF, streamed ------
@@ -840,11 +1092,17 @@ static int run_meanfield(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run
                          hipStream_t stream)
 {
     const KuraConsts kc = kuramoto_consts(d);
-    // oscillators per lane: the smallest of 1, 2, ..., 16 that needs at most
-    // 16 workgroups per realization (more workgroups if N is larger)
+    // oscillators per lane: the smallest of 1, 2, 4, 8 that needs at most 16
+    // workgroups per realization (more workgroups if N is larger; 8 per lane
+    // is the most the kernel holds in registers with its noise block, its
+    // prefetched next block and the sines and cosines kept for the drift)
     int opt = 1;
-    while (opt < 16 && (uint64_t)d->N > (uint64_t)16 * kMFThreads * opt) opt *= 2;
-    const uint64_t G64 = (d->N + (uint64_t)kMFThreads * opt - 1) / ((uint64_t)kMFThreads * opt);
+    while (opt < 8 && (uint64_t)d->N > (uint64_t)16 * kMFThreads * opt) opt *= 2;
+    uint64_t G64 = (d->N + (uint64_t)kMFThreads * opt - 1) / ((uint64_t)kMFThreads * opt);
+    // one wave polls the exchange: up to 16 workgroups flat, beyond that the
+    // two-level exchange over 8 groups (G a multiple of 8; the workgroups
+    // past the last oscillator contribute zero sums)
+    if (G64 > 16) G64 = (G64 + 7) / 8 * 8;
     const uint32_t G = (uint32_t)G64;
     void* kern = nullptr;
     const bool heun = run->scheme == SDE_HEUN;
@@ -852,8 +1110,7 @@ static int run_meanfield(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run
     case 1: kern = heun ? mf_kernel_ptr<1, SDE_HEUN>() : mf_kernel_ptr<1, SDE_EULER>(); break;
     case 2: kern = heun ? mf_kernel_ptr<2, SDE_HEUN>() : mf_kernel_ptr<2, SDE_EULER>(); break;
     case 4: kern = heun ? mf_kernel_ptr<4, SDE_HEUN>() : mf_kernel_ptr<4, SDE_EULER>(); break;
-    case 8: kern = heun ? mf_kernel_ptr<8, SDE_HEUN>() : mf_kernel_ptr<8, SDE_EULER>(); break;
-    default: kern = heun ? mf_kernel_ptr<16, SDE_HEUN>() : mf_kernel_ptr<16, SDE_EULER>(); break;
+    default: kern = heun ? mf_kernel_ptr<8, SDE_HEUN>() : mf_kernel_ptr<8, SDE_EULER>(); break;
     }
     int per_cu = 0;
     SDE_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kMFThreads, 0));
@@ -882,7 +1139,7 @@ static int run_meanfield(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run
         SDE_HIP(ctx, hipGetLastError());
         MFArgs A;
         A.slots2 = static_cast<uint64_t*>(slots) + slot_words;
-        A.tree = (G >= kMFTreeMinGroups && G % 8 == 0) ? 1u : 0u;
+        A.tree = G > 16 ? 1u : 0u;
         A.theta = phi + (uint64_t)r0 * d->N;
         A.omega = omega;
         A.r_samples = r_samples ? r_samples + (uint64_t)r0 * n_samples : nullptr;
@@ -903,6 +1160,7 @@ static int run_meanfield(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run
         A.c2 = kc.c2;
         A.init_from_state = run->init == SDE_INIT_FROM_STATE;
         A.xcd_map = (ctx->xcds == 8 && nr % 8 == 0) ? 1 : 0;
+        A.xcd_local = ctx->kura_xcd_local;
         A.spin_limit = 1u << 26;
         A.r_base = r0;
         void* args[] = {&A};

@@ -65,6 +65,7 @@ struct sde_ctx {
     int kura_mf = 0;              // mean-field variant: 0 auto, 1 streamed, 2 registers
     int kura_jsplit = 0;          // all-pairs j slices: 0 auto, else forced
     int kura_tile = 0;            // all-pairs oscillators per lane: 0 tuned, else 1, 2, 4
+    int kura_xcd_local = 1;       // mean field: exchange through the XCD's L2 when possible
     std::map<std::string, int> tune;
     std::string tune_path;
     sde_stats last{};

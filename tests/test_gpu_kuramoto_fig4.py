@@ -76,7 +76,7 @@ def test_streamed_first_100_steps(gpu, scheme, N, R):
 @pytest.mark.parametrize("streamed,N", [(True, 1 << 17), (False, 1 << 18)])
 def test_tree_exchange_vs_oracle(gpu, streamed, N):
     """2 realizations of N = 2^17 streamed (128 workgroups per realization)
-    or N = 2^18 in registers (32 workgroups of 512 lanes x 16 oscillators),
+    or N = 2^18 in registers (64 workgroups of 512 lanes x 8 oscillators),
     so the sums go through the two-level exchange (group leaders, then the
     8 group sums); first 100 steps against the oracle."""
     R = 2
@@ -95,8 +95,9 @@ def test_tree_exchange_vs_oracle(gpu, streamed, N):
 @pytest.mark.parametrize("N", [12289, 30001, 65535, 100003])
 def test_register_resident_lane_counts(gpu, N):
     """The register-resident kernel at each count of oscillators per lane
-    (2, 4, 8, 16 for these N, at most 16 workgroups per realization; the
-    last workgroup ragged), Heun and Euler-Maruyama, 3 realizations."""
+    (2, 4, 8 for these N, the last workgroup ragged; N = 100003 needs 25
+    workgroups of 8 per lane, rounded up to 32 for the two-level exchange,
+    the last 7 empty), Heun and Euler-Maruyama, 3 realizations."""
     R = 3
     cfg = sde_inputs.kuramoto_uniform(N=N, R=R)
     for scheme in (0, 1):
