@@ -144,7 +144,11 @@ typedef struct {
  *   point_sums [device] double [n_pts][2] or NULL: (sum_p vbar_p,
  *                             sum_p vbar_p^2) with vbar_p = acc_p / W,
  *                             W = number of window steps before
- *                             step0 + n_steps (0 if none: sums are 0).
+ *                             step0 + n_steps.
+ * n_transient is an absolute step index, so a call that ends before it
+ * (n_transient >= step0 + n_steps: a transient integrated in pieces, whose
+ * state the next call resumes) is valid: its window is empty, W = 0, acc
+ * is unchanged and the point sums are 0.  It is not an error.
  * The noise of path p of point q at absolute step n is component n & 3 of
  * the Box-Muller Gaussians of Philox(ctr = (n >> 2, p, q, SDE_TAG_NOISE)).
  * Points of different potentials and of m > 0 / m = 0 mix freely in one

@@ -4,17 +4,22 @@
 // the integrator where the ensemble disagrees.
 //
 // Training works on minibatches of B samples for all members at once
-// (grid.z = member).  One tiled FP32 kernel serves the three products of a
-// layer -- forward Z = A W^T + b, weight gradient dW = dZ^T A, input
-// gradient dA = dZ W -- with the bias/GELU (forward) and GELU' (backward)
-// applied in its epilogue.  A whole epoch of steps is recorded once as a HIP
-// graph; the Adam step count is read from a device counter so the same graph
-// replays every epoch.
+// (grid.z = member).  One tiled kernel serves the three products of a layer
+// -- forward Z = A W^T + b, weight gradient dW = dZ^T A, input gradient
+// dA = dZ W -- on the FP32 matrix cores (v_mfma_f32_16x16x4_f32; 64 x 64
+// tiles staged through LDS in 16-k slices, a 32 x 32 quarter per wave), with
+// the bias/GELU (forward) and GELU' (backward) applied in its epilogue.  A
+// whole epoch of steps is recorded once as a HIP graph; the Adam step count
+// is read from a device counter so the same graph replays every epoch.
 //
-// Inference is one fused kernel: a workgroup takes 128 points, keeps their
-// activations (128 x 256 FP32) in LDS and runs every member through every
-// layer, streaming weight slices through LDS, then writes the members' mean
-// and sample standard deviation.
+// Inference is one fused kernel for all members (mlp_infer_mfma_kernel):
+// the hidden weights are packed once per call into the fragment layout of
+// the FP32 MFMA (a 16 x 16 block per 1 KB run); a workgroup takes 64 queries
+// whose activations stay in LDS in the operand layout of the next layer,
+// each of its 4 waves computes 16 queries x all 256 outputs of a layer on
+// v_mfma_f32_16x16x4_f32 with the weights streamed from L2, bias and GELU
+// write the next operand, and the output layer, the members' mean and their
+// sample standard deviation follow.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
