@@ -332,9 +332,11 @@ ANM_CENTER = [4.25, 5.0, 0.0, -3.0, 0.95]
 ANM_SCALE = [0.75, 1.0, 0.3, 1.0, 0.25]
 SURR_VARIANTS = {
     # params generator, feature centre/scale, potential, steps per drive period, queries in the timed
-    # scan, training points, epochs
-    "batch": (sde_inputs.jj_random_params, SURR_CENTER, SURR_SCALE, 0, 200, 1000000, 100000, 30),
-    "anm": (sde_inputs.jj_anm_params, ANM_CENTER, ANM_SCALE, 1, 100, 100000, 200000, 150),
+    # scan, training points, training schedule (epochs, learning rate) in order, Adam's state carried
+    # from one stage to the next
+    "batch": (sde_inputs.jj_random_params, SURR_CENTER, SURR_SCALE, 0, 200, 1000000, 100000, ((30, 1e-3),)),
+    "anm": (sde_inputs.jj_anm_params, ANM_CENTER, ANM_SCALE, 1, 100, 100000, 600000,
+            ((150, 1e-3), (50, 3e-4), (50, 1e-4), (50, 3e-5))),
 }
 
 
@@ -347,7 +349,8 @@ def _surr_points(sde, P, paths, steps, potential=0, spp=200):
 def bench_surrogate(args, sde, torch, dev, variant="batch"):
     """The learned <v> surrogate: labels simulated by the integrator (512
     paths x 1e5 steps, half transient), 5 members of 5-256-256-256-1 trained
-    on the GPU (1e5 points x 30 epochs; 2e5 x 150 for "anm"), and a scan
+    on the GPU (1e5 points x 30 epochs at lr 1e-3; for "anm" 6e5 points x 300
+    epochs, the learning rate stepped 1e-3, 3e-4, 1e-4, 3e-5), and a scan
     that falls back to simulation where the members' spread exceeds 0.02.
     Reported: error against 4096 held-out points simulated at 4096 paths at
     that threshold (and at every candidate of 0.005 ... 0.1, and without
@@ -360,7 +363,7 @@ def bench_surrogate(args, sde, torch, dev, variant="batch"):
     (dt = 2pi/omega/200), 1e6 queries; "anm": the paper's potential around
     its Fig. 2 point (dt = 0.01 drive period), where <v> varies in sign and
     size, 1e5 queries."""
-    gen, center, scale, potential, spp, n_query, n_train, epochs = SURR_VARIANTS[variant]
+    gen, center, scale, potential, spp, n_query, n_train, schedule = SURR_VARIANTS[variant]
     ctx = sde.sde_create(0)
     stream = torch.cuda.current_stream()
 
@@ -392,9 +395,12 @@ def bench_surrogate(args, sde, torch, dev, variant="batch"):
 
     sur = sde.sde_surrogate_create(ctx, [5, 256, 256, 256, 1], 5, seed + 70)
     sde.sde_surrogate_set_scaling(sur, sde.make_scaling(center, scale, float(ytr.mean()), float(ytr.std()), 0))
+    Xtr, Ytr = feats(Ptr), torch.from_numpy(ytr.astype(np.float32)).to(dev)
     t0 = time.perf_counter()
-    curve = sde.sde_surrogate_train(sur, feats(Ptr), torch.from_numpy(ytr.astype(np.float32)).to(dev),
-                                    sde.make_train_opts(epochs, 1024, lr=1e-3, shuffle_seed=seed + 71))
+    curve = []
+    for k, (epochs_k, lr_k) in enumerate(schedule):
+        curve += list(sde.sde_surrogate_train(sur, Xtr, Ytr, sde.make_train_opts(epochs_k, 1024, lr=lr_k,
+                                                                                 shuffle_seed=seed + 71 + k)))
     t_train = time.perf_counter() - t0
     # the spread threshold: the largest candidate whose validation error (scan
     # with fallback against 4096-path labels) is within 1e-2
@@ -442,7 +448,8 @@ def bench_surrogate(args, sde, torch, dev, variant="batch"):
     return {"workload": "jj_surrogate" if variant == "batch" else "jj_surrogate_anm",
             "potential": "-sin(phi)" if potential == 0 else "sin(2 pi x)",
             "train_points": n_train, "label_budget": "512 paths x 1e5 steps",
-            "label_seconds": t_labels, "train_seconds": t_train, "epochs": epochs,
+            "label_seconds": t_labels, "train_seconds": t_train,
+            "schedule": [{"epochs": e_, "lr": l_} for e_, l_ in schedule],
             "loss_first_last": [float(curve[0]), float(curve[-1])],
             "holdout": {"points": 4096, "paths": 4096, "mae": float(err.mean()),
                         "p95": float(np.quantile(err, 0.95)), "max": float(err.max()), "r2": r2,
