@@ -709,6 +709,7 @@ def bench_kuramoto(name, args, sde, torch, dev, steps=None, reps=1):
                            "peak": PEAK_FMA_LANES / 1e12, "unit": "T lane-op units/s",
                            "frac": ops * osc_steps / t / PEAK_FMA_LANES, "traffic": None}
         rec["us_per_stage"] = t / (n * (2 if heun else 1)) * 1e6
+        rec["oscillators_per_lane"] = st["kura_mf_opt"]
     elif spec["coupling"] == 1:
         pairs = float(N) * N * R * n * (2 if heun else 1)
         ops = W_FULL + W_TRANS + W_FULL
@@ -719,6 +720,7 @@ def bench_kuramoto(name, args, sde, torch, dev, steps=None, reps=1):
                            "unit": "T lane-op units/s", "frac": ops * pairs / t / PEAK_FMA_LANES,
                            "traffic": None}
     else:
+        rec["launch"] = {"waves": st["dense_waves"], "xcd_bands": st["dense_xcd_bands"]}
         gemm_flop = 2.0 * N * N * 2 * R * n * (2 if heun else 1)
         if spec["coupling"] == 2:
             # FP32 MFMA (v_mfma_f32_16x16x4_f32): MI355X's FP32 matrix peak equals its FP32 vector peak

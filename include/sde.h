@@ -429,10 +429,21 @@ enum {
     SDE_OPT_KURA_TILE = 6, /* all-pairs oscillators per lane (tile of 256 x OPT     */
                           /* phases): 0 (default) = tuned per shape class, or 1, 2, */
                           /* 4 to force                                              */
-    SDE_OPT_KURA_XCD_LOCAL = 7 /* register-resident mean field: 1 (default) = the  */
+    SDE_OPT_KURA_XCD_LOCAL = 7, /* register-resident mean field: 1 (default) = the */
                           /* workgroups of a realization that run on one XCD        */
                           /* exchange their sums through that XCD's L2 (checked at  */
                           /* the start of every launch); 0 = always at device scope */
+    SDE_OPT_KURA_MF_OPT = 8, /* register-resident mean field oscillators per lane   */
+                          /* (512 lanes per workgroup, so N / (512 OPT) workgroups  */
+                          /* per realization): 0 (default) = tuned per shape class, */
+                          /* or 1, 2, 4, 8 to force (SDE_ERR_UNSUPPORTED if N does  */
+                          /* not fit at that count)                                 */
+    SDE_OPT_DENSE_LAUNCH = 9 /* dense coupling launch: 0 (default) = tuned per shape */
+                          /* class; 1 = 8 waves per workgroup splitting the k loop, */
+                          /* row tiles dealt to XCDs in bands; 2 = 4 waves, bands;  */
+                          /* 3 = 8 waves, plain order; 4 = 4 waves, plain order     */
+                          /* (FP32 always runs 4 waves; bands apply when the row    */
+                          /* tiles split evenly over the 8 XCDs)                    */
 };
 /* Sets an option of the context.  SDE_ERR_INVALID for an unknown option or
  * value. */
@@ -453,7 +464,11 @@ typedef struct {
                              /* through HBM (1) or held it in registers (0)           */
     int32_t kura_jsplit;     /* j slices of the last all-pairs (TILED) call           */
     int32_t kura_tile;       /* oscillators per lane of the last all-pairs call       */
-    int32_t reserved;
+    int32_t kura_mf_opt;     /* oscillators per lane of the last register-resident    */
+                             /* mean-field call                                       */
+    int32_t dense_waves;     /* waves per workgroup (k-loop split) of the last dense  */
+                             /* call                                                  */
+    int32_t dense_xcd_bands; /* its row tiles were dealt to XCDs in bands (1)         */
 } sde_stats;
 /* Statistics of the last integration call on `ctx`. */
 int sde_get_stats(const sde_ctx* ctx, sde_stats* out);

@@ -336,6 +336,13 @@ __device__ __forceinline__ void mf2_exchange_wave(const MFArgs& A, uint32_t r, u
                       ((d(sh.ws[4]) + d(sh.ws[5])) + (d(sh.ws[6]) + d(sh.ws[7])));
     const double Cw = ((d(sh.wc[0]) + d(sh.wc[1])) + (d(sh.wc[2]) + d(sh.wc[3]))) +
                       ((d(sh.wc[4]) + d(sh.wc[5])) + (d(sh.wc[6]) + d(sh.wc[7])));
+    if (A.G == 1) {  // the realization is one workgroup: nothing to exchange
+        if (lane == 0) {
+            sh.S = Sw;
+            sh.C = Cw;
+        }
+        return;
+    }
     const bool local = sh.local != 0;
     const uint64_t tag = (uint64_t)(epoch + 1) << 32;
     const uint32_t per1 = A.G * kMFWordsPerGroup;
@@ -382,6 +389,7 @@ __device__ __forceinline__ void mf2_exchange_wave(const MFArgs& A, uint32_t r, u
 __device__ __forceinline__ void mf2_locality(const MFArgs& A, uint32_t r, uint32_t w, MF2Shared& sh)
 {
     const uint32_t lane = threadIdx.x & (kWave - 1);
+    if (A.G == 1) return;  // no exchange
     const uint32_t xcc = __builtin_amdgcn_s_getreg((20) | (0 << 6) | ((4 - 1) << 11));  // HW_REG_XCC_ID[3:0]
     const uint64_t tag = 1ull << 32;
     const uint32_t per1 = A.G * kMFWordsPerGroup;
@@ -1087,86 +1095,207 @@ static int run_meanfield_streamed(sde_ctx* ctx, const sde_kuramoto_desc* d, cons
     return SDE_OK;
 }
 
-static int run_meanfield(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, float* phi,
-                         const float* omega, double* r_samples, uint64_t n_samples, uint32_t M,
-                         hipStream_t stream)
+static int ilog2_u64(uint64_t x)
 {
-    const KuraConsts kc = kuramoto_consts(d);
-    // oscillators per lane: the smallest of 1, 2, 4, 8 that needs at most 16
-    // workgroups per realization (more workgroups if N is larger; 8 per lane
-    // is the most the kernel holds in registers with its noise block, its
-    // prefetched next block and the sines and cosines kept for the drift)
-    int opt = 1;
-    while (opt < 8 && (uint64_t)d->N > (uint64_t)16 * kMFThreads * opt) opt *= 2;
-    uint64_t G64 = (d->N + (uint64_t)kMFThreads * opt - 1) / ((uint64_t)kMFThreads * opt);
-    // one wave polls the exchange: up to 16 workgroups flat, beyond that the
-    // two-level exchange over 8 groups (G a multiple of 8; the workgroups
-    // past the last oscillator contribute zero sums)
-    if (G64 > 16) G64 = (G64 + 7) / 8 * 8;
-    const uint32_t G = (uint32_t)G64;
+    int r = 0;
+    while (x > 1) {
+        x >>= 1;
+        ++r;
+    }
+    return r;
+}
+
+// The register-resident kernel at `opt` oscillators per lane: workgroups per
+// realization (up to 16 flat; beyond that the two-level exchange over 8
+// groups, G a multiple of 8, the workgroups past the last oscillator
+// contributing zero sums), entry point, co-resident workgroups, and whether
+// a realization fits (at most one polling lane per exchange word).
+struct MFShape {
+    int opt = 0;
+    uint32_t G = 0;
     void* kern = nullptr;
-    const bool heun = run->scheme == SDE_HEUN;
+    uint64_t capacity = 0;
+    bool fits = false;
+};
+
+static int mf_shape(sde_ctx* ctx, uint32_t N, int opt, bool heun, MFShape* out)
+{
+    uint64_t G64 = ((uint64_t)N + (uint64_t)kMFThreads * opt - 1) / ((uint64_t)kMFThreads * opt);
+    if (G64 > 16) G64 = (G64 + 7) / 8 * 8;
     switch (opt) {
-    case 1: kern = heun ? mf_kernel_ptr<1, SDE_HEUN>() : mf_kernel_ptr<1, SDE_EULER>(); break;
-    case 2: kern = heun ? mf_kernel_ptr<2, SDE_HEUN>() : mf_kernel_ptr<2, SDE_EULER>(); break;
-    case 4: kern = heun ? mf_kernel_ptr<4, SDE_HEUN>() : mf_kernel_ptr<4, SDE_EULER>(); break;
-    default: kern = heun ? mf_kernel_ptr<8, SDE_HEUN>() : mf_kernel_ptr<8, SDE_EULER>(); break;
+    case 1: out->kern = heun ? mf_kernel_ptr<1, SDE_HEUN>() : mf_kernel_ptr<1, SDE_EULER>(); break;
+    case 2: out->kern = heun ? mf_kernel_ptr<2, SDE_HEUN>() : mf_kernel_ptr<2, SDE_EULER>(); break;
+    case 4: out->kern = heun ? mf_kernel_ptr<4, SDE_HEUN>() : mf_kernel_ptr<4, SDE_EULER>(); break;
+    default: out->kern = heun ? mf_kernel_ptr<8, SDE_HEUN>() : mf_kernel_ptr<8, SDE_EULER>(); break;
     }
     int per_cu = 0;
-    SDE_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, kMFThreads, 0));
-    const uint64_t capacity = (uint64_t)std::max(per_cu, 0) * ctx->n_cu;
-    const bool fits = capacity >= G64 && G64 <= kMaxMFGroups;
-    if (ctx->kura_mf == 1 || (ctx->kura_mf == 0 && !fits))
-        return run_meanfield_streamed(ctx, d, run, phi, omega, r_samples, n_samples, M, stream);
-    if (!fits)
-        return fail(ctx, SDE_ERR_UNSUPPORTED, "mean-field kernel: N = %u needs %llu co-resident workgroups, the "
-                    "device holds %llu (at most %u per realization)", d->N, (unsigned long long)G64,
-                    (unsigned long long)capacity, kMaxMFGroups);
-    // realizations per cooperative launch: as many as fit co-resident
-    const uint32_t r_per_launch = (uint32_t)std::min<uint64_t>(d->R, capacity / G);
+    SDE_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, out->kern, kMFThreads, 0));
+    out->opt = opt;
+    out->capacity = (uint64_t)std::max(per_cu, 0) * ctx->n_cu;
+    out->fits = G64 <= kMaxMFGroups && out->capacity >= G64;
+    out->G = (uint32_t)G64;
+    return SDE_OK;
+}
 
-    void* slots = nullptr;
-    const size_t slot_words = (size_t)2 * r_per_launch * G * kMFWordsPerGroup;
-    const size_t slot2_words = (size_t)2 * r_per_launch * 8 * kMFWordsPerGroup;
-    int st = ensure_ws(ctx, kSlotKuraPartials, (slot_words + slot2_words) * sizeof(uint64_t), &slots);
-    if (st) return st;
+// Exchange words one call at this shape needs (both parities, both levels).
+static size_t mf_slot_words(const MFShape& sh, uint32_t R, size_t* slot_words)
+{
+    const uint32_t r_per_launch = (uint32_t)std::min<uint64_t>(R, sh.capacity / sh.G);
+    *slot_words = (size_t)2 * r_per_launch * sh.G * kMFWordsPerGroup;
+    return *slot_words + (size_t)2 * r_per_launch * 8 * kMFWordsPerGroup;
+}
+
+// All realizations of one call at shape `sh`, as many per cooperative
+// launch as fit co-resident; `slots` holds mf_slot_words words.
+static int mf_launch(sde_ctx* ctx, const MFShape& sh, const sde_kuramoto_desc* d, const KuraConsts& kc,
+                     uint64_t seed, uint64_t step0, uint64_t n_steps, bool init_from_state, float* phi,
+                     const float* omega, double* r_samples, uint64_t n_samples, uint32_t M, int* flag,
+                     uint64_t* slots, hipStream_t stream)
+{
+    const uint32_t G = sh.G;
+    const uint32_t r_per_launch = (uint32_t)std::min<uint64_t>(d->R, sh.capacity / G);
+    size_t slot_words = 0;
+    const size_t n32 = 2 * mf_slot_words(sh, d->R, &slot_words);
     for (uint32_t r0 = 0; r0 < d->R; r0 += r_per_launch) {
         const uint32_t nr = std::min(r_per_launch, d->R - r0);
         // tags start at 1: zeroed slots never match
-        const size_t n32 = 2 * (slot_words + slot2_words);
         hipLaunchKernelGGL(mf_zero_kernel, dim3((uint32_t)((n32 + 255) / 256)), dim3(256), 0, stream,
-                           static_cast<uint32_t*>(slots), n32);
+                           reinterpret_cast<uint32_t*>(slots), n32);
         SDE_HIP(ctx, hipGetLastError());
         MFArgs A;
-        A.slots2 = static_cast<uint64_t*>(slots) + slot_words;
+        A.slots2 = slots + slot_words;
         A.tree = G > 16 ? 1u : 0u;
         A.theta = phi + (uint64_t)r0 * d->N;
         A.omega = omega;
         A.r_samples = r_samples ? r_samples + (uint64_t)r0 * n_samples : nullptr;
-        A.slots = static_cast<uint64_t*>(slots);
-        A.flag = ctx->flag;
+        A.slots = slots;
+        A.flag = flag;
         A.N = d->N;
         A.R = nr;
         A.G = G;
         A.M = M;
-        A.step0 = run->step0;
-        A.n_steps = d->n_steps;
+        A.step0 = step0;
+        A.n_steps = n_steps;
         A.n_samples = n_samples;
-        A.key0 = (uint32_t)run->seed;
-        A.key1 = (uint32_t)(run->seed >> 32);
+        A.key0 = (uint32_t)seed;
+        A.key1 = (uint32_t)(seed >> 32);
         A.omega_scale = kc.omega_scale;
         A.hdt2pi = kc.hdt2pi;
         A.kn = kc.kn;
         A.c2 = kc.c2;
-        A.init_from_state = run->init == SDE_INIT_FROM_STATE;
+        A.init_from_state = init_from_state;
         A.xcd_map = (ctx->xcds == 8 && nr % 8 == 0) ? 1 : 0;
         A.xcd_local = ctx->kura_xcd_local;
         A.spin_limit = 1u << 26;
         A.r_base = r0;
         void* args[] = {&A};
-        SDE_HIP(ctx, hipLaunchCooperativeKernel(kern, dim3(nr * G), dim3(kMFThreads), args, 0, stream));
+        SDE_HIP(ctx, hipLaunchCooperativeKernel(sh.kern, dim3(nr * G), dim3(kMFThreads), args, 0, stream));
     }
     return SDE_OK;
+}
+
+// Times every fitting shape on a 64-step run of the call's N and R (fresh
+// phases from Philox into a scratch state, no samples, the NaN flag of the
+// trials) and returns the fastest; the default shape is kept unless another
+// is more than 3 % faster, so that timing noise does not move the choice.
+static int mf_tune(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, const KuraConsts& kc,
+                   const float* omega, const MFShape (&shapes)[4], int n_shapes, int def, uint64_t* slots,
+                   hipStream_t stream, int* best_opt)
+{
+    void* scratch = nullptr;
+    int st = ensure_ws(ctx, kSlotTune, (size_t)d->N * d->R * sizeof(float), &scratch);
+    if (st) return st;
+    hipEvent_t e0, e1;
+    SDE_HIP(ctx, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return fail(ctx, SDE_ERR_DEVICE, "mean-field autotuner: hipEventCreate failed");
+    }
+    float ms[4] = {};
+    for (int c = 0; c < n_shapes && st == SDE_OK; ++c) {
+        for (int rep = 0; rep < 2 && st == SDE_OK; ++rep) {  // the first launch loads the code object
+            if (hipEventRecord(e0, stream) != hipSuccess) st = SDE_ERR_DEVICE;
+            if (!st)
+                st = mf_launch(ctx, shapes[c], d, kc, run->seed, 0, 64, false, static_cast<float*>(scratch), omega,
+                               nullptr, 0, 100, ctx->tune_flag, slots, stream);
+            if (!st && hipEventRecord(e1, stream) != hipSuccess) st = SDE_ERR_DEVICE;
+            if (!st && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&ms[c], e0, e1) != hipSuccess))
+                st = SDE_ERR_DEVICE;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st == SDE_ERR_DEVICE) return fail(ctx, st, "mean-field autotuner: HIP event or launch failed");
+    if (st) return st;
+    int best = def;
+    for (int c = 0; c < n_shapes; ++c)
+        if (ms[c] < 0.97f * ms[best]) best = c;
+    *best_opt = shapes[best].opt;
+    return SDE_OK;
+}
+
+static int run_meanfield(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, float* phi,
+                         const float* omega, double* r_samples, uint64_t n_samples, uint32_t M,
+                         hipStream_t stream)
+{
+    const KuraConsts kc = kuramoto_consts(d);
+    const bool heun = run->scheme == SDE_HEUN;
+    // the shapes at 1, 2, 4, 8 oscillators per lane (8 is the most the kernel
+    // holds in registers with its noise block, its prefetched next block and
+    // the sines and cosines kept for the drift); the default is the smallest
+    // that needs at most 16 workgroups per realization, else the largest
+    MFShape shapes[4];
+    int n_fit = 0, def = -1;
+    MFShape fit[4];
+    for (int c = 0; c < 4; ++c) {
+        int st = mf_shape(ctx, d->N, 1 << c, heun, &shapes[c]);
+        if (st) return st;
+        if (!shapes[c].fits) continue;
+        if (def < 0 && shapes[c].G <= 16) def = n_fit;
+        fit[n_fit++] = shapes[c];
+    }
+    if (def < 0) def = n_fit - 1;
+    if (ctx->kura_mf == 1 || (ctx->kura_mf == 0 && n_fit == 0))
+        return run_meanfield_streamed(ctx, d, run, phi, omega, r_samples, n_samples, M, stream);
+    if (n_fit == 0)
+        return fail(ctx, SDE_ERR_UNSUPPORTED, "mean-field kernel: N = %u needs %u co-resident workgroups of %d "
+                    "lanes x 8 oscillators, the device holds %llu (at most %u per realization)", d->N, shapes[3].G,
+                    kMFThreads, (unsigned long long)shapes[3].capacity, kMaxMFGroups);
+    // exchange words for any of the fitting shapes
+    size_t words = 0, unused = 0;
+    for (int c = 0; c < n_fit; ++c) words = std::max(words, mf_slot_words(fit[c], d->R, &unused));
+    void* slots = nullptr;
+    int st = ensure_ws(ctx, kSlotKuraPartials, words * sizeof(uint64_t), &slots);
+    if (st) return st;
+    // oscillators per lane: forced, cached, or tuned on this call's shape class
+    int chosen = -1;
+    if (ctx->kura_mf_opt) {
+        for (int c = 0; c < n_fit; ++c)
+            if (fit[c].opt == ctx->kura_mf_opt) chosen = c;
+        if (chosen < 0)
+            return fail(ctx, SDE_ERR_UNSUPPORTED, "mean-field kernel: N = %u does not fit at %d oscillators per lane",
+                        d->N, ctx->kura_mf_opt);
+    } else {
+        char key[160];
+        snprintf(key, sizeof key, "meanfield|%s|N2^%d|R2^%d|%s|xcd%d", ctx->arch.c_str(), ilog2_u64(d->N),
+                 ilog2_u64(d->R), heun ? "heun" : "euler", ctx->kura_xcd_local);
+        int opt = 0;
+        if (!tune_lookup(ctx, key, &opt) && ctx->autotune && n_fit > 1) {
+            const auto t0 = std::chrono::steady_clock::now();
+            if ((st = mf_tune(ctx, d, run, kc, omega, fit, n_fit, def, static_cast<uint64_t*>(slots), stream, &opt)))
+                return st;
+            ctx->last.tuned = 1;
+            ctx->last.tune_ms =
+                std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            tune_store(ctx, key, opt);
+        }
+        for (int c = 0; c < n_fit; ++c)
+            if (fit[c].opt == opt) chosen = c;
+        if (chosen < 0) chosen = def;  // no choice yet, or one made for another N of the class that does not fit
+    }
+    ctx->last.kura_mf_opt = fit[chosen].opt;
+    return mf_launch(ctx, fit[chosen], d, kc, run->seed, run->step0, d->n_steps, run->init == SDE_INIT_FROM_STATE,
+                     phi, omega, r_samples, n_samples, M, ctx->flag, static_cast<uint64_t*>(slots), stream);
 }
 
 // One stage: the whole j range per workgroup (J = 1), or J slices of jlen
@@ -1268,16 +1397,6 @@ static int tiled_tune(sde_ctx* ctx, const sde_kuramoto_desc* d, const TiledArgs&
     (void)hipEventDestroy(e1);
     if (st == SDE_ERR_DEVICE) return fail(ctx, st, "all-pairs autotuner: HIP event or launch failed");
     return st;
-}
-
-static int ilog2_u64(uint64_t x)
-{
-    int r = 0;
-    while (x > 1) {
-        x >>= 1;
-        ++r;
-    }
-    return r;
 }
 
 static int run_tiled(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, float* phi,

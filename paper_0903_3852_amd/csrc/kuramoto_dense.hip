@@ -34,15 +34,19 @@
 //                    float4 holding the k of four consecutive MFMAs.
 // A workgroup owns 128 rows x 32 realizations (64 columns), so every lane
 // holds S and C of the same (i, r) in its accumulators; its waves split the
-// k loop (8 waves for the 16-bit variants, 4 for FP32) and sum their partial
-// tiles through LDS in a fixed order.  Workgroups are dealt to XCDs so that
-// each XCD sweeps a contiguous band of rows over all columns: its slice of K
-// is read from HBM/MALL once per product, B once per XCD, and the workgroups
-// that share a K slab or a B column block hit in the XCD's L2.
+// k loop (8 or 4 waves for the 16-bit variants, 4 for FP32) and sum their
+// partial tiles through LDS in a fixed order.  Workgroups are dealt to XCDs
+// so that each XCD sweeps a contiguous band of rows over all columns: its
+// slice of K is read from HBM/MALL once per product, B once per XCD, and the
+// workgroups that share a K slab or a B column block hit in the XCD's L2.
+// The wave count and the banding (against plain row-major order) are chosen
+// per shape class by timing one stage of each.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
+#include <type_traits>
 
 #include "device_common.h"
 #include "kuramoto_common.h"
@@ -76,6 +80,7 @@ struct DenseArgs {
     float omega_scale, hdt2pi, c2;
     int32_t stage;         // 1 predictor (or Euler step), 2 corrector
     int32_t euler;
+    int32_t band;          // deal row tiles to XCDs in contiguous bands (when they split evenly)
 };
 
 __device__ __forceinline__ uint32_t bcol(uint32_t r, uint32_t kind)
@@ -144,11 +149,12 @@ __device__ __forceinline__ float dense_stage(const DenseArgs& A, uint64_t n, uin
     return t;
 }
 
-// workgroup -> (row tile, realization tile); XCD-aware when the row tiles
-// split evenly over the 8 XCDs.
-__device__ __forceinline__ void tile_of(uint32_t b, uint32_t n_mt, uint32_t n_nt, uint32_t& mt, uint32_t& nt)
+// workgroup -> (row tile, realization tile); with `band`, XCD-aware when the
+// row tiles split evenly over the 8 XCDs (workgroup b runs on XCD b mod 8).
+__device__ __forceinline__ void tile_of(uint32_t b, uint32_t n_mt, uint32_t n_nt, int32_t band, uint32_t& mt,
+                                        uint32_t& nt)
 {
-    if (n_mt % 8 == 0) {
+    if (band && n_mt % 8 == 0) {
         const uint32_t x = b & 7u, l = b >> 3;
         mt = x * (n_mt / 8) + l / n_nt;
         nt = l % n_nt;
@@ -348,15 +354,16 @@ __device__ __forceinline__ void dense_reduce_tile(const f32x4 (&acc)[8][4], f32x
 // as its 12 MFMAs are issued, the B fragments after the last row block, and
 // the SIMD's other wave computes while one waits.  Per accumulator the
 // products still enter in the order hi*hi, hi*lo, lo*hi of each k block.
-constexpr int kDense16Threads = 512;
-constexpr uint32_t kSplitK16 = 8;
-
-template <typename T, typename V>
-__global__ __launch_bounds__(kDense16Threads, 1) void dense_mfma_kernel(DenseArgs A)
+// A 4-wave variant (one wave per SIMD, every fourth k block) is the other
+// candidate of the autotuner.
+template <typename T, typename V, int NW>
+__global__ __launch_bounds__(NW * 64, 1) void dense_mfma_kernel(DenseArgs A)
 {
+    static_assert(NW == 4 || NW == 8, "4 or 8 waves");
+    constexpr uint32_t kThreads = NW * 64, kSplit = NW;
     // Partial tiles are summed in two rounds: waves 4-7 hand theirs to waves
-    // 0-3 (red[0..2] and slot3), then waves 1-3 hand the pair sums to the
-    // tile (red[0..2]).  The transposed tile [realization][row] overlays
+    // 0-3 (red[0..2] and slot3; 8 waves only), then waves 1-3 hand theirs to
+    // the tile (red[0..2]).  The transposed tile [realization][row] overlays
     // slot3, whose contents are consumed before the tile is written.
     __shared__ f32x4 red[3][32][kWave];
     __shared__ __attribute__((aligned(16))) float tile[2 * kRealTile * (kRowTile + 1)];
@@ -365,7 +372,7 @@ __global__ __launch_bounds__(kDense16Threads, 1) void dense_mfma_kernel(DenseArg
     float (*tS)[kRowTile + 1] = reinterpret_cast<float (*)[kRowTile + 1]>(tile);
     float (*tC)[kRowTile + 1] = reinterpret_cast<float (*)[kRowTile + 1]>(tile + kRealTile * (kRowTile + 1));
     uint32_t mt, nt;
-    tile_of(blockIdx.x, A.Mp / kRowTile, A.Rp / kRealTile, mt, nt);
+    tile_of(blockIdx.x, A.Mp / kRowTile, A.Rp / kRealTile, A.band, mt, nt);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63u;
     const uint32_t KB = A.Np / kKStep;
     const uint64_t frag = 2 * 64 * 8;              // elements per k block (hi + lo)
@@ -395,9 +402,9 @@ __global__ __launch_bounds__(kDense16Threads, 1) void dense_mfma_kernel(DenseArg
             al[m] = *reinterpret_cast<const V*>(pa + m * stream + o + kFragLo);
         }
     }
-    for (uint32_t kb = wave; kb < KB; kb += kSplitK16) {
-        const bool more = kb + kSplitK16 < KB;
-        const uint64_t on = (uint64_t)(more ? kb + kSplitK16 : kb) * frag;
+    for (uint32_t kb = wave; kb < KB; kb += kSplit) {
+        const bool more = kb + kSplit < KB;
+        const uint64_t on = (uint64_t)(more ? kb + kSplit : kb) * frag;
 #pragma unroll
         for (int m = 0; m < 8; ++m) {
 #pragma unroll
@@ -414,22 +421,24 @@ __global__ __launch_bounds__(kDense16Threads, 1) void dense_mfma_kernel(DenseArg
         if (more) load_b(on);
     }
     // round 1: wave w < 4 adds wave w + 4's partial
-    if (wave >= 4) {
-        f32x4 (*dst)[kWave] = wave == 7 ? slot3 : red[wave - 4];
+    if constexpr (NW == 8) {
+        if (wave >= 4) {
+            f32x4 (*dst)[kWave] = wave == 7 ? slot3 : red[wave - 4];
 #pragma unroll
-        for (int m = 0; m < 8; ++m)
+            for (int m = 0; m < 8; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n) dst[m * 4 + n][lane] = acc[m][n];
+                for (int n = 0; n < 4; ++n) dst[m * 4 + n][lane] = acc[m][n];
+        }
+        __syncthreads();
+        if (wave < 4) {
+            const f32x4 (*src)[kWave] = wave == 3 ? slot3 : red[wave];
+#pragma unroll
+            for (int m = 0; m < 8; ++m)
+#pragma unroll
+                for (int n = 0; n < 4; ++n) acc[m][n] += src[m * 4 + n][lane];
+        }
+        __syncthreads();
     }
-    __syncthreads();
-    if (wave < 4) {
-        const f32x4 (*src)[kWave] = wave == 3 ? slot3 : red[wave];
-#pragma unroll
-        for (int m = 0; m < 8; ++m)
-#pragma unroll
-            for (int n = 0; n < 4; ++n) acc[m][n] += src[m * 4 + n][lane];
-    }
-    __syncthreads();
     // round 2: p0 + ((p1 + p2) + p3) into the tile, transposed, times the
     // exact power of two that undoes the scaling of K
     const float inv = A.scale[1];
@@ -450,7 +459,7 @@ __global__ __launch_bounds__(kDense16Threads, 1) void dense_mfma_kernel(DenseArg
             }
     }
     __syncthreads();
-    for (uint32_t p = threadIdx.x; p < 32 * kWave; p += kDense16Threads) {
+    for (uint32_t p = threadIdx.x; p < 32 * kWave; p += kThreads) {
         const uint32_t quad = p / kWave, l = p % kWave;
         const f32x4 sum = (red[0][quad][l] + red[1][quad][l]) + red[2][quad][l];
         const uint32_t m = quad / 4, n = quad % 4;
@@ -460,8 +469,8 @@ __global__ __launch_bounds__(kDense16Threads, 1) void dense_mfma_kernel(DenseArg
         for (int q = 0; q < 4; ++q) t[rl][m * 16 + 4 * (l >> 4) + q] += sum[q] * inv;
     }
     __syncthreads();
-    dense_tile_stage<kDense16Threads>(A, mt, nt, tS, tC);
-    dense_tile_store<T, V, kDense16Threads>(A, mt, nt, tS, tC);
+    dense_tile_stage<kThreads>(A, mt, nt, tS, tC);
+    dense_tile_store<T, V, kThreads>(A, mt, nt, tS, tC);
 }
 
 // ------------------------------------------------------------- FP32 MFMA --
@@ -476,7 +485,7 @@ __global__ __launch_bounds__(kDenseThreads, 1) void dense_mfma32_kernel(DenseArg
     __shared__ f32x4 red[kSplitK - 1][32][kWave];
     __shared__ float tS[kRealTile][kRowTile + 1], tC[kRealTile][kRowTile + 1];
     uint32_t mt, nt;
-    tile_of(blockIdx.x, A.Mp / kRowTile, A.Rp / kRealTile, mt, nt);
+    tile_of(blockIdx.x, A.Mp / kRowTile, A.Rp / kRealTile, A.band, mt, nt);
     const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
     const uint32_t KB16 = A.Np / 16;
     const uint64_t stream = (uint64_t)KB16 * 256;  // floats per 16-row block
@@ -580,6 +589,16 @@ __global__ void dense_operand_kernel(const float* theta, uint32_t N, uint32_t R,
 }
 
 // ------------------------------------------------------------------ host --
+static int ilog2_dense(uint64_t x)
+{
+    int r = 0;
+    while (x > 1) {
+        x >>= 1;
+        ++r;
+    }
+    return r;
+}
+
 template <typename T>
 static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, float* phi,
                            const float* omega, const float* K, double* r_samples, uint64_t n_samples, uint32_t M,
@@ -640,16 +659,98 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
     uint64_t* nbase = nullptr;
     if ((st = step_counter(ctx, &nbase))) return st;
     A.nbase = nbase;
+    // launch choice: bit 0 = 4 waves instead of 8 (16-bit variants), bit 1 =
+    // row tiles in plain order instead of XCD bands
+    int choice = 0;
     auto launch = [&](hipStream_t s) -> int {
-        if constexpr (sizeof(T) == 4)
+        A.band = (choice & 2) ? 0 : 1;
+        if constexpr (sizeof(T) == 4) {
             hipLaunchKernelGGL(dense_mfma32_kernel, grid, dim3(kDenseThreads), 0, s, A);
-        else if constexpr (__is_same(T, __bf16))
-            hipLaunchKernelGGL((dense_mfma_kernel<__bf16, bf16x8>), grid, dim3(kDense16Threads), 0, s, A);
-        else
-            hipLaunchKernelGGL((dense_mfma_kernel<_Float16, f16x8>), grid, dim3(kDense16Threads), 0, s, A);
+        } else {
+            typedef typename std::conditional<__is_same(T, __bf16), bf16x8, f16x8>::type V;
+            if (choice & 1)
+                hipLaunchKernelGGL((dense_mfma_kernel<T, V, 4>), grid, dim3(256), 0, s, A);
+            else
+                hipLaunchKernelGGL((dense_mfma_kernel<T, V, 8>), grid, dim3(512), 0, s, A);
+        }
         SDE_HIP(ctx, hipGetLastError());
         return SDE_OK;
     };
+    // The choice is tuned per shape class: one predictor stage of each
+    // candidate from the call's operand, its phases, carry and next operand
+    // going to scratch and to the operand buffer the call's first stage
+    // overwrites anyway; the default (8 waves, bands) is kept unless another
+    // is more than 3 % faster.
+    {
+        const bool band_matters = (Mp / kRowTile) % 8 == 0;
+        const int n_cand = (sizeof(T) == 4 ? 1 : 2) * (band_matters ? 2 : 1);
+        int cands[4], nc = 0;
+        for (int c = 0; c < 4; ++c) {
+            if ((c & 1) && sizeof(T) == 4) continue;
+            if ((c & 2) && !band_matters) continue;
+            cands[nc++] = c;
+        }
+        char tkey[160];
+        snprintf(tkey, sizeof tkey, "dense%d|%s|N2^%d|R2^%d", d->coupling, ctx->arch.c_str(), ilog2_dense(N),
+                 ilog2_dense(R));
+        if (ctx->dense_launch) {
+            choice = ctx->dense_launch - 1;
+        } else if (!tune_lookup(ctx, tkey, &choice)) {
+            choice = 0;
+            if (ctx->autotune && n_cand > 1) {
+                const auto t0 = std::chrono::steady_clock::now();
+                void* scratch = nullptr;
+                if ((st = ensure_ws(ctx, kSlotTune, (size_t)2 * NR * sizeof(float), &scratch))) return st;
+                launch_step_set(nbase, run->step0, stream);
+                DenseArgs saved = A;
+                A.k = 0;
+                A.stage = 1;
+                A.euler = 0;
+                A.B = Bbuf[0];
+                A.Bnext = Bbuf[1];
+                A.src = phi;
+                A.base = phi;
+                A.dst = static_cast<float*>(scratch);
+                A.F1 = static_cast<float*>(scratch) + NR;
+                hipEvent_t e0, e1;
+                SDE_HIP(ctx, hipEventCreate(&e0));
+                if (hipEventCreate(&e1) != hipSuccess) {
+                    (void)hipEventDestroy(e0);
+                    return fail(ctx, SDE_ERR_DEVICE, "dense autotuner: hipEventCreate failed");
+                }
+                float ms[4] = {};
+                for (int c = 0; c < nc && st == SDE_OK; ++c) {
+                    choice = cands[c];
+                    for (int rep = 0; rep < 2 && st == SDE_OK; ++rep) {  // the first launch loads the code object
+                        if (hipEventRecord(e0, stream) != hipSuccess) st = SDE_ERR_DEVICE;
+                        if (!st) st = launch(stream);
+                        if (!st && hipEventRecord(e1, stream) != hipSuccess) st = SDE_ERR_DEVICE;
+                        if (!st && (hipEventSynchronize(e1) != hipSuccess ||
+                                    hipEventElapsedTime(&ms[c], e0, e1) != hipSuccess))
+                            st = SDE_ERR_DEVICE;
+                    }
+                }
+                (void)hipEventDestroy(e0);
+                (void)hipEventDestroy(e1);
+                if (st == SDE_ERR_DEVICE) return fail(ctx, st, "dense autotuner: HIP event or launch failed");
+                if (st) return st;
+                int best = 0;
+                for (int c = 1; c < nc; ++c)
+                    if (ms[c] < 0.97f * ms[best]) best = c;
+                choice = cands[best];
+                A = saved;
+                ctx->last.tuned = 1;
+                ctx->last.tune_ms =
+                    std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+                tune_store(ctx, tkey, choice);
+            }
+        }
+        if (choice < 0 || choice > 3) choice = 0;
+        if (sizeof(T) == 4) choice &= 2;    // one FP32 kernel (4 waves)
+        if (!band_matters) choice &= 1;     // bands or not: the same order
+    }
+    ctx->last.dense_waves = sizeof(T) == 4 ? 4 : (choice & 1) ? 4 : 8;
+    ctx->last.dense_xcd_bands = (choice & 2) || (Mp / kRowTile) % 8 != 0 ? 0 : 1;
     // `count` steps from the device step base, then advance it.  The operand
     // buffers alternate per stage; chunks hold an even number of stages so a
     // recorded chunk always starts from the same buffer.
@@ -686,9 +787,9 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
     launch_step_set(nbase, run->step0, stream);
     const uint32_t C = chunk_steps(M, d->n_steps, A.euler != 0);
     char key[320];
-    snprintf(key, sizeof key, "dense%d|%p|%p|%p|%p|%p|%p|%u|%u|%u|%u|%a|%a|%a|%d|%llu|%u|%llu", d->coupling,
+    snprintf(key, sizeof key, "dense%d|%p|%p|%p|%p|%p|%p|%u|%u|%u|%u|%a|%a|%a|%d|%llu|%u|%llu|v%d", d->coupling,
              (void*)phi, (void*)omega, (void*)r_samples, wa, wb, wk, N, R, A.key0, A.key1, A.omega_scale, A.hdt2pi,
-             A.c2, A.euler, (unsigned long long)run->step0, M, (unsigned long long)n_samples);
+             A.c2, A.euler, (unsigned long long)run->step0, M, (unsigned long long)n_samples, choice);
     const uint64_t full = d->n_steps / C, rem = d->n_steps % C;
     for (uint64_t c = 0; c < full; ++c)
         if ((st = run_recorded(ctx, std::string(key) + "|C" + std::to_string(C), stream,

@@ -326,6 +326,14 @@ int sde_set_option(sde_ctx* ctx, int option, int64_t value)
         if (value != 0 && value != 1) break;
         ctx->kura_xcd_local = (int)value;
         return SDE_OK;
+    case SDE_OPT_KURA_MF_OPT:
+        if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8) break;
+        ctx->kura_mf_opt = (int)value;
+        return SDE_OK;
+    case SDE_OPT_DENSE_LAUNCH:
+        if (value < 0 || value > 4) break;
+        ctx->dense_launch = (int)value;
+        return SDE_OK;
     default: break;
     }
     return fail(ctx, SDE_ERR_INVALID, "option %d: invalid value %lld", option, (long long)value);

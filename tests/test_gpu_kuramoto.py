@@ -159,6 +159,60 @@ def test_dense_euler_and_small_shapes(gpu, coupling, tol, N, R, scheme):
     np.testing.assert_allclose(rs.cpu().numpy(), rref, rtol=0, atol=10 * tol)
 
 
+def test_dense_launch_choices(gpu):
+    """Every dense launch choice, forced (8 or 4 waves splitting the k loop,
+    row tiles in XCD bands or plain order; N = 1000 gives 8 row tiles, so
+    the banding applies), for each product against the oracle over 50 Heun
+    steps; the order of the tiles changes no arithmetic, so banded and plain
+    runs of one wave count agree bit for bit."""
+    sde, ctx, dev = gpu
+    N, R, n = 1000, 40, 50
+    Kmat = sde_inputs.dense_coupling(N, 4.0, 31)
+    omega = sde_inputs.kuramoto_omega(N, 0.5, 32)
+    ref, _ = oracle.kuramoto_integrate(N, R, 4.0, 0.05, 0.005, n, 0, oracle.DENSE, 0, 33,
+                                       omega.astype(np.float64), Kmat=Kmat.astype(np.float64))
+    for coupling, tol in [(2, 1e-5), (3, 1e-4), (4, 1e-5)]:
+        got = {}
+        for launch in (1, 2, 3, 4):
+            sde.sde_set_option(ctx, sde.SDE_OPT_DENSE_LAUNCH, launch)
+            ph, _ = _run(gpu, N, R, 4.0, 0.05, 0.005, n, coupling, 0, 33, omega, Kmat, samples=False)
+            st = sde.sde_get_stats(ctx)
+            waves = 4 if coupling == 2 or launch in (2, 4) else 8
+            assert st["dense_waves"] == waves and st["dense_xcd_bands"] == (1 if launch <= 2 else 0)
+            err = _circ_err(ph.cpu().numpy(), ref)
+            print(f"dense coupling {coupling}, launch {launch}: max phase error {err.max():.2e}")
+            assert err.max() <= tol
+            got[launch] = ph.clone()
+        assert torch.equal(got[1], got[3]) and torch.equal(got[2], got[4])
+        if coupling == 2:
+            assert torch.equal(got[1], got[2])
+    for bad in (-1, 5):
+        with pytest.raises(sde.SDEError):
+            sde.sde_set_option(ctx, sde.SDE_OPT_DENSE_LAUNCH, bad)
+
+
+def test_dense_tuner(gpu):
+    """Left to the tuner, the first call of a shape class times the launch
+    choices and caches one; the next call reuses it without tuning and
+    equals, bit for bit, a run forced to that choice."""
+    sde, ctx, dev = gpu
+    N, R, n = 2000, 9, 10
+    Kmat = sde_inputs.dense_coupling(N, 4.0, 51)
+    omega = sde_inputs.kuramoto_omega(N, 0.5, 52)
+    _run(gpu, N, R, 4.0, 0.05, 0.005, n, 3, 0, 53, omega, Kmat, samples=False)
+    st1 = sde.sde_get_stats(ctx)
+    assert st1["tuned"] == 1 and st1["dense_waves"] in (4, 8) and st1["dense_xcd_bands"] in (0, 1)
+    a, _ = _run(gpu, N, R, 4.0, 0.05, 0.005, n, 3, 0, 53, omega, Kmat, samples=False)
+    st2 = sde.sde_get_stats(ctx)
+    assert st2["tuned"] == 0
+    assert (st2["dense_waves"], st2["dense_xcd_bands"]) == (st1["dense_waves"], st1["dense_xcd_bands"])
+    launch = 1 + (1 if st1["dense_waves"] == 4 else 0) + (0 if st1["dense_xcd_bands"] else 2)
+    sde.sde_set_option(ctx, sde.SDE_OPT_DENSE_LAUNCH, launch)
+    b, _ = _run(gpu, N, R, 4.0, 0.05, 0.005, n, 3, 0, 53, omega, Kmat, samples=False)
+    assert torch.equal(a, b)
+    print(f"dense tuner: {st1['dense_waves']} waves, bands {st1['dense_xcd_bands']} ({st1['tune_ms']:.2f} ms)")
+
+
 def test_dense_full_size_sampled(gpu):
     """The dense workload at its size -- N = 4096, 256 realizations, the
     BF16x3 product -- for 200 steps, realizations 0..3 checked against the

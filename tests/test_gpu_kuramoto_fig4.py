@@ -40,9 +40,10 @@ def _circ_err(theta_gpu, phi_ref):
 
 
 def _run(gpu, N, R, K, D, dt, n_steps, scheme=0, seed=1, omega=None, phi=None, step0=0, M=100, streamed=True,
-         samples=True):
+         samples=True, opt=0):
     sde, ctx, dev = gpu
     sde.sde_set_option(ctx, sde.SDE_OPT_KURA_MF, 1 if streamed else 2)
+    sde.sde_set_option(ctx, sde.SDE_OPT_KURA_MF_OPT, opt)
     om = omega if isinstance(omega, torch.Tensor) else torch.from_numpy(np.asarray(omega, dtype=np.float32)).to(dev)
     if phi is None:
         ph = torch.empty((R, N), dtype=torch.float32, device=dev)
@@ -54,7 +55,10 @@ def _run(gpu, N, R, K, D, dt, n_steps, scheme=0, seed=1, omega=None, phi=None, s
     desc = sde.sde_kuramoto_desc(N, R, K, D, dt, n_steps, sde.SDE_MEANFIELD, 0)
     run = sde.make_run(seed, step0=step0, scheme=scheme, init=init, sample_every=M, sync=1)
     sde.sde_kuramoto_integrate(ctx, desc, run, ph, om, None, rs)
-    assert sde.sde_get_stats(ctx)["mf_streamed"] == (1 if streamed else 0)
+    st = sde.sde_get_stats(ctx)
+    assert st["mf_streamed"] == (1 if streamed else 0)
+    if opt:
+        assert st["kura_mf_opt"] == opt
     return ph, rs
 
 
@@ -83,7 +87,7 @@ def test_tree_exchange_vs_oracle(gpu, streamed, N):
     cfg = sde_inputs.kuramoto_uniform(N=N, R=R)
     for scheme in (0, 1):
         ph, rs = _run(gpu, N, R, cfg["K"], cfg["D"], cfg["dt"], 100, scheme, cfg["seed"], cfg["omega"],
-                      streamed=streamed)
+                      streamed=streamed, opt=0 if streamed else 8)
         ref, rref = oracle.kuramoto_integrate(N, R, cfg["K"], cfg["D"], cfg["dt"], 100, 100, oracle.MEANFIELD,
                                               scheme, cfg["seed"], cfg["omega"].astype(np.float64))
         err = _circ_err(ph.cpu().numpy(), ref)
@@ -92,23 +96,60 @@ def test_tree_exchange_vs_oracle(gpu, streamed, N):
         np.testing.assert_allclose(rs.cpu().numpy(), rref, rtol=0, atol=1e-6)
 
 
-@pytest.mark.parametrize("N", [12289, 30001, 65535, 100003])
-def test_register_resident_lane_counts(gpu, N):
-    """The register-resident kernel at each count of oscillators per lane
-    (2, 4, 8 for these N, the last workgroup ragged; N = 100003 needs 25
-    workgroups of 8 per lane, rounded up to 32 for the two-level exchange,
-    the last 7 empty), Heun and Euler-Maruyama, 3 realizations."""
+@pytest.mark.parametrize("N,opt", [(12289, 2), (30001, 4), (65535, 8), (100003, 8), (12289, 1), (700, 2),
+                                   (4000, 8), (512, 1)])
+def test_register_resident_lane_counts(gpu, N, opt):
+    """The register-resident kernel at each count of oscillators per lane,
+    forced, the last workgroup ragged: N = 100003 needs 25 workgroups of 8
+    per lane, rounded up to 32 for the two-level exchange, the last 7 empty;
+    12289 at 1 per lane also takes the two-level exchange (25 -> 32);
+    700, 4000 and 512 fit one workgroup (no exchange).  Heun and
+    Euler-Maruyama, 3 realizations."""
     R = 3
     cfg = sde_inputs.kuramoto_uniform(N=N, R=R)
     for scheme in (0, 1):
         ph, rs = _run(gpu, N, R, cfg["K"], cfg["D"], cfg["dt"], 100, scheme, cfg["seed"], cfg["omega"],
-                      streamed=False)
+                      streamed=False, opt=opt)
         ref, rref = oracle.kuramoto_integrate(N, R, cfg["K"], cfg["D"], cfg["dt"], 100, 100, oracle.MEANFIELD,
                                               scheme, cfg["seed"], cfg["omega"].astype(np.float64))
         err = _circ_err(ph.cpu().numpy(), ref)
-        print(f"registers, N {N}, scheme {scheme}: max phase error {err.max():.2e}")
+        print(f"registers, N {N}, {opt} per lane, scheme {scheme}: max phase error {err.max():.2e}")
         assert err.max() <= 1e-5
         np.testing.assert_allclose(rs.cpu().numpy(), rref, rtol=0, atol=1e-6)
+
+
+def test_meanfield_tuner(gpu):
+    """With the lane count left to the tuner, the first call of a shape class
+    times the fitting counts and caches the choice; the next call of the
+    class reuses it without tuning and equals, bit for bit, a run forced to
+    that count.  A count at which N does not fit is refused."""
+    sde, ctx, dev = gpu
+    N, R = 8197, 5
+    cfg = sde_inputs.kuramoto_uniform(N=N, R=R)
+    args = (N, R, cfg["K"], cfg["D"], cfg["dt"], 50, 0, cfg["seed"], cfg["omega"])
+    _run(gpu, *args, streamed=False)
+    st1 = sde.sde_get_stats(ctx)
+    assert st1["tuned"] == 1 and st1["kura_mf_opt"] in (1, 2, 4, 8)
+    a, ra = _run(gpu, *args, streamed=False)
+    st2 = sde.sde_get_stats(ctx)
+    assert st2["tuned"] == 0 and st2["kura_mf_opt"] == st1["kura_mf_opt"]
+    b, rb = _run(gpu, *args, streamed=False, opt=st1["kura_mf_opt"])
+    assert torch.equal(a, b) and torch.equal(ra, rb)
+    print(f"mean-field tuner: {st1['kura_mf_opt']} per lane for N {N}, R {R} ({st1['tune_ms']:.2f} ms)")
+    for bad in (3, 16, -1):
+        with pytest.raises(sde.SDEError):
+            sde.sde_set_option(ctx, sde.SDE_OPT_KURA_MF_OPT, bad)
+    # 2^18 oscillators at 1 per lane would need 512 workgroups per realization
+    Nb = 1 << 18
+    ph = torch.zeros((1, Nb), dtype=torch.float32, device=dev)
+    om = torch.zeros(Nb, dtype=torch.float32, device=dev)
+    sde.sde_set_option(ctx, sde.SDE_OPT_KURA_MF, 2)
+    sde.sde_set_option(ctx, sde.SDE_OPT_KURA_MF_OPT, 1)
+    desc = sde.sde_kuramoto_desc(Nb, 1, 1.0, 0.1, 0.01, 10, sde.SDE_MEANFIELD, 0)
+    with pytest.raises(sde.SDEError) as e:
+        sde.sde_kuramoto_integrate(ctx, desc, sde.make_run(1, sync=1), ph, om, None, None)
+    assert e.value.status == sde.SDE_ERR_UNSUPPORTED
+    assert torch.count_nonzero(ph) == 0
 
 
 def test_streamed_matches_register_resident(gpu):
