@@ -436,14 +436,22 @@ enum {
     SDE_OPT_KURA_MF_OPT = 8, /* register-resident mean field oscillators per lane   */
                           /* (512 lanes per workgroup, so N / (512 OPT) workgroups  */
                           /* per realization): 0 (default) = tuned per shape class, */
-                          /* or 1, 2, 4, 8 to force (SDE_ERR_UNSUPPORTED if N does  */
-                          /* not fit at that count)                                 */
-    SDE_OPT_DENSE_LAUNCH = 9 /* dense coupling launch: 0 (default) = tuned per shape */
+                          /* or 1, 2, 4, 8 to restrict the choice to that count     */
+                          /* (SDE_ERR_UNSUPPORTED if N does not fit at it)          */
+    SDE_OPT_DENSE_LAUNCH = 9, /* dense coupling launch: 0 (default) = tuned per shape */
                           /* class; 1 = 8 waves per workgroup splitting the k loop, */
                           /* row tiles dealt to XCDs in bands; 2 = 4 waves, bands;  */
                           /* 3 = 8 waves, plain order; 4 = 4 waves, plain order     */
                           /* (FP32 always runs 4 waves; bands apply when the row    */
                           /* tiles split evenly over the 8 XCDs)                    */
+    SDE_OPT_KURA_MF_PAIRED = 10 /* register-resident mean field realizations per    */
+                          /* workgroup: 0 (default) = tuned per shape class; 1 =    */
+                          /* one; 2 = two (R even, 2 or 4 oscillators per lane, at  */
+                          /* most 32 workgroups per realization: each workgroup     */
+                          /* evaluates one realization's stage while the other's    */
+                          /* sums are exchanged).  With this option or              */
+                          /* SDE_OPT_KURA_MF_OPT set, the restricted set's default  */
+                          /* is run untuned; SDE_ERR_UNSUPPORTED if it is empty     */
 };
 /* Sets an option of the context.  SDE_ERR_INVALID for an unknown option or
  * value. */
@@ -469,6 +477,9 @@ typedef struct {
     int32_t dense_waves;     /* waves per workgroup (k-loop split) of the last dense  */
                              /* call                                                  */
     int32_t dense_xcd_bands; /* its row tiles were dealt to XCDs in bands (1)         */
+    int32_t kura_mf_paired;  /* the last register-resident mean-field call held two   */
+                             /* realizations per workgroup (1)                        */
+    int32_t reserved;
 } sde_stats;
 /* Statistics of the last integration call on `ctx`. */
 int sde_get_stats(const sde_ctx* ctx, sde_stats* out);

@@ -31,6 +31,7 @@ SDE_OPT_AUTOTUNE, SDE_OPT_GRAPHS, SDE_OPT_JJ_PPT, SDE_OPT_KURA_MF, SDE_OPT_KURA_
 SDE_OPT_KURA_XCD_LOCAL = 7
 SDE_OPT_KURA_MF_OPT = 8
 SDE_OPT_DENSE_LAUNCH = 9
+SDE_OPT_KURA_MF_PAIRED = 10
 
 EXPORTS = ["sde_create", "sde_destroy", "sde_strerror", "sde_last_error", "sde_check",
            "sde_jj_integrate", "sde_jj_integrate_noalloc", "sde_jj_integrate_f64", "sde_jj_integrate_recorded",
@@ -70,7 +71,8 @@ class sde_stats(ctypes.Structure):
                 ("tune_ms", ctypes.c_double), ("work_items", ctypes.c_uint64),
                 ("mf_streamed", ctypes.c_int32), ("kura_jsplit", ctypes.c_int32),
                 ("kura_tile", ctypes.c_int32), ("kura_mf_opt", ctypes.c_int32),
-                ("dense_waves", ctypes.c_int32), ("dense_xcd_bands", ctypes.c_int32)]
+                ("dense_waves", ctypes.c_int32), ("dense_xcd_bands", ctypes.c_int32),
+                ("kura_mf_paired", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class sde_surrogate_scaling(ctypes.Structure):

@@ -384,9 +384,10 @@ __device__ __forceinline__ void mf2_exchange_wave(const MFArgs& A, uint32_t r, u
 }
 
 // Whether all G workgroups of realization r run on one XCD: each publishes
-// its XCD id (epoch 0, agent scope) and reads everyone's.  Run by wave 0;
+// its XCD id (epoch 0, agent scope) and reads everyone's.  Run by one wave;
 // the answer is the same in every workgroup of the realization.
-__device__ __forceinline__ void mf2_locality(const MFArgs& A, uint32_t r, uint32_t w, MF2Shared& sh)
+template <typename SH>
+__device__ __forceinline__ void mf2_locality(const MFArgs& A, uint32_t r, uint32_t w, SH& sh)
 {
     const uint32_t lane = threadIdx.x & (kWave - 1);
     if (A.G == 1) return;  // no exchange
@@ -567,6 +568,352 @@ __global__ __launch_bounds__(kMFThreads, 1) void kuramoto_mf_kernel(MFArgs A)
             bad |= !isfinite(th[k]);
         }
     }
+    if (__ballot(bad) != 0 && lane == 0) atomicOr(A.flag, 1);
+}
+
+// ------------------------------------ MF, two realizations per workgroup --
+// The register-resident mean field with the exchange latency hidden behind
+// arithmetic: every workgroup holds the same slice of oscillators of two
+// realizations (A = 2p and B = 2p + 1 of the launch) in eight compute waves,
+// plus one exchange wave per realization.  The compute waves alternate
+// between the two realizations -- while A's sums travel between the
+// workgroups they evaluate B's stage, and the other way round -- and meet
+// the exchange waves only through flags in LDS, so no workgroup barrier is
+// on the step path.  An exchange wave adds its realization's eight wave
+// partials in wave order (FP64), publishes the sum as four tagged words,
+// polls the G workgroups' words (up to 32 workgroups, two words per lane),
+// adds the G pairs in a fixed order -- every workgroup of a realization gets
+// the same bits -- and leaves the sums in LDS.  Per realization the epochs,
+// words and their two parities are those of the one-realization kernel.
+constexpr int kMFPWaves = kMFWaves + 2;
+constexpr int kMFPThreads = kMFPWaves * kWave;
+constexpr uint32_t kMaxMFPGroups = 2 * kWave / kMFWordsPerGroup;
+
+struct MFPShared {
+    float ps[2][kMFWaves], pc[2][kMFWaves];  // per-wave FP32 partials of A and B
+    double S[2], C[2];                       // the realizations' sums of the epoch in ready[]
+    uint32_t arrived[2];                     // wave partials written so far (8 per epoch)
+    uint32_t ready[2];                       // epoch whose sums are in S, C
+    int ok;
+    int local;                               // the pair's workgroups share one XCD
+    __attribute__((aligned(16))) uint32_t words[2][kWave];  // each exchange wave's staged words
+};
+
+__device__ __forceinline__ uint32_t lds_acquire(const uint32_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+__device__ __forceinline__ void lds_release(uint32_t* p, uint32_t v)
+{
+    __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// Lanes poll words t and t + 64 (t < n, n <= 128) at p(.) until both carry
+// `tag`; both loads are in flight together.  False once a wait exceeded the
+// spin bound (the error flag is then set).
+template <typename Addr>
+__device__ __forceinline__ bool mfp_poll(const MFArgs& A, uint32_t n, Addr p, uint64_t tag, uint32_t& d0,
+                                         uint32_t& d1)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const bool has0 = lane < n, has1 = lane + kWave < n;
+    const uint64_t* q0 = p(has0 ? lane : 0u);
+    const uint64_t* q1 = p(has1 ? lane + kWave : 0u);
+    bool ok = true, got0 = !has0, got1 = !has1;
+    uint32_t spins = 0;
+    d0 = d1 = 0u;
+    while (!(got0 && got1)) {
+        const uint64_t v0 = got0 ? tag : __hip_atomic_load(q0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const uint64_t v1 = got1 ? tag : __hip_atomic_load(q1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (!got0 && (v0 & 0xffffffff00000000ull) == tag) {
+            got0 = true;
+            d0 = (uint32_t)v0;
+        }
+        if (!got1 && (v1 & 0xffffffff00000000ull) == tag) {
+            got1 = true;
+            d1 = (uint32_t)v1;
+        }
+        if (got0 && got1) break;
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > A.spin_limit) {
+            ok = false;
+            break;
+        }
+    }
+    if (__ballot(!ok) != 0) {
+        if (lane == 0) atomicOr(A.flag, 2);
+        return false;
+    }
+    return true;
+}
+
+// Exchange wave of realization X (0 = A, 1 = B): for every epoch, the
+// workgroup's sum published as soon as the eight wave partials are in, then
+// the G workgroups' sums polled, added and handed to the compute waves.
+__device__ __forceinline__ void mfp_exchange_loop(const MFArgs& A, int X, uint32_t r, uint32_t w, uint64_t n_epochs,
+                                                  MFPShared& sh)
+{
+    const uint32_t lane = threadIdx.x & (kWave - 1);
+    const bool local = sh.local != 0;
+    const uint32_t per1 = A.G * kMFWordsPerGroup;
+    auto d = [](float x) { return (double)x; };
+    for (uint32_t e = 1; e <= (uint32_t)n_epochs; ++e) {
+        const uint64_t tag = (uint64_t)(e + 1) << 32;
+        uint32_t spins = 0;
+        while (lds_acquire(&sh.arrived[X]) < kMFWaves * e) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > A.spin_limit) {
+                if (lane == 0) {
+                    __hip_atomic_store(&sh.ok, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    atomicOr(A.flag, 2);
+                }
+                return;
+            }
+        }
+        const double Sw = ((d(sh.ps[X][0]) + d(sh.ps[X][1])) + (d(sh.ps[X][2]) + d(sh.ps[X][3]))) +
+                          ((d(sh.ps[X][4]) + d(sh.ps[X][5])) + (d(sh.ps[X][6]) + d(sh.ps[X][7])));
+        const double Cw = ((d(sh.pc[X][0]) + d(sh.pc[X][1])) + (d(sh.pc[X][2]) + d(sh.pc[X][3]))) +
+                          ((d(sh.pc[X][4]) + d(sh.pc[X][5])) + (d(sh.pc[X][6]) + d(sh.pc[X][7])));
+        uint32_t d0 = 0u, d1 = 0u;
+        if (A.G > 1) {
+            mf2_publish_lanes(mf_word(A, A.slots, per1, r, e, w * kMFWordsPerGroup), tag, Sw, Cw, local);
+            if (!mfp_poll(A, per1, [&](uint32_t t) { return mf_word(A, A.slots, per1, r, e, t); }, tag, d0, d1)) {
+                if (lane == 0) __hip_atomic_store(&sh.ok, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                return;
+            }
+        } else if (lane < kMFWordsPerGroup) {  // one workgroup: its own sums are the pair
+            const uint64_t v = (uint64_t)__double_as_longlong(lane < 2 ? Sw : Cw);
+            d0 = (lane & 1u) ? (uint32_t)(v >> 32) : (uint32_t)v;
+        }
+        double S, C;
+        mf2_sum_words(d0, sh.words[X], S, C);
+        if (per1 > (uint32_t)kWave) {
+            double S1, C1;
+            mf2_sum_words(d1, sh.words[X], S1, C1);
+            S += S1;
+            C += C1;
+        }
+        if (lane == 0) {
+            sh.S[X] = S;
+            sh.C[X] = C;
+            lds_release(&sh.ready[X], e);
+        }
+    }
+}
+
+template <int OPT, int SCHEME>
+__global__ __launch_bounds__(kMFPThreads, 1) void kuramoto_mfp_kernel(MFArgs A)
+{
+    __shared__ MFPShared sh;
+    const uint32_t lane = threadIdx.x & (kWave - 1), wid = threadIdx.x / kWave;
+    if (threadIdx.x == 0) {
+        sh.ok = 1;
+        sh.local = 0;
+        sh.arrived[0] = sh.arrived[1] = 0u;
+        sh.ready[0] = sh.ready[1] = 0u;
+    }
+    // workgroup -> (pair p, slice w)
+    uint32_t p, w;
+    if (A.xcd_map) {
+        const uint32_t x = blockIdx.x & 7u, l = blockIdx.x >> 3, per = (A.R >> 1) >> 3;
+        p = x * per + l / A.G;
+        w = l % A.G;
+    } else {
+        p = blockIdx.x / A.G;
+        w = blockIdx.x % A.G;
+    }
+    const uint32_t rA = 2 * p;
+    const uint64_t n_epochs = (SCHEME == SDE_HEUN ? 2 : 1) * A.n_steps + 1;
+    __syncthreads();
+    if (wid == kMFWaves && A.G > 1) mf2_locality(A, rA, w, sh);
+    __syncthreads();
+    if (!sh.ok) return;
+    if (wid >= kMFWaves) {
+        // The exchanges are the critical path: their waves issue before the
+        // compute waves that share their SIMDs (those fill their waits with
+        // noise generation).
+        __builtin_amdgcn_s_setprio(3);
+        mfp_exchange_loop(A, (int)(wid - kMFWaves), rA + (wid - kMFWaves), w, n_epochs, sh);
+        return;
+    }
+
+    const uint32_t N = A.N;
+    float th[2][OPT], F1[2][OPT], sn[2][OPT], cs[2][OPT], om[OPT];
+    uint32_t idx[OPT];
+    bool live[OPT];
+#pragma unroll
+    for (int k = 0; k < OPT; ++k) {
+        idx[k] = (w * OPT + k) * kMFThreads + threadIdx.x;
+        live[k] = idx[k] < N;
+        const uint32_t i = live[k] ? idx[k] : 0u;
+        om[k] = live[k] ? A.omega[i] : 0.f;
+#pragma unroll
+        for (int X = 0; X < 2; ++X) {
+            if (A.init_from_state) {
+                th[X][k] = live[k] ? A.theta[(uint64_t)(rA + X) * N + i] : 0.f;
+            } else {
+                const U4 x = philox4x32_10(U4{0u, i, A.r_base + rA + X, (uint32_t)SDE_TAG_INIT}, A.key0, A.key1);
+                th[X][k] = (float)(x.x >> 8) * 0x1p-24f;
+            }
+        }
+    }
+    // Noise of the current block of 4 steps (g) and of the next (gn), the
+    // latter generated one (realization, oscillator) item at a time while a
+    // wave waits for sums; gn_done items are ready (wave-uniform).
+    float g[2][OPT][4], gn[2][OPT][4];
+    uint64_t gblk = ~0ull;
+    uint32_t gn_done = 0;
+    // (Selects rather than a branch per item: the compiler would merge the
+    // branches into one store at a computed index and move gn to scratch.)
+    auto prefetch1 = [&]() {
+        if (gblk == ~0ull || gn_done >= 2u * OPT) return;
+        const uint32_t nb = (uint32_t)(gblk + 1), Xs = gn_done / OPT, ks = gn_done % OPT;
+        uint32_t i = idx[0];
+#pragma unroll
+        for (int k = 1; k < OPT; ++k) i = (uint32_t)k == ks ? idx[k] : i;
+        float t[4];
+        gauss4_scaled(U4{nb, i, A.r_base + rA + Xs, (uint32_t)SDE_TAG_NOISE}, A.key0, A.key1, A.c2, t);
+#pragma unroll
+        for (int X = 0; X < 2; ++X)
+#pragma unroll
+            for (int k = 0; k < OPT; ++k) {
+                const bool mine = (uint32_t)(X * OPT + k) == gn_done;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) gn[X][k][q] = mine ? t[q] : gn[X][k][q];
+            }
+        ++gn_done;
+    };
+    // sin and cos of realization X's phases t[] (kept for the drift) and the
+    // wave's FP32 sums of them, handed to the exchange wave
+    auto partial = [&](int X, const float (&t)[OPT]) {
+        float s = 0.f, c = 0.f;
+#pragma unroll
+        for (int k = 0; k < OPT; ++k) {
+            sn[X][k] = live[k] ? sin_rev(t[k]) : 0.f;
+            cs[X][k] = live[k] ? cos_rev(t[k]) : 0.f;
+            s += sn[X][k];
+            c += cs[X][k];
+        }
+        s = wave_sum_dpp(s);
+        c = wave_sum_dpp(c);
+        if (lane == kWave - 1) {
+            sh.ps[X][wid] = s;
+            sh.pc[X][wid] = c;
+            __hip_atomic_fetch_add(&sh.arrived[X], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    };
+    // realization X's sums of epoch e, generating noise while they are not there
+    auto await = [&](int X, uint32_t e, double& Sd, double& Cd) -> bool {
+        if (lds_acquire(&sh.ready[X]) != e) {
+            prefetch1();
+            uint32_t spins = 0;
+            while (lds_acquire(&sh.ready[X]) != e) {
+                if (__hip_atomic_load(&sh.ok, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) == 0) return false;
+                __builtin_amdgcn_s_sleep(1);
+                if (++spins > A.spin_limit) {
+                    if (lane == 0) atomicOr(A.flag, 2);
+                    return false;
+                }
+            }
+        }
+        Sd = sh.S[X];
+        Cd = sh.C[X];
+        return true;
+    };
+
+#pragma unroll
+    for (int X = 0; X < 2; ++X) partial(X, th[X]);
+    uint32_t e = 1;
+    const double invN = 1.0 / (double)N;
+    uint64_t n = A.step0;
+    const uint64_t n_end = A.step0 + A.n_steps;
+    uint64_t local = 0;
+    bool ok = true;
+    for (;;) {
+        const bool last = n == n_end;
+        if (!last && (n >> 2) != gblk) {
+            const uint64_t b = n >> 2;
+            if (gblk != ~0ull && b == gblk + 1 && gn_done == 2u * OPT) {
+#pragma unroll
+                for (int X = 0; X < 2; ++X)
+#pragma unroll
+                    for (int k = 0; k < OPT; ++k)
+#pragma unroll
+                        for (int q = 0; q < 4; ++q) g[X][k][q] = gn[X][k][q];
+            } else {
+#pragma unroll
+                for (int X = 0; X < 2; ++X)
+#pragma unroll
+                    for (int k = 0; k < OPT; ++k)
+                        gauss4_scaled(U4{(uint32_t)b, idx[k], A.r_base + rA + X, (uint32_t)SDE_TAG_NOISE}, A.key0,
+                                      A.key1, A.c2, g[X][k]);
+            }
+            gblk = b;
+            gn_done = 0;
+        }
+        const uint32_t j = (uint32_t)n & 3u;
+        auto noise = [&](int X, int k) {
+            return j == 0 ? g[X][k][0] : j == 1 ? g[X][k][1] : j == 2 ? g[X][k][2] : g[X][k][3];
+        };
+        // stage 1 (the Euler-Maruyama step): sums at theta_n; every M steps r
+#pragma unroll
+        for (int X = 0; X < 2; ++X) {
+            double Sd, Cd;
+            if (ok && !await(X, e, Sd, Cd)) ok = false;
+            if (!ok) break;
+            if (A.r_samples && local % A.M == 0 && w == 0 && threadIdx.x == 0)
+                A.r_samples[(uint64_t)(rA + X) * A.n_samples + local / A.M] = std::sqrt(Sd * Sd + Cd * Cd) * invN;
+            if (last) continue;
+            const float S = (float)Sd, C = (float)Cd;
+            float tt[OPT];
+#pragma unroll
+            for (int k = 0; k < OPT; ++k) {
+                F1[X][k] = fmaf(A.kn, fmaf(cs[X][k], S, -sn[X][k] * C), om[k]);
+                tt[k] = fmaf(A.omega_scale, F1[X][k], th[X][k]) + noise(X, k);
+            }
+            if (SCHEME == SDE_HEUN) {
+                partial(X, tt);
+            } else {
+#pragma unroll
+                for (int k = 0; k < OPT; ++k) th[X][k] = tt[k] - floorf(tt[k]);
+                partial(X, th[X]);
+            }
+        }
+        if (!ok || last) break;
+        ++e;
+        if (SCHEME == SDE_HEUN) {
+            // stage 2: sums at the predictor
+#pragma unroll
+            for (int X = 0; X < 2; ++X) {
+                double S2d, C2d;
+                if (ok && !await(X, e, S2d, C2d)) ok = false;
+                if (!ok) break;
+                const float S2 = (float)S2d, C2 = (float)C2d;
+#pragma unroll
+                for (int k = 0; k < OPT; ++k) {
+                    const float F2 = fmaf(A.kn, fmaf(cs[X][k], S2, -sn[X][k] * C2), om[k]);
+                    const float t = fmaf(A.hdt2pi, F1[X][k] + F2, th[X][k]) + noise(X, k);
+                    th[X][k] = t - floorf(t);
+                }
+                partial(X, th[X]);
+            }
+            if (!ok) break;
+            ++e;
+        }
+        ++n;
+        ++local;
+    }
+    bool bad = false;
+#pragma unroll
+    for (int X = 0; X < 2; ++X)
+#pragma unroll
+        for (int k = 0; k < OPT; ++k) {
+            if (live[k]) {
+                A.theta[(uint64_t)(rA + X) * N + idx[k]] = th[X][k];
+                bad |= !isfinite(th[X][k]);
+            }
+        }
     if (__ballot(bad) != 0 && lane == 0) atomicOr(A.flag, 1);
 }
 
@@ -1005,6 +1352,9 @@ static int validate(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run
     if (!aligned(phi, 4) || !aligned(omega, 4) || !aligned(K, 16) || !aligned(r_samples, 8))
         return fail(ctx, SDE_ERR_INVALID, "misaligned device pointer");
     if ((uint64_t)d->N * d->R > (1ull << 40)) return fail(ctx, SDE_ERR_INVALID, "N * R too large");
+    if (d->coupling == SDE_MEANFIELD && d->n_steps >= (1ull << 31))
+        return fail(ctx, SDE_ERR_INVALID, "mean field: at most 2^31 - 1 steps per call (the exchange tags count "
+                    "stages in 32 bits); split the run, it resumes bit for bit");
     return SDE_OK;
 }
 
@@ -1023,6 +1373,12 @@ template <int OPT, int SCHEME>
 static void* mf_kernel_ptr()
 {
     return reinterpret_cast<void*>(kuramoto_mf_kernel<OPT, SCHEME>);
+}
+
+template <int OPT, int SCHEME>
+static void* mfp_kernel_ptr()
+{
+    return reinterpret_cast<void*>(kuramoto_mfp_kernel<OPT, SCHEME>);
 }
 
 // The streamed mean field: G workgroups per realization (as many as fit
@@ -1110,37 +1466,63 @@ static int ilog2_u64(uint64_t x)
 // groups, G a multiple of 8, the workgroups past the last oscillator
 // contributing zero sums), entry point, co-resident workgroups, and whether
 // a realization fits (at most one polling lane per exchange word).
+// The two-realization kernel (paired): the same lanes per realization and
+// slice, realizations taken two at a time (R even), a flat exchange of at
+// most 32 workgroups, OPT 2 or 4 (the registers of two realizations).
+constexpr int kMFShapes = 6;
+
 struct MFShape {
     int opt = 0;
+    bool paired = false;
     uint32_t G = 0;
     void* kern = nullptr;
+    uint32_t threads = 0;
     uint64_t capacity = 0;
     bool fits = false;
 };
 
-static int mf_shape(sde_ctx* ctx, uint32_t N, int opt, bool heun, MFShape* out)
+static int mf_shape(sde_ctx* ctx, uint32_t N, uint32_t R, int opt, bool paired, bool heun, MFShape* out)
 {
     uint64_t G64 = ((uint64_t)N + (uint64_t)kMFThreads * opt - 1) / ((uint64_t)kMFThreads * opt);
-    if (G64 > 16) G64 = (G64 + 7) / 8 * 8;
-    switch (opt) {
-    case 1: out->kern = heun ? mf_kernel_ptr<1, SDE_HEUN>() : mf_kernel_ptr<1, SDE_EULER>(); break;
-    case 2: out->kern = heun ? mf_kernel_ptr<2, SDE_HEUN>() : mf_kernel_ptr<2, SDE_EULER>(); break;
-    case 4: out->kern = heun ? mf_kernel_ptr<4, SDE_HEUN>() : mf_kernel_ptr<4, SDE_EULER>(); break;
-    default: out->kern = heun ? mf_kernel_ptr<8, SDE_HEUN>() : mf_kernel_ptr<8, SDE_EULER>(); break;
+    if (!paired && G64 > 16) G64 = (G64 + 7) / 8 * 8;
+    if (paired) {
+        switch (opt) {
+        case 2: out->kern = heun ? mfp_kernel_ptr<2, SDE_HEUN>() : mfp_kernel_ptr<2, SDE_EULER>(); break;
+        default: out->kern = heun ? mfp_kernel_ptr<4, SDE_HEUN>() : mfp_kernel_ptr<4, SDE_EULER>(); break;
+        }
+        out->threads = kMFPThreads;
+    } else {
+        switch (opt) {
+        case 1: out->kern = heun ? mf_kernel_ptr<1, SDE_HEUN>() : mf_kernel_ptr<1, SDE_EULER>(); break;
+        case 2: out->kern = heun ? mf_kernel_ptr<2, SDE_HEUN>() : mf_kernel_ptr<2, SDE_EULER>(); break;
+        case 4: out->kern = heun ? mf_kernel_ptr<4, SDE_HEUN>() : mf_kernel_ptr<4, SDE_EULER>(); break;
+        default: out->kern = heun ? mf_kernel_ptr<8, SDE_HEUN>() : mf_kernel_ptr<8, SDE_EULER>(); break;
+        }
+        out->threads = kMFThreads;
     }
     int per_cu = 0;
-    SDE_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, out->kern, kMFThreads, 0));
+    SDE_HIP(ctx, hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, out->kern, (int)out->threads, 0));
     out->opt = opt;
+    out->paired = paired;
     out->capacity = (uint64_t)std::max(per_cu, 0) * ctx->n_cu;
-    out->fits = G64 <= kMaxMFGroups && out->capacity >= G64;
+    out->fits = paired ? (R % 2 == 0 && (opt == 2 || opt == 4) && G64 <= kMaxMFPGroups && out->capacity >= G64)
+                       : (G64 <= kMaxMFGroups && out->capacity >= G64);
     out->G = (uint32_t)G64;
     return SDE_OK;
+}
+
+// Realizations per cooperative launch: as many as fit co-resident (pairs
+// for the paired kernel).
+static uint32_t mf_r_per_launch(const MFShape& sh, uint32_t R)
+{
+    const uint64_t units = sh.capacity / sh.G;
+    return (uint32_t)std::min<uint64_t>(R, sh.paired ? 2 * units : units);
 }
 
 // Exchange words one call at this shape needs (both parities, both levels).
 static size_t mf_slot_words(const MFShape& sh, uint32_t R, size_t* slot_words)
 {
-    const uint32_t r_per_launch = (uint32_t)std::min<uint64_t>(R, sh.capacity / sh.G);
+    const uint32_t r_per_launch = mf_r_per_launch(sh, R);
     *slot_words = (size_t)2 * r_per_launch * sh.G * kMFWordsPerGroup;
     return *slot_words + (size_t)2 * r_per_launch * 8 * kMFWordsPerGroup;
 }
@@ -1153,7 +1535,7 @@ static int mf_launch(sde_ctx* ctx, const MFShape& sh, const sde_kuramoto_desc* d
                      uint64_t* slots, hipStream_t stream)
 {
     const uint32_t G = sh.G;
-    const uint32_t r_per_launch = (uint32_t)std::min<uint64_t>(d->R, sh.capacity / G);
+    const uint32_t r_per_launch = mf_r_per_launch(sh, d->R);
     size_t slot_words = 0;
     const size_t n32 = 2 * mf_slot_words(sh, d->R, &slot_words);
     for (uint32_t r0 = 0; r0 < d->R; r0 += r_per_launch) {
@@ -1184,23 +1566,25 @@ static int mf_launch(sde_ctx* ctx, const MFShape& sh, const sde_kuramoto_desc* d
         A.kn = kc.kn;
         A.c2 = kc.c2;
         A.init_from_state = init_from_state;
-        A.xcd_map = (ctx->xcds == 8 && nr % 8 == 0) ? 1 : 0;
+        const uint32_t units = sh.paired ? nr / 2 : nr;  // realizations, or pairs of them
+        A.xcd_map = (ctx->xcds == 8 && units % 8 == 0) ? 1 : 0;
         A.xcd_local = ctx->kura_xcd_local;
         A.spin_limit = 1u << 26;
         A.r_base = r0;
         void* args[] = {&A};
-        SDE_HIP(ctx, hipLaunchCooperativeKernel(sh.kern, dim3(nr * G), dim3(kMFThreads), args, 0, stream));
+        SDE_HIP(ctx, hipLaunchCooperativeKernel(sh.kern, dim3(units * G), dim3(sh.threads), args, 0, stream));
     }
     return SDE_OK;
 }
 
-// Times every fitting shape on a 64-step run of the call's N and R (fresh
+// Times every candidate shape on a 64-step run of the call's N and R (fresh
 // phases from Philox into a scratch state, no samples, the NaN flag of the
-// trials) and returns the fastest; the default shape is kept unless another
-// is more than 3 % faster, so that timing noise does not move the choice.
+// trials) and returns the index of the fastest; the default shape is kept
+// unless another is more than 3 % faster, so that timing noise does not
+// move the choice.
 static int mf_tune(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, const KuraConsts& kc,
-                   const float* omega, const MFShape (&shapes)[4], int n_shapes, int def, uint64_t* slots,
-                   hipStream_t stream, int* best_opt)
+                   const float* omega, const MFShape* shapes, int n_shapes, int def, uint64_t* slots,
+                   hipStream_t stream, int* best)
 {
     void* scratch = nullptr;
     int st = ensure_ws(ctx, kSlotTune, (size_t)d->N * d->R * sizeof(float), &scratch);
@@ -1211,7 +1595,7 @@ static int mf_tune(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run,
         (void)hipEventDestroy(e0);
         return fail(ctx, SDE_ERR_DEVICE, "mean-field autotuner: hipEventCreate failed");
     }
-    float ms[4] = {};
+    float ms[kMFShapes] = {};
     for (int c = 0; c < n_shapes && st == SDE_OK; ++c) {
         for (int rep = 0; rep < 2 && st == SDE_OK; ++rep) {  // the first launch loads the code object
             if (hipEventRecord(e0, stream) != hipSuccess) st = SDE_ERR_DEVICE;
@@ -1227,12 +1611,14 @@ static int mf_tune(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run,
     (void)hipEventDestroy(e1);
     if (st == SDE_ERR_DEVICE) return fail(ctx, st, "mean-field autotuner: HIP event or launch failed");
     if (st) return st;
-    int best = def;
+    int b = def;
     for (int c = 0; c < n_shapes; ++c)
-        if (ms[c] < 0.97f * ms[best]) best = c;
-    *best_opt = shapes[best].opt;
+        if (ms[c] < 0.97f * ms[b]) b = c;
+    *best = b;
     return SDE_OK;
 }
+
+static int mf_code(const MFShape& s) { return s.opt | (s.paired ? 16 : 0); }
 
 static int run_meanfield(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run* run, float* phi,
                          const float* omega, double* r_samples, uint64_t n_samples, uint32_t M,
@@ -1240,60 +1626,72 @@ static int run_meanfield(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_run
 {
     const KuraConsts kc = kuramoto_consts(d);
     const bool heun = run->scheme == SDE_HEUN;
-    // the shapes at 1, 2, 4, 8 oscillators per lane (8 is the most the kernel
-    // holds in registers with its noise block, its prefetched next block and
-    // the sines and cosines kept for the drift); the default is the smallest
-    // that needs at most 16 workgroups per realization, else the largest
-    MFShape shapes[4];
+    // The candidates: one realization per workgroup at 1, 2, 4, 8 oscillators
+    // per lane (8 is the most the kernel holds in registers with its noise
+    // block, its prefetched next block and the sines and cosines kept for the
+    // drift), and two per workgroup at 2 or 4.  The default is the smallest
+    // one-realization count that needs at most 16 workgroups per
+    // realization, else the largest that fits.  The options restrict the set.
+    MFShape all[kMFShapes];
+    static const int kOpt[kMFShapes] = {1, 2, 4, 8, 2, 4};
     int n_fit = 0, def = -1;
-    MFShape fit[4];
-    for (int c = 0; c < 4; ++c) {
-        int st = mf_shape(ctx, d->N, 1 << c, heun, &shapes[c]);
+    MFShape fit[kMFShapes];
+    for (int c = 0; c < kMFShapes; ++c) {
+        const bool paired = c >= 4;
+        int st = mf_shape(ctx, d->N, d->R, kOpt[c], paired, heun, &all[c]);
         if (st) return st;
-        if (!shapes[c].fits) continue;
-        if (def < 0 && shapes[c].G <= 16) def = n_fit;
-        fit[n_fit++] = shapes[c];
+        if (!all[c].fits) continue;
+        if (ctx->kura_mf_opt && kOpt[c] != ctx->kura_mf_opt) continue;
+        if ((ctx->kura_mf_paired == 1 && paired) || (ctx->kura_mf_paired == 2 && !paired)) continue;
+        if (def < 0 && !paired && all[c].G <= 16) def = n_fit;
+        fit[n_fit++] = all[c];
     }
-    if (def < 0) def = n_fit - 1;
-    if (ctx->kura_mf == 1 || (ctx->kura_mf == 0 && n_fit == 0))
+    if (def < 0) {
+        for (int c = 0; c < n_fit; ++c)
+            if (!fit[c].paired) def = c;
+        if (def < 0) def = 0;
+    }
+    const bool forced = ctx->kura_mf_opt != 0 || ctx->kura_mf_paired != 0;
+    const bool any_fit = all[0].fits || all[1].fits || all[2].fits || all[3].fits;
+    if (ctx->kura_mf == 1 || (ctx->kura_mf == 0 && !any_fit))
         return run_meanfield_streamed(ctx, d, run, phi, omega, r_samples, n_samples, M, stream);
-    if (n_fit == 0)
+    if (!any_fit)
         return fail(ctx, SDE_ERR_UNSUPPORTED, "mean-field kernel: N = %u needs %u co-resident workgroups of %d "
-                    "lanes x 8 oscillators, the device holds %llu (at most %u per realization)", d->N, shapes[3].G,
-                    kMFThreads, (unsigned long long)shapes[3].capacity, kMaxMFGroups);
-    // exchange words for any of the fitting shapes
+                    "lanes x 8 oscillators, the device holds %llu (at most %u per realization)", d->N, all[3].G,
+                    kMFThreads, (unsigned long long)all[3].capacity, kMaxMFGroups);
+    if (n_fit == 0)
+        return fail(ctx, SDE_ERR_UNSUPPORTED, "mean-field kernel: N = %u, R = %u does not fit the forced shape (%d "
+                    "oscillators per lane, paired option %d)", d->N, d->R, ctx->kura_mf_opt, ctx->kura_mf_paired);
+    // exchange words for any of the candidates
     size_t words = 0, unused = 0;
     for (int c = 0; c < n_fit; ++c) words = std::max(words, mf_slot_words(fit[c], d->R, &unused));
     void* slots = nullptr;
     int st = ensure_ws(ctx, kSlotKuraPartials, words * sizeof(uint64_t), &slots);
     if (st) return st;
-    // oscillators per lane: forced, cached, or tuned on this call's shape class
-    int chosen = -1;
-    if (ctx->kura_mf_opt) {
-        for (int c = 0; c < n_fit; ++c)
-            if (fit[c].opt == ctx->kura_mf_opt) chosen = c;
-        if (chosen < 0)
-            return fail(ctx, SDE_ERR_UNSUPPORTED, "mean-field kernel: N = %u does not fit at %d oscillators per lane",
-                        d->N, ctx->kura_mf_opt);
-    } else {
+    // the shape: forced (the default of the restricted set), cached, or tuned
+    // on this call's shape class
+    int chosen = def;
+    if (!forced) {
         char key[160];
         snprintf(key, sizeof key, "meanfield|%s|N2^%d|R2^%d|%s|xcd%d", ctx->arch.c_str(), ilog2_u64(d->N),
                  ilog2_u64(d->R), heun ? "heun" : "euler", ctx->kura_xcd_local);
-        int opt = 0;
-        if (!tune_lookup(ctx, key, &opt) && ctx->autotune && n_fit > 1) {
+        int code = 0;
+        if (tune_lookup(ctx, key, &code)) {
+            for (int c = 0; c < n_fit; ++c)
+                if (mf_code(fit[c]) == code) chosen = c;  // else made for another N or R of the class: the default
+        } else if (ctx->autotune && n_fit > 1) {
             const auto t0 = std::chrono::steady_clock::now();
-            if ((st = mf_tune(ctx, d, run, kc, omega, fit, n_fit, def, static_cast<uint64_t*>(slots), stream, &opt)))
+            if ((st = mf_tune(ctx, d, run, kc, omega, fit, n_fit, def, static_cast<uint64_t*>(slots), stream,
+                              &chosen)))
                 return st;
             ctx->last.tuned = 1;
             ctx->last.tune_ms =
                 std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-            tune_store(ctx, key, opt);
+            tune_store(ctx, key, mf_code(fit[chosen]));
         }
-        for (int c = 0; c < n_fit; ++c)
-            if (fit[c].opt == opt) chosen = c;
-        if (chosen < 0) chosen = def;  // no choice yet, or one made for another N of the class that does not fit
     }
     ctx->last.kura_mf_opt = fit[chosen].opt;
+    ctx->last.kura_mf_paired = fit[chosen].paired ? 1 : 0;
     return mf_launch(ctx, fit[chosen], d, kc, run->seed, run->step0, d->n_steps, run->init == SDE_INIT_FROM_STATE,
                      phi, omega, r_samples, n_samples, M, ctx->flag, static_cast<uint64_t*>(slots), stream);
 }

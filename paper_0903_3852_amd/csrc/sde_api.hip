@@ -330,6 +330,10 @@ int sde_set_option(sde_ctx* ctx, int option, int64_t value)
         if (value != 0 && value != 1 && value != 2 && value != 4 && value != 8) break;
         ctx->kura_mf_opt = (int)value;
         return SDE_OK;
+    case SDE_OPT_KURA_MF_PAIRED:
+        if (value < 0 || value > 2) break;
+        ctx->kura_mf_paired = (int)value;
+        return SDE_OK;
     case SDE_OPT_DENSE_LAUNCH:
         if (value < 0 || value > 4) break;
         ctx->dense_launch = (int)value;

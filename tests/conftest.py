@@ -43,7 +43,7 @@ def _default_options(request):
         for opt, value in [(sde.SDE_OPT_AUTOTUNE, 1), (sde.SDE_OPT_GRAPHS, 1), (sde.SDE_OPT_JJ_PPT, 0),
                            (sde.SDE_OPT_KURA_MF, 0), (sde.SDE_OPT_KURA_JSPLIT, 0), (sde.SDE_OPT_KURA_TILE, 0),
                            (sde.SDE_OPT_KURA_XCD_LOCAL, 1), (sde.SDE_OPT_KURA_MF_OPT, 0),
-                           (sde.SDE_OPT_DENSE_LAUNCH, 0)]:
+                           (sde.SDE_OPT_DENSE_LAUNCH, 0), (sde.SDE_OPT_KURA_MF_PAIRED, 0)]:
             sde.sde_set_option(ctx, opt, value)
 
 

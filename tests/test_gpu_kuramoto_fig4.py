@@ -40,10 +40,12 @@ def _circ_err(theta_gpu, phi_ref):
 
 
 def _run(gpu, N, R, K, D, dt, n_steps, scheme=0, seed=1, omega=None, phi=None, step0=0, M=100, streamed=True,
-         samples=True, opt=0):
+         samples=True, opt=0, paired=0):
+    """paired: 0 as tuned, 1 one realization per workgroup, 2 two."""
     sde, ctx, dev = gpu
     sde.sde_set_option(ctx, sde.SDE_OPT_KURA_MF, 1 if streamed else 2)
     sde.sde_set_option(ctx, sde.SDE_OPT_KURA_MF_OPT, opt)
+    sde.sde_set_option(ctx, sde.SDE_OPT_KURA_MF_PAIRED, paired)
     om = omega if isinstance(omega, torch.Tensor) else torch.from_numpy(np.asarray(omega, dtype=np.float32)).to(dev)
     if phi is None:
         ph = torch.empty((R, N), dtype=torch.float32, device=dev)
@@ -59,6 +61,8 @@ def _run(gpu, N, R, K, D, dt, n_steps, scheme=0, seed=1, omega=None, phi=None, s
     assert st["mf_streamed"] == (1 if streamed else 0)
     if opt:
         assert st["kura_mf_opt"] == opt
+    if paired:
+        assert st["kura_mf_paired"] == paired - 1
     return ph, rs
 
 
@@ -87,7 +91,7 @@ def test_tree_exchange_vs_oracle(gpu, streamed, N):
     cfg = sde_inputs.kuramoto_uniform(N=N, R=R)
     for scheme in (0, 1):
         ph, rs = _run(gpu, N, R, cfg["K"], cfg["D"], cfg["dt"], 100, scheme, cfg["seed"], cfg["omega"],
-                      streamed=streamed, opt=0 if streamed else 8)
+                      streamed=streamed, opt=0 if streamed else 8, paired=0 if streamed else 1)
         ref, rref = oracle.kuramoto_integrate(N, R, cfg["K"], cfg["D"], cfg["dt"], 100, 100, oracle.MEANFIELD,
                                               scheme, cfg["seed"], cfg["omega"].astype(np.float64))
         err = _circ_err(ph.cpu().numpy(), ref)
@@ -109,7 +113,7 @@ def test_register_resident_lane_counts(gpu, N, opt):
     cfg = sde_inputs.kuramoto_uniform(N=N, R=R)
     for scheme in (0, 1):
         ph, rs = _run(gpu, N, R, cfg["K"], cfg["D"], cfg["dt"], 100, scheme, cfg["seed"], cfg["omega"],
-                      streamed=False, opt=opt)
+                      streamed=False, opt=opt, paired=1)
         ref, rref = oracle.kuramoto_integrate(N, R, cfg["K"], cfg["D"], cfg["dt"], 100, 100, oracle.MEANFIELD,
                                               scheme, cfg["seed"], cfg["omega"].astype(np.float64))
         err = _circ_err(ph.cpu().numpy(), ref)
@@ -133,12 +137,17 @@ def test_meanfield_tuner(gpu):
     a, ra = _run(gpu, *args, streamed=False)
     st2 = sde.sde_get_stats(ctx)
     assert st2["tuned"] == 0 and st2["kura_mf_opt"] == st1["kura_mf_opt"]
-    b, rb = _run(gpu, *args, streamed=False, opt=st1["kura_mf_opt"])
+    assert st2["kura_mf_paired"] == st1["kura_mf_paired"]
+    b, rb = _run(gpu, *args, streamed=False, opt=st1["kura_mf_opt"], paired=1 + st1["kura_mf_paired"])
     assert torch.equal(a, b) and torch.equal(ra, rb)
-    print(f"mean-field tuner: {st1['kura_mf_opt']} per lane for N {N}, R {R} ({st1['tune_ms']:.2f} ms)")
+    print(f"mean-field tuner: {st1['kura_mf_opt']} per lane, paired {st1['kura_mf_paired']} for N {N}, R {R} "
+          f"({st1['tune_ms']:.2f} ms)")
     for bad in (3, 16, -1):
         with pytest.raises(sde.SDEError):
             sde.sde_set_option(ctx, sde.SDE_OPT_KURA_MF_OPT, bad)
+    for bad in (3, -1):
+        with pytest.raises(sde.SDEError):
+            sde.sde_set_option(ctx, sde.SDE_OPT_KURA_MF_PAIRED, bad)
     # 2^18 oscillators at 1 per lane would need 512 workgroups per realization
     Nb = 1 << 18
     ph = torch.zeros((1, Nb), dtype=torch.float32, device=dev)
@@ -150,6 +159,53 @@ def test_meanfield_tuner(gpu):
         sde.sde_kuramoto_integrate(ctx, desc, sde.make_run(1, sync=1), ph, om, None, None)
     assert e.value.status == sde.SDE_ERR_UNSUPPORTED
     assert torch.count_nonzero(ph) == 0
+
+
+@pytest.mark.parametrize("N,opt,R", [(65536, 4, 4), (12289, 2, 2), (30001, 4, 6), (700, 2, 2), (20000, 2, 4)])
+def test_two_realizations_per_workgroup(gpu, N, opt, R):
+    """The kernel that holds two realizations per workgroup (and a ninth
+    wave for the exchanges), forced: N = 65536 at 4 per lane is 32
+    workgroups per realization (two polled words per lane), 20000 at 2 per
+    lane 20, 12289 and 30001 13 and 15 (ragged), 700 a single workgroup (no
+    exchange); R = 6 is three pairs.  Heun and Euler-Maruyama against the
+    oracle over 100 steps, as the one-realization kernel."""
+    cfg = sde_inputs.kuramoto_uniform(N=N, R=R)
+    for scheme in (0, 1):
+        ph, rs = _run(gpu, N, R, cfg["K"], cfg["D"], cfg["dt"], 100, scheme, cfg["seed"], cfg["omega"],
+                      streamed=False, opt=opt, paired=2)
+        ref, rref = oracle.kuramoto_integrate(N, R, cfg["K"], cfg["D"], cfg["dt"], 100, 100, oracle.MEANFIELD,
+                                              scheme, cfg["seed"], cfg["omega"].astype(np.float64))
+        err = _circ_err(ph.cpu().numpy(), ref)
+        print(f"two per workgroup, N {N}, {opt} per lane, R {R}, scheme {scheme}: max phase error {err.max():.2e}")
+        assert err.max() <= 1e-5
+        np.testing.assert_allclose(rs.cpu().numpy(), rref, rtol=0, atol=1e-6)
+
+
+def test_two_realizations_resume_and_limits(gpu):
+    """Two realizations per workgroup: a run split in two calls equals the
+    whole run bit for bit, a repeated run is identical, and an odd R or a
+    slice of more than 32 workgroups is refused when forced."""
+    sde, ctx, dev = gpu
+    N, R = 3000, 4
+    cfg = sde_inputs.kuramoto_uniform(N=N, R=R)
+    base = (N, R, cfg["K"], cfg["D"], cfg["dt"])
+    full, rf = _run(gpu, *base, 50, 0, 5, cfg["omega"], streamed=False, paired=2, samples=False)
+    again, _ = _run(gpu, *base, 50, 0, 5, cfg["omega"], streamed=False, paired=2, samples=False)
+    a, _ = _run(gpu, *base, 21, 0, 5, cfg["omega"], streamed=False, paired=2, samples=False)
+    b, _ = _run(gpu, *base, 29, 0, 5, cfg["omega"], phi=a, step0=21, streamed=False, paired=2, samples=False)
+    assert torch.equal(full, again) and torch.equal(full, b)
+    om = torch.zeros(N, dtype=torch.float32, device=dev)
+    for n_, r_, opt in [(N, 3, 0), (1 << 17, 2, 2)]:
+        ph = torch.zeros((r_, n_), dtype=torch.float32, device=dev)
+        om = torch.zeros(n_, dtype=torch.float32, device=dev)
+        sde.sde_set_option(ctx, sde.SDE_OPT_KURA_MF, 2)
+        sde.sde_set_option(ctx, sde.SDE_OPT_KURA_MF_OPT, opt)
+        sde.sde_set_option(ctx, sde.SDE_OPT_KURA_MF_PAIRED, 2)
+        desc = sde.sde_kuramoto_desc(n_, r_, 1.0, 0.1, 0.01, 10, sde.SDE_MEANFIELD, 0)
+        with pytest.raises(sde.SDEError) as e:
+            sde.sde_kuramoto_integrate(ctx, desc, sde.make_run(1, sync=1), ph, om, None, None)
+        assert e.value.status == sde.SDE_ERR_UNSUPPORTED
+        assert torch.count_nonzero(ph) == 0
 
 
 def test_streamed_matches_register_resident(gpu):
