@@ -335,7 +335,7 @@ SURR_VARIANTS = {
     # scan, training points, training schedule (epochs, learning rate) in order, Adam's state carried
     # from one stage to the next
     "batch": (sde_inputs.jj_random_params, SURR_CENTER, SURR_SCALE, 0, 200, 1000000, 100000, ((30, 1e-3),)),
-    "anm": (sde_inputs.jj_anm_params, ANM_CENTER, ANM_SCALE, 1, 100, 100000, 600000,
+    "anm": (sde_inputs.jj_anm_params, ANM_CENTER, ANM_SCALE, 1, 100, 100000, 1000000,
             ((150, 1e-3), (50, 3e-4), (50, 1e-4), (50, 3e-5))),
 }
 
@@ -349,7 +349,7 @@ def _surr_points(sde, P, paths, steps, potential=0, spp=200):
 def bench_surrogate(args, sde, torch, dev, variant="batch"):
     """The learned <v> surrogate: labels simulated by the integrator (512
     paths x 1e5 steps, half transient), 5 members of 5-256-256-256-1 trained
-    on the GPU (1e5 points x 30 epochs at lr 1e-3; for "anm" 6e5 points x 300
+    on the GPU (1e5 points x 30 epochs at lr 1e-3; for "anm" 1e6 points x 300
     epochs, the learning rate stepped 1e-3, 3e-4, 1e-4, 3e-5), and a scan
     that falls back to simulation where the members' spread exceeds 0.02.
     Reported: error against 4096 held-out points simulated at 4096 paths at
