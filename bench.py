@@ -30,17 +30,27 @@ sys.path.insert(0, ROOT)
 
 import sde_inputs  # noqa: E402
 
+_T0 = time.time()
+
+
+def progress(msg):
+    """A progress line on stderr (long legs print one at least every minute)."""
+    print(f"[{time.time() - _T0:7.1f} s] {msg}", file=sys.stderr, flush=True)
+
 # ---------------------------------------------------------------------------
 # ALU roofline.  Peak: the FP32 vector rate, 256 CUs x 4 SIMDs x 32 FP32 lanes
-# x 2.4 GHz = 7.86e13 lane-operations per second (157.3 TFLOP/s as FMAs).
-# gfx950 reaches it without packed instructions: a wave64 v_add_f32 /
-# v_fma_f32 / v_xor_b32 with VGPR or constant operands issues in 2 SIMD
-# cycles.  The same instruction with an SGPR operand, v_mad_u64_u32,
-# v_mul_hi_u32, conversions, floor and FP64 add/fma take 4 cycles, the
-# transcendentals (v_sin, v_cos, v_log, v_sqrt) 8 (bench.py --workload
-# valu_costs measures each form).  Algorithmic work is therefore counted in
-# units of one 2-cycle lane-operation: W_FULL = 1, W_HALF = 2, W_TRANS = 4,
-# each operation the method needs counted once in its cheapest form.
+# x 2.4 GHz = 7.86e13 lane-operations per second (157.3 TFLOP/s as FMAs), one
+# wave64 FP32 add / mul / fma or 32-bit integer operation per 2 SIMD cycles
+# without packed instructions.  The forms with an SGPR operand,
+# v_mad_u64_u32, v_mul_hi_u32, conversions, floor and FP64 add/fma run at half
+# that rate, the transcendentals (v_sin, v_cos, v_log, v_sqrt) at a quarter.
+# Algorithmic work is counted in units of the peak's lane-operation: W_FULL =
+# 1, W_HALF = 2, W_TRANS = 4, each operation the method needs counted once in
+# its cheapest form.  (--workload valu_costs times each form alone: streams of
+# one full-rate form take 2.9-3.8 cycles per instruction, the half-rate forms
+# 4.4-5.1, the transcendentals 8.3-8.4; a mixed stream issues faster, the
+# transcendentals overlapping other work, so the fractions are against the
+# published peak and do not flatter the kernels.)
 # ---------------------------------------------------------------------------
 PEAK_FMA_LANES = 256 * 4 * 32 * 2.4e9
 PEAK_MFMA_16BIT = 2.5e15           # dense bf16 / fp16 MFMA FLOP/s
@@ -383,10 +393,12 @@ def bench_surrogate(args, sde, torch, dev, variant="batch"):
     seed = sde_inputs.seed_of(5) + (0 if variant == "batch" else 1000)
     Ptr = gen(n_train, seed + 50)
     ytr, t_labels = simulate(Ptr, 512, 100000, seed + 51)
+    progress(f"surrogate {variant}: {n_train} training labels in {t_labels:.1f} s")
     Pho = gen(4096, seed + 60)
     yho, _ = simulate(Pho, 4096, 100000, seed + 61)
     Pva = gen(2048, seed + 65)  # validation set: picks the spread threshold
     yva, _ = simulate(Pva, 4096, 100000, seed + 66)
+    progress(f"surrogate {variant}: held-out and validation labels done")
 
     def feats(P):
         X = P.astype(np.float64).copy()
@@ -401,6 +413,7 @@ def bench_surrogate(args, sde, torch, dev, variant="batch"):
     for k, (epochs_k, lr_k) in enumerate(schedule):
         curve += list(sde.sde_surrogate_train(sur, Xtr, Ytr, sde.make_train_opts(epochs_k, 1024, lr=lr_k,
                                                                                  shuffle_seed=seed + 71 + k)))
+        progress(f"surrogate {variant}: training stage {k + 1}/{len(schedule)} ({epochs_k} epochs at lr {lr_k:g})")
     t_train = time.perf_counter() - t0
     # the spread threshold: the largest candidate whose validation error (scan
     # with fallback against 4096-path labels) is within 1e-2
@@ -445,6 +458,7 @@ def bench_surrogate(args, sde, torch, dev, variant="batch"):
     t_plain = t_plain_sub * n_query / 10000
     sde.sde_surrogate_destroy(sur)
     sde.sde_destroy(ctx)
+    progress(f"surrogate {variant}: scans done")
     return {"workload": "jj_surrogate" if variant == "batch" else "jj_surrogate_anm",
             "potential": "-sin(phi)" if potential == 0 else "sin(2 pi x)",
             "train_points": n_train, "label_budget": "512 paths x 1e5 steps",
@@ -948,7 +962,9 @@ def bench_sweep(args, sde, torch, dev):
 VALU_FORMS = ["v_add_f32 v,v", "v_add_f32 v,s", "v_fma_f32 v,v,v", "v_fma_f32 s,v,v", "v_mul_f32 v,v",
               "v_xor_b32 v,v", "v_xor_b32 v,s", "v_add_u32 v,v", "v_lshrrev_b32 8,v", "v_mad_u64_u32 v,s,v",
               "v_mul_hi_u32 v,v", "v_cvt_f32_u32", "v_floor_f32", "v_add_f64", "v_fma_f64", "v_cvt_f64_f32",
-              "v_sin_f32", "v_cos_f32", "v_log_f32", "v_sqrt_f32", "v_mov_b32_dpp row_shr", "v_mov_b32 v"]
+              "v_sin_f32", "v_cos_f32", "v_log_f32", "v_sqrt_f32", "v_mov_b32_dpp row_shr", "v_mov_b32 v",
+              "v_add_f32 v,const", "v_fma_f32 v,const,const", "v_mul_f32 const,v", "v_xor_b32 const,v",
+              "v_add_u32 const,v"]
 
 
 def bench_valu_costs(args):
@@ -1002,18 +1018,24 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload == "jj_scan":
         out = bench_jj(args, sde, torch, dev)
+        progress("jj_scan leg done")
         if not args.no_kuramoto:
-            out["kuramoto"] = [bench_kuramoto(w, args, sde, torch, dev)
-                               for w in ("kuramoto_mf", "kuramoto_mf_em", "kuramoto_tiled",
-                                         "kuramoto_dense_bf16x3", "kuramoto_dense_fp16x3", "kuramoto_dense_fp32")]
+            out["kuramoto"] = []
+            for w in ("kuramoto_mf", "kuramoto_mf_em", "kuramoto_tiled", "kuramoto_dense_bf16x3",
+                      "kuramoto_dense_fp16x3", "kuramoto_dense_fp32"):
+                out["kuramoto"].append(bench_kuramoto(w, args, sde, torch, dev))
+                progress(f"{w} leg done")
             jb = bench_jj_batch(args, sde, torch, dev)
             jb["tail_efficiency"] = jb["path_steps_per_s"] / (out["config"]["path_steps_per_step"] /
                                                             (out["kernel_ms"] / 1e3))
             out["jj_batch"] = jb
+            progress("jj_batch leg done")
             out["surrogate"] = bench_surrogate(args, sde, torch, dev)
             out["surrogate_anm"] = bench_surrogate(args, sde, torch, dev, variant="anm")
             out["fig2"] = bench_fig2(args, sde, torch, dev)
+            progress("jj_fig2 leg done")
             out["fig4"] = bench_fig4(args, sde, torch, dev)
+            progress("kuramoto_fig4 leg done")
     elif args.workload == "jj_batch":
         out = bench_jj_batch(args, sde, torch, dev)
     elif args.workload == "jj_surrogate":

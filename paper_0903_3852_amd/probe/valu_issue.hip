@@ -64,6 +64,13 @@ __global__ __launch_bounds__(256) void valu_issue_kernel(float* out, int iters, 
         if (MODE == 19) VP_CHAIN8(asm volatile("v_sqrt_f32 %0, %0" : "+v"(x[k])))
         if (MODE == 20) VP_CHAIN8(asm volatile("v_mov_b32_dpp %0, %1 row_shr:1 row_mask:0xf bank_mask:0xf" : "=v"(x[k]) : "v"(y[k])))
         if (MODE == 21) VP_CHAIN8(asm volatile("v_mov_b32 %0, %1" : "=v"(x[k]) : "v"(y[(k + 3) & 7])))
+        // the 2-cycle forms with one VGPR operand and inline constants (no
+        // second VGPR read, so no register-bank conflict between operands)
+        if (MODE == 22) VP_CHAIN8(asm volatile("v_add_f32 %0, 1.0, %0" : "+v"(x[k])))
+        if (MODE == 23) VP_CHAIN8(asm volatile("v_fma_f32 %0, %0, 0.5, 1.0" : "+v"(x[k])))
+        if (MODE == 24) VP_CHAIN8(asm volatile("v_mul_f32 %0, 0.5, %0" : "+v"(x[k])))
+        if (MODE == 25) VP_CHAIN8(asm volatile("v_xor_b32 %0, 63, %0" : "+v"(x[k])))
+        if (MODE == 26) VP_CHAIN8(asm volatile("v_add_u32 %0, 17, %0" : "+v"(x[k])))
     }
     float t = 0.f;
 #pragma unroll
@@ -99,7 +106,8 @@ typedef float (*TimeFn)(float*, int);
 const TimeFn kModes[] = {time_mode<0>,  time_mode<1>,  time_mode<2>,  time_mode<3>,  time_mode<4>,  time_mode<5>,
                          time_mode<6>,  time_mode<7>,  time_mode<8>,  time_mode<9>,  time_mode<10>, time_mode<11>,
                          time_mode<12>, time_mode<13>, time_mode<14>, time_mode<15>, time_mode<16>, time_mode<17>,
-                         time_mode<18>, time_mode<19>, time_mode<20>, time_mode<21>};
+                         time_mode<18>, time_mode<19>, time_mode<20>, time_mode<21>, time_mode<22>, time_mode<23>,
+                         time_mode<24>, time_mode<25>, time_mode<26>};
 
 }  // namespace
 
