@@ -138,6 +138,44 @@ JJ_VALU_COUNTERS = {"valu_instructions_per_path_step": 37.54, "transcendental_pe
                     "source": "profiles/jj_scan_valu_counters.md"}
 
 
+# VALU counters of the Kuramoto kernels, valid while the kernel's section of
+# kuramoto.hip (and device_common.h) is the one they were taken on.
+KURA_VALU_COUNTERS = {
+    "kuramoto_tiled": ({"valu_instructions_per_pair_term": 3.08, "transcendental_per_pair_term": 1.00,
+                        "valu_instructions_per_simd_cycle": 0.187,
+                        "source": "profiles/kuramoto_tiled_valu_counters.md"},
+                       ("-- TILED ------", "-- host --"), "83dae3dd99caa9a8ce16ff5666c8ea49485dd8f6"),
+    "kuramoto_mf": ({"valu_instructions_per_oscillator_stage": 30.8, "transcendental_per_oscillator_stage": 3.07,
+                     "valu_instructions_per_simd_cycle": 0.114, "source": "profiles/kuramoto_meanfield_counters.md"},
+                    ("-- MF ------", "-- MF, two realizations per workgroup --"),
+                    "bf6326f326184ca62fe6b4e410874b86ecb99729"),
+}
+
+
+def _section_sha1(path, first, last):
+    """SHA-1 of the lines of `path` from the one containing `first` to the
+    next one containing `last`."""
+    out, on = [], False
+    with open(path) as fh:
+        for line in fh.read().split("\n"):
+            if first in line:
+                on = True
+            if on:
+                out.append(line)
+            if on and last in line and first not in line:
+                break
+    return hashlib.sha1(("\n".join(out) + "\n").encode()).hexdigest()
+
+
+def kura_counters(name):
+    """The VALU counters of workload `name`'s kernel if its source is the one they were taken on."""
+    if name not in KURA_VALU_COUNTERS:
+        return None
+    rec, (first, last), sha = KURA_VALU_COUNTERS[name]
+    return rec if _section_sha1(os.path.join(ROOT, "paper_0903_3852_amd", "csrc", "kuramoto.hip"), first,
+                                last) == sha else None
+
+
 def _jj_source_sha1():
     h = hashlib.sha1()
     for f in ("jj.hip", "device_common.h"):
@@ -724,6 +762,9 @@ def bench_kuramoto(name, args, sde, torch, dev, steps=None, reps=1):
                            "frac": ops * osc_steps / t / PEAK_FMA_LANES, "traffic": None}
         rec["us_per_stage"] = t / (n * (2 if heun else 1)) * 1e6
         rec["oscillators_per_lane"] = st["kura_mf_opt"]
+        rec["two_realizations_per_workgroup"] = bool(st["kura_mf_paired"])
+        if heun and st["kura_mf_opt"] == 8 and not st["kura_mf_paired"]:
+            rec["roofline"]["counters"] = kura_counters("kuramoto_mf")
     elif spec["coupling"] == 1:
         pairs = float(N) * N * R * n * (2 if heun else 1)
         ops = W_FULL + W_TRANS + W_FULL
@@ -732,7 +773,7 @@ def bench_kuramoto(name, args, sde, torch, dev, steps=None, reps=1):
         rec["j_slices"] = st["kura_jsplit"]
         rec["roofline"] = {"bound": "alu", "achieved": ops * pairs / t / 1e12, "peak": PEAK_FMA_LANES / 1e12,
                            "unit": "T lane-op units/s", "frac": ops * pairs / t / PEAK_FMA_LANES,
-                           "traffic": None}
+                           "traffic": None, "counters": kura_counters("kuramoto_tiled")}
     else:
         rec["launch"] = {"waves": st["dense_waves"], "xcd_bands": st["dense_xcd_bands"]}
         gemm_flop = 2.0 * N * N * 2 * R * n * (2 if heun else 1)
