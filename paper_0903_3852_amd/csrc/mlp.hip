@@ -988,6 +988,7 @@ int sde_surrogate_train(sde_surrogate* s, const float* X, const float* y, uint64
                         float* loss_curve, void* hip_stream)
 {
     if (check_s(s)) return SDE_ERR_INVALID;
+    const TraceRange range("sde_surrogate_train");
     sde_ctx* ctx = s->ctx;
     ctx->last_error.clear();
     if (!X || !y || !o || n == 0 || o->epochs == 0 || o->batch == 0 || o->batch > n || n > 0xffffffffull)
@@ -1118,6 +1119,7 @@ static int predict_impl(sde_surrogate* s, const float* X, uint64_t n, float* mea
 int sde_surrogate_predict(sde_surrogate* s, const float* X, uint64_t n, float* mean, float* spread, void* hip_stream)
 {
     if (check_s(s)) return SDE_ERR_INVALID;
+    const TraceRange range("sde_surrogate_predict");
     s->ctx->last_error.clear();
     if (!X || !mean || !spread || n == 0 || (n + kInfMRows - 1) / kInfMRows > 0x7fffffffull)
         return fail(s->ctx, SDE_ERR_INVALID, "predict: bad arguments");
@@ -1130,6 +1132,7 @@ int sde_surrogate_scan(sde_surrogate* s, const sde_jj_point* q, uint64_t n, floa
                        double* v_out, uint8_t* used, sde_scan_stats* stats, void* hip_stream)
 {
     if (check_s(s)) return SDE_ERR_INVALID;
+    const TraceRange range("sde_surrogate_scan");
     sde_ctx* ctx = s->ctx;
     ctx->last_error.clear();
     if (!q || n == 0 || !fb || !v_out || !(spread_max >= 0) || s->widths[0] != 5)

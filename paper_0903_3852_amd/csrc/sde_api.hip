@@ -387,6 +387,7 @@ int sde_jj_integrate(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, cons
                      void* hip_stream)
 {
     if (!ctx) return SDE_ERR_INVALID;
+    const TraceRange range("sde_jj_integrate");
     ctx->last_error.clear();
     try {
         return jj_integrate_impl(ctx, pts, n_pts, run, theta, winding, v, acc, point_sums,
@@ -401,6 +402,7 @@ int sde_jj_integrate_noalloc(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_p
                              void* hip_stream)
 {
     if (!ctx) return SDE_ERR_INVALID;
+    const TraceRange range("sde_jj_integrate_noalloc");
     ctx->last_error.clear();
     try {
         return jj_integrate_noalloc_impl(ctx, pts, n_pts, run, theta, winding, v, acc, point_sums,
@@ -415,6 +417,7 @@ int sde_jj_integrate_f64(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_pts, 
                          void* hip_stream)
 {
     if (!ctx) return SDE_ERR_INVALID;
+    const TraceRange range("sde_jj_integrate_f64");
     ctx->last_error.clear();
     try {
         return jj_integrate_f64_impl(ctx, pts, n_pts, run, theta, winding, v, acc, point_sums,
@@ -429,6 +432,7 @@ int sde_jj_integrate_recorded(sde_ctx* ctx, const sde_jj_point* pts, uint32_t n_
                               uint32_t record_every, uint64_t n_rows, int32_t* rec_winding, void* hip_stream)
 {
     if (!ctx) return SDE_ERR_INVALID;
+    const TraceRange range("sde_jj_integrate_recorded");
     ctx->last_error.clear();
     try {
         return jj_integrate_recorded_impl(ctx, pts, n_pts, run, theta, winding, v, acc, point_sums, record_every,
@@ -443,6 +447,7 @@ int sde_kuramoto_integrate(sde_ctx* ctx, const sde_kuramoto_desc* desc, const sd
                            void* hip_stream)
 {
     if (!ctx) return SDE_ERR_INVALID;
+    const TraceRange range("sde_kuramoto_integrate");
     ctx->last_error.clear();
     try {
         return kuramoto_impl(ctx, desc, run, phi, omega, K, r_samples,
@@ -456,6 +461,7 @@ int sde_observables(sde_ctx* ctx, int kind, const void* dev_in, const uint32_t* 
                     uint32_t n_groups, double* host_out, void* hip_stream)
 {
     if (!ctx) return SDE_ERR_INVALID;
+    const TraceRange range("sde_observables");
     ctx->last_error.clear();
     try {
         return observables_impl(ctx, kind, dev_in, counts, n_groups, host_out,
@@ -469,6 +475,7 @@ int sde_position_histogram(sde_ctx* ctx, const int32_t* winding, uint64_t n, int
                            uint64_t* counts, void* hip_stream)
 {
     if (!ctx) return SDE_ERR_INVALID;
+    const TraceRange range("sde_position_histogram");
     ctx->last_error.clear();
     return histogram_impl(ctx, winding, n, n, 1, x0, n_bins, counts, static_cast<hipStream_t>(hip_stream));
 }
@@ -477,6 +484,7 @@ int sde_position_histograms(sde_ctx* ctx, const int32_t* winding, uint64_t n, ui
                             int64_t x0, uint32_t n_bins, uint64_t* counts, void* hip_stream)
 {
     if (!ctx) return SDE_ERR_INVALID;
+    const TraceRange range("sde_position_histograms");
     ctx->last_error.clear();
     return histogram_impl(ctx, winding, n, pitch, n_rows, x0, n_bins, counts, static_cast<hipStream_t>(hip_stream));
 }
@@ -485,6 +493,7 @@ int sde_phase_histograms(sde_ctx* ctx, const float* theta, uint64_t n, uint64_t 
                          uint32_t n_bins, uint64_t* counts, void* hip_stream)
 {
     if (!ctx) return SDE_ERR_INVALID;
+    const TraceRange range("sde_phase_histograms");
     ctx->last_error.clear();
     return phase_histogram_impl(ctx, theta, n, pitch, n_rows, n_bins, counts, static_cast<hipStream_t>(hip_stream));
 }

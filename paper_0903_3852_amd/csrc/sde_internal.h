@@ -3,6 +3,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <rocprofiler-sdk-roctx/roctx.h>
 
 #include <cstdarg>
 #include <cstdint>
@@ -101,6 +102,15 @@ enum Slot {
     kSlotMisc = 10,
     kSlotStep = 11,
     kSlotTune = 12,
+};
+
+// A roctx range around one C-ABI call (shown by rocprofv3 --marker-trace;
+// a cheap no-op when no tool is attached).
+struct TraceRange {
+    explicit TraceRange(const char* name) { roctxRangePushA(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange&) = delete;
+    TraceRange& operator=(const TraceRange&) = delete;
 };
 
 // Status helpers -----------------------------------------------------------
