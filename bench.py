@@ -58,8 +58,9 @@ PEAK_MFMA_FP32 = 157.3e12          # FP32 MFMA FLOP/s
 W_FULL = 1.0
 W_HALF = 2.0
 W_TRANS = 4.0
-# Philox4x32-10 per block of four steps: 10 rounds x (2 v_mad_u64_u32 + 4 xor).
-PHILOX_BLOCK = 10 * (2 * W_HALF + 4 * W_FULL)
+# Philox4x32-10 per block of four steps: 10 rounds x (2 wide products, each a
+# half-rate v_mad_u64_u32, and 2 three-way xors, each one v_bitop3_b32).
+PHILOX_BLOCK = 10 * (2 * W_HALF + 2 * W_FULL)
 # Box-Muller per pair of Gaussians: u1 = shift, add, convert, scale; u2 =
 # shift, convert, scale; log2, times c2, sqrt; cos, sin and two products.
 BOX_MULLER_PAIR = (3 * W_FULL + W_HALF) + (2 * W_FULL + W_HALF) + (2 * W_TRANS + W_FULL) + (2 * W_TRANS + 2 * W_FULL)
@@ -76,8 +77,8 @@ def jj_ops_per_path_step():
 
 def jj_valu_instr_per_path_step():
     """VALU instructions per path-step the method needs (a transcendental
-    counts 1): Philox 15, Box-Muller 7, Heun 15, wrap 1."""
-    return 60 / 4 + 14 / 2 + 15 + 4 / 4
+    counts 1): Philox 10, Box-Muller 7, Heun 15, wrap 1."""
+    return 40 / 4 + 14 / 2 + 15 + 4 / 4
 
 
 def jj_flops_per_path_step():
@@ -131,30 +132,29 @@ def _source_sha1(*files):
 # (FETCH_SIZE x 2.00 + WRITE_SIZE x 1.00, copy-calibrated), and its VALU
 # counters per path-step, from profiles/jj_scan_valu_counters.md.  Only valid
 # for the kernel source they were measured on.
-JJ_TRAFFIC_BYTES = (2 * 4267.56 + 6933.09) * 1024
-JJ_TRAFFIC_SOURCE_SHA1 = "9fefda8393829f33a889aab136f3f716b7f9e050"
-JJ_VALU_COUNTERS = {"valu_instructions_per_path_step": 37.54, "transcendental_per_path_step": 4.00,
-                    "salu_instructions_per_path_step": 8.08, "valu_instructions_per_simd_cycle": 0.269,
+JJ_TRAFFIC_BYTES = (2 * 3547.2 + 6612.1) * 1024
+JJ_TRAFFIC_SOURCE_SHA1 = "ca5065025955cec058718be06875fb2e71ce5666"
+JJ_VALU_COUNTERS = {"valu_instructions_per_path_step": 34.28, "transcendental_per_path_step": 4.00,
+                    "salu_instructions_per_path_step": 8.08, "valu_instructions_per_simd_cycle": 0.262,
                     "source": "profiles/jj_scan_valu_counters.md"}
 
 
 # VALU counters of the Kuramoto kernels, valid while the kernel's section of
-# kuramoto.hip (and device_common.h) is the one they were taken on.
+# kuramoto.hip and device_common.h are the ones they were taken on.
 KURA_VALU_COUNTERS = {
     "kuramoto_tiled": ({"valu_instructions_per_pair_term": 3.08, "transcendental_per_pair_term": 1.00,
                         "valu_instructions_per_simd_cycle": 0.187,
                         "source": "profiles/kuramoto_tiled_valu_counters.md"},
-                       ("-- TILED ------", "-- host --"), "83dae3dd99caa9a8ce16ff5666c8ea49485dd8f6"),
-    "kuramoto_mf": ({"valu_instructions_per_oscillator_stage": 30.8, "transcendental_per_oscillator_stage": 3.07,
-                     "valu_instructions_per_simd_cycle": 0.114, "source": "profiles/kuramoto_meanfield_counters.md"},
-                    ("-- MF ------", "-- MF, two realizations per workgroup --"),
-                    "bf6326f326184ca62fe6b4e410874b86ecb99729"),
+                       ("-- TILED ------", "-- host --"), "99154c35b9150737c63b10052e2fb4d746117639"),
+    "kuramoto_mf": ({"valu_instructions_per_oscillator_stage": 29.1, "transcendental_per_oscillator_stage": 3.07,
+                     "valu_instructions_per_simd_cycle": 0.108, "source": "profiles/kuramoto_meanfield_counters.md"},
+                    ("-- MF ------", "-- MF, two realizations per workgroup --"), "fddd8c97c34c8a31a73975c59e0ff3a61eb17c25"),
 }
 
 
 def _section_sha1(path, first, last):
     """SHA-1 of the lines of `path` from the one containing `first` to the
-    next one containing `last`."""
+    next one containing `last`, followed by device_common.h."""
     out, on = [], False
     with open(path) as fh:
         for line in fh.read().split("\n"):
@@ -164,7 +164,10 @@ def _section_sha1(path, first, last):
                 out.append(line)
             if on and last in line and first not in line:
                 break
-    return hashlib.sha1(("\n".join(out) + "\n").encode()).hexdigest()
+    h = hashlib.sha1(("\n".join(out) + "\n").encode())
+    with open(os.path.join(ROOT, "paper_0903_3852_amd", "csrc", "device_common.h"), "rb") as fh:
+        h.update(fh.read())
+    return h.hexdigest()
 
 
 def kura_counters(name):

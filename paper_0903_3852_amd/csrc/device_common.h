@@ -17,29 +17,52 @@ constexpr int kWave = 64;  // CDNA wavefront width
 // words 1 and 3 and the round key; the key advances by two Weyl constants.
 // Counter words that are wave-uniform (step block, point, tag) keep their
 // early rounds on the scalar unit: the compiler's uniformity analysis places
-// them in SGPRs, so round 1 costs no VALU multiply at all.
+// them in SGPRs, so round 1 costs no VALU multiply at all.  Once the words
+// are per-lane (when only counter word 1 varies across the wave, as in every
+// stream here: output word 0 from the fourth round, word 2 from the fifth),
+// each three-way xor is one v_bitop3_b32 (truth table 0x96) instead of two
+// v_xor_b32; earlier rounds keep the plain xors so that their uniform parts
+// can stay scalar.
 // --------------------------------------------------------------------------
 struct U4 {
     uint32_t x, y, z, w;
 };
 
+template <int R>
+__device__ __forceinline__ uint32_t philox_xor3(uint32_t a, uint32_t b, uint32_t k)
+{
+    if constexpr (R >= 3)
+        return __builtin_amdgcn_bitop3_b32(a, b, k, 0x96);
+    else
+        return a ^ b ^ k;
+}
+
+template <int R>
+__device__ __forceinline__ void philox_round(U4& c, uint32_t k0, uint32_t k1)
+{
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
+    U4 n;
+    n.x = philox_xor3<R>((uint32_t)(p1 >> 32), c.y, k0);
+    n.y = (uint32_t)p1;
+    n.z = philox_xor3<R - 1>((uint32_t)(p0 >> 32), c.w, k1);  // word 3 stays uniform one round longer
+    n.w = (uint32_t)p0;
+    c = n;
+}
+
 __device__ __forceinline__ U4 philox4x32_10(U4 c, uint32_t k0, uint32_t k1)
 {
-#pragma unroll
-    for (int r = 0; r < 10; ++r) {
-        if (r) {
-            k0 += 0x9E3779B9u;
-            k1 += 0xBB67AE85u;
-        }
-        const uint64_t p0 = (uint64_t)0xD2511F53u * c.x;
-        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c.z;
-        U4 n;
-        n.x = (uint32_t)(p1 >> 32) ^ c.y ^ k0;
-        n.y = (uint32_t)p1;
-        n.z = (uint32_t)(p0 >> 32) ^ c.w ^ k1;
-        n.w = (uint32_t)p0;
-        c = n;
-    }
+    constexpr uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
+    philox_round<0>(c, k0, k1);
+    philox_round<1>(c, k0 + W0, k1 + W1);
+    philox_round<2>(c, k0 + 2 * W0, k1 + 2 * W1);
+    philox_round<3>(c, k0 + 3 * W0, k1 + 3 * W1);
+    philox_round<4>(c, k0 + 4 * W0, k1 + 4 * W1);
+    philox_round<5>(c, k0 + 5 * W0, k1 + 5 * W1);
+    philox_round<6>(c, k0 + 6 * W0, k1 + 6 * W1);
+    philox_round<7>(c, k0 + 7 * W0, k1 + 7 * W1);
+    philox_round<8>(c, k0 + 8 * W0, k1 + 8 * W1);
+    philox_round<9>(c, k0 + 9 * W0, k1 + 9 * W1);
     return c;
 }
 
