@@ -1028,7 +1028,46 @@ def bench_valu_costs(args):
             raise RuntimeError(f"valu probe mode {mode} failed")
         instr = 2048 * 4.0 * iters * 8.0
         out[name] = round(1024 * 2.4e9 * ms.value * 1e-3 / instr, 3)
-    return {"workload": "valu_costs", "unit": "SIMD cycles per wave64 instruction", "cycles": out}
+    # Sustained matrix-core rate of the MFMA forms of the dense coupling, at
+    # 1, 2 and 8 waves per SIMD (256, 512, 2048 workgroups of 4 waves), in
+    # TFLOP/s and in SIMD cycles per MFMA at 2.4 GHz
+    lib.mfma_rate_time.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_float)]
+    lib.mfma_rate_time.restype = ctypes.c_int
+    mfma = {}
+    for form, (name, flop, peak) in enumerate([("v_mfma_f32_16x16x32_bf16", 16384, PEAK_MFMA_16BIT),
+                                               ("v_mfma_f32_16x16x32_f16", 16384, PEAK_MFMA_16BIT),
+                                               ("v_mfma_f32_16x16x4_f32", 2048, PEAK_MFMA_FP32)]):
+        rows = {}
+        for waves, blocks in ((1, 256), (2, 512), (8, 2048)):
+            it = 4000 if form < 2 else 8000
+            ms = ctypes.c_float()
+            if lib.mfma_rate_time(form, blocks, it, ctypes.byref(ms)) != 0:
+                raise RuntimeError(f"mfma probe form {form} failed")
+            n = blocks * 4.0 * it * 8.0
+            rate = n * flop / (ms.value * 1e-3)
+            rows[f"{waves}_waves_per_simd"] = {"tflops": round(rate / 1e12, 1), "frac_of_peak": round(rate / peak, 3),
+                                               "cycles_per_mfma": round(1024 * 2.4e9 * ms.value * 1e-3 / n, 2)}
+        mfma[name] = rows
+    # The same bf16 MFMA fed from memory as the dense coupling feeds it: per 96
+    # MFMAs a wave loads 24 (16, 8) 1 KB fragments one iteration ahead, 2 waves
+    # per SIMD, from a 2 MiB (L2-resident) or 1 GiB buffer
+    lib.mfma_feed_time.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_longlong,
+                                   ctypes.POINTER(ctypes.c_float)]
+    lib.mfma_feed_time.restype = ctypes.c_int
+    feed = {}
+    for loads in (24, 16, 8):
+        for label, nbytes in (("l2", 2 << 20), ("hbm", 1 << 30)):
+            it, blocks = 1000, 256
+            ms = ctypes.c_float()
+            if lib.mfma_feed_time(loads, blocks, it, nbytes, ctypes.byref(ms)) != 0:
+                raise RuntimeError(f"mfma feed probe ({loads} loads) failed")
+            t = ms.value * 1e-3
+            n = blocks * 8.0 * it * 96
+            feed[f"{loads}_loads_per_96_mfma_{label}"] = {
+                "tflops": round(n * 16384 / t / 1e12, 1), "frac_of_peak": round(n * 16384 / t / PEAK_MFMA_16BIT, 3),
+                "bytes_per_clk_per_cu": round(blocks * 8.0 * it * loads * 1024 / t / 256 / 2.4e9, 1)}
+    return {"workload": "valu_costs", "unit": "SIMD cycles per wave64 instruction", "cycles": out,
+            "mfma_rate": mfma, "mfma_fed_from_memory": feed}
 
 
 def main():

@@ -91,7 +91,9 @@ const char* sde_strerror(int status);
 /* Text describing the last failing call on `ctx` ("" if none). */
 const char* sde_last_error(const sde_ctx* ctx);
 /* Synchronizes the context's device and reports SDE_ERR_NUMERIC if any
- * integration since the last check produced a NaN/Inf state. */
+ * integration since the last check produced a NaN/Inf state, SDE_ERR_DEVICE
+ * if a bounded wait inside a kernel (between the workgroups of a mean-field
+ * realization, or the waves of a two-half dense workgroup) timed out. */
 int sde_check(sde_ctx* ctx);
 
 /* ---- run options shared by both models ----------------------------------- */
@@ -441,9 +443,12 @@ enum {
     SDE_OPT_DENSE_LAUNCH = 9, /* dense coupling launch: 0 (default) = tuned per shape */
                           /* class; 1 = 8 waves per workgroup splitting the k loop, */
                           /* row tiles dealt to XCDs in bands; 2 = 4 waves, bands;  */
-                          /* 3 = 8 waves, plain order; 4 = 4 waves, plain order     */
-                          /* (FP32 always runs 4 waves; bands apply when the row    */
-                          /* tiles split evenly over the 8 XCDs)                    */
+                          /* 3 = 8 waves, plain order; 4 = 4 waves, plain order;    */
+                          /* 5 = two workgroups per 128 x 128 tile over the two     */
+                          /* halves of k (16-bit products, an even number of        */
+                          /* 32-realization tiles; else as 1), bands; 6 = the same, */
+                          /* plain order (FP32 always runs 4 waves; bands apply     */
+                          /* when the row tiles split evenly over the 8 XCDs)       */
     SDE_OPT_KURA_MF_PAIRED = 10 /* register-resident mean field realizations per    */
                           /* workgroup: 0 (default) = tuned per shape class; 1 =    */
                           /* one; 2 = two (R even, 2 or 4 oscillators per lane, at  */
@@ -479,7 +484,8 @@ typedef struct {
     int32_t dense_xcd_bands; /* its row tiles were dealt to XCDs in bands (1)         */
     int32_t kura_mf_paired;  /* the last register-resident mean-field call held two   */
                              /* realizations per workgroup (1)                        */
-    int32_t reserved;
+    int32_t dense_k_halves;  /* workgroups per output tile of the last dense call      */
+                             /* (2: the two halves of k, then a stage kernel)         */
 } sde_stats;
 /* Statistics of the last integration call on `ctx`. */
 int sde_get_stats(const sde_ctx* ctx, sde_stats* out);

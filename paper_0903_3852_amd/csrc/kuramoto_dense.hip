@@ -81,6 +81,7 @@ struct DenseArgs {
     int32_t stage;         // 1 predictor (or Euler step), 2 corrector
     int32_t euler;
     int32_t band;          // deal row tiles to XCDs in contiguous bands (when they split evenly)
+    int* flag;             // error flag (a wave pairing that timed out in the two-half kernel)
 };
 
 __device__ __forceinline__ uint32_t bcol(uint32_t r, uint32_t kind)
@@ -473,6 +474,229 @@ __global__ __launch_bounds__(NW * 64, 1) void dense_mfma_kernel(DenseArgs A)
     dense_tile_store<T, V, kThreads>(A, mt, nt, tS, tC);
 }
 
+// ------------------------------------------- split MFMA, two K halves --
+// The same product with twice the tile per workgroup, to halve what each
+// CU loads per MFMA: a workgroup computes a 128-row x 64-realization tile (two
+// realization tiles) over one half of the k range, so two workgroups share
+// each tile and a second kernel adds their partial tiles (in half order)
+// and runs the stage update.  Eight waves: wave w computes the 128 x 64
+// tile of column half c = w & 1 over every fourth k block (slice s = w >> 1)
+// of its half.  The two waves of a slice need the same K fragments: each
+// loads its four row blocks (hi and lo) straight into LDS
+// (global_load_lds_dwordx4, no VGPRs), double-buffered, and reads all eight
+// from there row block by row block as its MFMAs go; its own B fragments
+// come from global memory into a second register set.  Both loads of block
+// j + 1 are issued as block j starts, a whole block of MFMAs ahead.  Per
+// block a CU then loads 16 KB per wave against 24 KB in the one-half
+// kernel.  The waves of a slice pace each other through an LDS counter of
+// blocks published, never a workgroup barrier: a wave publishes block j once
+// its own loads of it have landed and its reads of block j - 1 are done, so
+// a partner that has seen block j published may refill the buffer of j - 1.
+constexpr int kSplit2Waves = 8;
+// s_waitcnt immediate (gfx9 encoding) waiting for LDS and scalar memory only:
+// lgkmcnt(0) with vmcnt and expcnt at their maxima
+constexpr int kWaitLdsOnly = (3 << 14) | (0 << 8) | (7 << 4) | 0xF;
+constexpr int kSplit2StageThreads = 512;  // the stage kernel: 8 waves, 4 partial fragments each
+
+// Partial tiles: [half][row tile][realization tile][row block 8][column
+// block 4][lane] of f32x4, each (row block, column block) the accumulator of
+// one MFMA output block as a wave holds it.
+__device__ __forceinline__ uint64_t split2_part(uint32_t h, uint32_t mt, uint32_t nt, uint32_t n_mt, uint32_t n_nt)
+{
+    return (((uint64_t)h * n_mt + mt) * n_nt + nt) * (32 * kWave);
+}
+
+__device__ __forceinline__ uint32_t lds_acquire_u32(const uint32_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+template <typename T, typename V>
+__global__ __launch_bounds__(kSplit2Waves * 64, 1) void dense_split2_kernel(DenseArgs A, f32x4* P)
+{
+    // K fragments by slice, buffer and fragment (row block m: hi at 2m, lo
+    // at 2m + 1); after the k loop the same memory holds the slice partials.
+    __shared__ V xa[4][2][16][kWave];
+    __shared__ uint32_t pub[4][2];
+    f32x4 (*red)[32][kWave] = reinterpret_cast<f32x4 (*)[32][kWave]>(&xa[0][0][0][0]);
+    static_assert(sizeof(xa) >= 4 * 32 * kWave * sizeof(f32x4), "the slice partials fit in the fragment buffers");
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63u;
+    const uint32_t c = wave & 1u, s = wave >> 1;
+    if (threadIdx.x < 8) (&pub[0][0])[threadIdx.x] = 0u;
+    __syncthreads();
+    // workgroup -> (row tile mt, tile pair pt, k half h)
+    const uint32_t n_mt = A.Mp / kRowTile, n_nt = A.Rp / kRealTile, n_pt = n_nt / 2;
+    uint32_t mt, pt, h;
+    {
+        const uint32_t b = blockIdx.x;
+        uint32_t l;
+        if (A.band && n_mt % 8 == 0) {
+            mt = (b & 7u) * (n_mt / 8);
+            l = b >> 3;
+            mt += l / (2 * n_pt);
+        } else {
+            mt = b / (2 * n_pt);
+            l = b;
+        }
+        const uint32_t rem = l % (2 * n_pt);
+        pt = rem >> 1;
+        h = rem & 1u;
+    }
+    const uint32_t nt = 2 * pt + c;
+    const uint32_t KB = A.Np / kKStep, KBh = (KB + 1) / 2;
+    const uint32_t kb0 = h * KBh, kb1 = min(KB, kb0 + KBh);
+    const uint32_t first = kb0 + s;
+    const uint32_t n_j = first < kb1 ? (kb1 - first + 3) / 4 : 0u;
+    const uint64_t frag = 2 * 64 * 8;              // elements per k block (hi + lo)
+    const uint64_t stream = (uint64_t)KB * frag;  // elements per 16-row block
+    const T* pa = static_cast<const T*>(A.K) + (uint64_t)(mt * 8) * stream;
+    const T* pb = static_cast<const T*>(A.B) + (uint64_t)(nt * 4) * stream + lane * 8;
+
+    f32x4 acc[8][4];
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    V bh[2][4], bl[2][4];  // B of the current block and of the next, by block parity
+    // this wave's four row blocks (hi and lo) of block j into buffer j & 1
+    auto load_a = [&](uint32_t j) {
+        const uint64_t o = (uint64_t)(first + 4 * j) * frag;
+#pragma unroll
+        for (int mm = 0; mm < 4; ++mm) {
+            const uint32_t m = 4 * c + mm;
+#pragma unroll
+            for (int lo = 0; lo < 2; ++lo)
+                __builtin_amdgcn_global_load_lds(
+                    static_cast<const void*>(pa + m * stream + o + lo * kFragLo + lane * 8),
+                    (void __attribute__((address_space(3)))*)&xa[s][j & 1u][2 * m + lo][0], 16, 0, 0);
+        }
+    };
+    auto load_b = [&](uint32_t j, V* dh, V* dl) {
+        const uint64_t o = (uint64_t)(first + 4 * j) * frag;
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            dh[n] = *reinterpret_cast<const V*>(pb + n * stream + o);
+            dl[n] = *reinterpret_cast<const V*>(pb + n * stream + o + kFragLo);
+        }
+    };
+    auto spin_until = [&](const uint32_t* p, uint32_t v) {
+        uint32_t spins = 0;
+        while (lds_acquire_u32(p) < v) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > (1u << 24)) {  // a partner that never arrives: give up (error flag)
+                if (lane == 0) atomicOr(A.flag, 2);
+                break;
+            }
+        }
+    };
+    // block j with its B in register set P (= j & 1)
+    auto block = [&](uint32_t j, auto parity) {
+        constexpr int P = decltype(parity)::value;
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of block j have landed, its reads of j - 1 are done
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        if (lane == 0) __hip_atomic_store(&pub[s][c], j + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        spin_until(&pub[s][c ^ 1u], j + 1);
+        if (j + 1 < n_j) {  // the partner is done with block j - 1's buffer
+            load_a(j + 1);
+            load_b(j + 1, bh[P ^ 1], bl[P ^ 1]);
+        }
+        // row block m + 1's fragments are read while row block m's 12 MFMAs
+        // issue; the wait for row block m's reads comes before the next reads
+        // are issued (an LDS-only wait: the next block's loads stay in flight)
+        const V* xs = &xa[s][j & 1u][0][lane];
+        V ah = xs[0], al = xs[kWave];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            __builtin_amdgcn_s_waitcnt(kWaitLdsOnly);
+            V nh, nl;
+            if (m < 7) {
+                nh = xs[(2 * m + 2) * kWave];
+                nl = xs[(2 * m + 3) * kWave];
+            }
+            __builtin_amdgcn_sched_barrier(0);  // the reads stay ahead of the MFMAs
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = mfma16<T, V>(ah, bh[P][n], acc[m][n]);
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = mfma16<T, V>(ah, bl[P][n], acc[m][n]);
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = mfma16<T, V>(al, bh[P][n], acc[m][n]);
+            __builtin_amdgcn_sched_barrier(0);  // and the next wait stays behind them
+            if (m < 7) {
+                ah = nh;
+                al = nl;
+            }
+        }
+    };
+    if (n_j > 0) {
+        load_a(0);
+        load_b(0, bh[0], bl[0]);
+    }
+    for (uint32_t j = 0; j < n_j; j += 2) {
+        block(j, std::integral_constant<int, 0>{});
+        if (j + 1 < n_j) block(j + 1, std::integral_constant<int, 1>{});
+    }
+    // slice partials in half order: ((s0 + s2) + (s1 + s3)) per column half
+    __syncthreads();
+    if (s >= 2) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) red[(s - 2) * 2 + c][m * 4 + n][lane] = acc[m][n];
+    }
+    __syncthreads();
+    if (s < 2) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] += red[s * 2 + c][m * 4 + n][lane];
+    }
+    __syncthreads();
+    if (s == 1) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) red[c][m * 4 + n][lane] = acc[m][n];
+    }
+    __syncthreads();
+    if (s == 0) {
+        f32x4* out = P + split2_part(h, mt, nt, n_mt, n_nt);
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) out[(m * 4 + n) * kWave + lane] = acc[m][n] + red[c][m * 4 + n][lane];
+    }
+}
+
+// The stage of one 128-row x 32-realization tile from the two halves'
+// partials: their sum (half 0 + half 1), unscaled, transposed into the LDS
+// tile, then the update and the next operand as in the one-half kernel.
+template <typename T, typename V>
+__global__ __launch_bounds__(kSplit2StageThreads, 1) void dense_split2_stage_kernel(DenseArgs A, const f32x4* P)
+{
+    __shared__ __attribute__((aligned(16))) float tile[2 * kRealTile * (kRowTile + 1)];
+    float (*tS)[kRowTile + 1] = reinterpret_cast<float (*)[kRowTile + 1]>(tile);
+    float (*tC)[kRowTile + 1] = reinterpret_cast<float (*)[kRowTile + 1]>(tile + kRealTile * (kRowTile + 1));
+    uint32_t mt, nt;
+    tile_of(blockIdx.x, A.Mp / kRowTile, A.Rp / kRealTile, A.band, mt, nt);
+    const uint32_t n_mt = A.Mp / kRowTile, n_nt = A.Rp / kRealTile;
+    const uint32_t wave = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+    const f32x4* p0 = P + split2_part(0, mt, nt, n_mt, n_nt);
+    const f32x4* p1 = P + split2_part(1, mt, nt, n_mt, n_nt);
+    const float inv = A.scale[1];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t q = wave * 4 + k, m = q / 4, n = q % 4;
+        const f32x4 v = p0[q * kWave + lane] + p1[q * kWave + lane];
+        float(*t)[kRowTile + 1] = (n >> 1) ? tC : tS;
+        const uint32_t rl = (n & 1) * 16 + (lane & 15u);
+#pragma unroll
+        for (int e = 0; e < 4; ++e) t[rl][m * 16 + 4 * (lane >> 4) + e] = v[e] * inv;
+    }
+    __syncthreads();
+    dense_tile_stage<kSplit2StageThreads>(A, mt, nt, tS, tC);
+    dense_tile_store<T, V, kSplit2StageThreads>(A, mt, nt, tS, tC);
+}
+
 // ------------------------------------------------------------- FP32 MFMA --
 // The FP32 product on v_mfma_f32_16x16x4_f32, split over the k loop the
 // same way but by 4 waves (one per SIMD): every wave computes the whole
@@ -655,12 +879,20 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
     A.c2 = kc.c2;
     A.F1 = F1;
     A.euler = run->scheme == SDE_EULER;
-    const dim3 grid((Mp / kRowTile) * (Rp / kRealTile));
+    A.flag = ctx->flag;
+    const uint32_t n_mt = Mp / kRowTile, n_nt = Rp / kRealTile;
+    const dim3 grid(n_mt * n_nt);
     uint64_t* nbase = nullptr;
     if ((st = step_counter(ctx, &nbase))) return st;
     A.nbase = nbase;
+    // The two-half kernel (16-bit products, an even number of realization
+    // tiles): its partial tiles, two per output tile.
+    const bool split2_ok = sizeof(T) == 2 && n_nt % 2 == 0;
+    void* wpart = nullptr;
+    const size_t part_bytes = (size_t)2 * n_mt * n_nt * 32 * kWave * sizeof(f32x4);
     // launch choice: bit 0 = 4 waves instead of 8 (16-bit variants), bit 1 =
-    // row tiles in plain order instead of XCD bands
+    // row tiles in plain order instead of XCD bands, bit 2 = two workgroups
+    // per tile over the two halves of k (16-bit variants)
     int choice = 0;
     auto launch = [&](hipStream_t s) -> int {
         A.band = (choice & 2) ? 0 : 1;
@@ -668,10 +900,17 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
             hipLaunchKernelGGL(dense_mfma32_kernel, grid, dim3(kDenseThreads), 0, s, A);
         } else {
             typedef typename std::conditional<__is_same(T, __bf16), bf16x8, f16x8>::type V;
-            if (choice & 1)
+            if (choice & 4) {
+                f32x4* part = static_cast<f32x4*>(wpart);
+                hipLaunchKernelGGL((dense_split2_kernel<T, V>), dim3(n_mt * n_nt), dim3(kSplit2Waves * 64), 0, s, A,
+                                   part);
+                hipLaunchKernelGGL((dense_split2_stage_kernel<T, V>), grid, dim3(kSplit2StageThreads), 0, s, A,
+                                   static_cast<const f32x4*>(part));
+            } else if (choice & 1) {
                 hipLaunchKernelGGL((dense_mfma_kernel<T, V, 4>), grid, dim3(256), 0, s, A);
-            else
+            } else {
                 hipLaunchKernelGGL((dense_mfma_kernel<T, V, 8>), grid, dim3(512), 0, s, A);
+            }
         }
         SDE_HIP(ctx, hipGetLastError());
         return SDE_OK;
@@ -683,18 +922,20 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
     // is more than 3 % faster.
     {
         const bool band_matters = (Mp / kRowTile) % 8 == 0;
-        const int n_cand = (sizeof(T) == 4 ? 1 : 2) * (band_matters ? 2 : 1);
-        int cands[4], nc = 0;
-        for (int c = 0; c < 4; ++c) {
+        int cands[6], nc = 0;
+        for (int c : {0, 1, 2, 3, 4, 6}) {
             if ((c & 1) && sizeof(T) == 4) continue;
             if ((c & 2) && !band_matters) continue;
+            if ((c & 4) && !split2_ok) continue;
             cands[nc++] = c;
         }
+        const int n_cand = nc;
+        if (split2_ok && (st = ensure_ws(ctx, kSlotDenseOut, part_bytes, &wpart))) return st;
         char tkey[160];
         snprintf(tkey, sizeof tkey, "dense%d|%s|N2^%d|R2^%d", d->coupling, ctx->arch.c_str(), ilog2_dense(N),
                  ilog2_dense(R));
         if (ctx->dense_launch) {
-            choice = ctx->dense_launch - 1;
+            choice = ctx->dense_launch <= 4 ? ctx->dense_launch - 1 : ctx->dense_launch == 5 ? 4 : 6;
         } else if (!tune_lookup(ctx, tkey, &choice)) {
             choice = 0;
             if (ctx->autotune && n_cand > 1) {
@@ -712,13 +953,14 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
                 A.base = phi;
                 A.dst = static_cast<float*>(scratch);
                 A.F1 = static_cast<float*>(scratch) + NR;
+                A.flag = ctx->tune_flag;
                 hipEvent_t e0, e1;
                 SDE_HIP(ctx, hipEventCreate(&e0));
                 if (hipEventCreate(&e1) != hipSuccess) {
                     (void)hipEventDestroy(e0);
                     return fail(ctx, SDE_ERR_DEVICE, "dense autotuner: hipEventCreate failed");
                 }
-                float ms[4] = {};
+                float ms[6] = {};
                 for (int c = 0; c < nc && st == SDE_OK; ++c) {
                     choice = cands[c];
                     for (int rep = 0; rep < 2 && st == SDE_OK; ++rep) {  // the first launch loads the code object
@@ -745,12 +987,15 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
                 tune_store(ctx, tkey, choice);
             }
         }
-        if (choice < 0 || choice > 3) choice = 0;
+        if (choice < 0 || choice > 7) choice = 0;
         if (sizeof(T) == 4) choice &= 2;    // one FP32 kernel (4 waves)
-        if (!band_matters) choice &= 1;     // bands or not: the same order
+        if (!split2_ok) choice &= 3;        // the two-half kernel needs an even number of realization tiles
+        if (choice & 4) choice &= 6;        // the two-half kernel has 8 waves
+        if (!band_matters) choice &= 5;     // bands or not: the same order
     }
     ctx->last.dense_waves = sizeof(T) == 4 ? 4 : (choice & 1) ? 4 : 8;
     ctx->last.dense_xcd_bands = (choice & 2) || (Mp / kRowTile) % 8 != 0 ? 0 : 1;
+    ctx->last.dense_k_halves = (choice & 4) ? 2 : 1;
     // `count` steps from the device step base, then advance it.  The operand
     // buffers alternate per stage; chunks hold an even number of stages so a
     // recorded chunk always starts from the same buffer.

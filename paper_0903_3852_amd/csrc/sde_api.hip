@@ -109,6 +109,8 @@ int sync_and_check(sde_ctx* ctx, hipStream_t stream)
     SDE_HIP(ctx, hipMemcpy(&flag, ctx->flag, sizeof flag, hipMemcpyDeviceToHost));
     if (flag) {
         SDE_HIP(ctx, hipMemset(ctx->flag, 0, sizeof(int)));
+        if (flag & 2)  // a bounded wait between workgroups or waves gave up: the results are not valid
+            return fail(ctx, SDE_ERR_DEVICE, "a wait between workgroups or waves timed out (results invalid)");
         return fail(ctx, SDE_ERR_NUMERIC, "the integrated state became NaN or Inf");
     }
     return SDE_OK;
@@ -335,7 +337,7 @@ int sde_set_option(sde_ctx* ctx, int option, int64_t value)
         ctx->kura_mf_paired = (int)value;
         return SDE_OK;
     case SDE_OPT_DENSE_LAUNCH:
-        if (value < 0 || value > 4) break;
+        if (value < 0 || value > 6) break;
         ctx->dense_launch = (int)value;
         return SDE_OK;
     default: break;

@@ -173,22 +173,49 @@ def test_dense_launch_choices(gpu):
                                        omega.astype(np.float64), Kmat=Kmat.astype(np.float64))
     for coupling, tol in [(2, 1e-5), (3, 1e-4), (4, 1e-5)]:
         got = {}
-        for launch in (1, 2, 3, 4):
+        for launch in (1, 2, 3, 4, 5, 6):
             sde.sde_set_option(ctx, sde.SDE_OPT_DENSE_LAUNCH, launch)
             ph, _ = _run(gpu, N, R, 4.0, 0.05, 0.005, n, coupling, 0, 33, omega, Kmat, samples=False)
             st = sde.sde_get_stats(ctx)
             waves = 4 if coupling == 2 or launch in (2, 4) else 8
-            assert st["dense_waves"] == waves and st["dense_xcd_bands"] == (1 if launch <= 2 else 0)
+            halves = 2 if coupling != 2 and launch >= 5 else 1
+            assert st["dense_waves"] == waves and st["dense_k_halves"] == halves
+            assert st["dense_xcd_bands"] == (1 if launch in (1, 2, 5) else 0)
             err = _circ_err(ph.cpu().numpy(), ref)
             print(f"dense coupling {coupling}, launch {launch}: max phase error {err.max():.2e}")
             assert err.max() <= tol
             got[launch] = ph.clone()
-        assert torch.equal(got[1], got[3]) and torch.equal(got[2], got[4])
+        assert torch.equal(got[1], got[3]) and torch.equal(got[2], got[4]) and torch.equal(got[5], got[6])
         if coupling == 2:
-            assert torch.equal(got[1], got[2])
-    for bad in (-1, 5):
+            assert torch.equal(got[1], got[2]) and torch.equal(got[1], got[5])
+    for bad in (-1, 7):
         with pytest.raises(sde.SDEError):
             sde.sde_set_option(ctx, sde.SDE_OPT_DENSE_LAUNCH, bad)
+
+
+@pytest.mark.parametrize("N,R", [(1000, 64), (100, 64), (40, 100), (3000, 40), (300, 70), (700, 9)])
+def test_dense_two_halves(gpu, N, R):
+    """The two-half launch (two workgroups per 128 x 32 tile over the two
+    halves of k, A fragments shared through LDS by the wave pairs) against the
+    oracle over 30 Heun steps: k extents of 32 blocks of 32, 4, 2 (some k
+    slices idle) and 94 (halves of 47 blocks, slices of 12 and 11), and odd
+    numbers of 32-realization tiles (R = 70 pads to 96: 3 tiles; R = 9: 1
+    tile), where the launch falls back to the one-half kernel."""
+    sde, ctx, dev = gpu
+    n = 30
+    Kmat = sde_inputs.dense_coupling(N, 4.0, 61)
+    omega = sde_inputs.kuramoto_omega(N, 0.5, 62)
+    ref, _ = oracle.kuramoto_integrate(N, R, 4.0, 0.05, 0.005, n, 0, oracle.DENSE, 0, 63,
+                                       omega.astype(np.float64), Kmat=Kmat.astype(np.float64))
+    even = ((R + 31) // 32) % 2 == 0
+    for coupling, tol in [(3, 1e-4), (4, 1e-5)]:
+        sde.sde_set_option(ctx, sde.SDE_OPT_DENSE_LAUNCH, 5)
+        ph, _ = _run(gpu, N, R, 4.0, 0.05, 0.005, n, coupling, 0, 63, omega, Kmat, samples=False)
+        st = sde.sde_get_stats(ctx)
+        assert st["dense_k_halves"] == (2 if even else 1) and st["dense_waves"] == 8
+        err = _circ_err(ph.cpu().numpy(), ref)
+        print(f"two halves N={N} R={R} coupling {coupling}: max phase error {err.max():.2e}", flush=True)
+        assert err.max() <= tol
 
 
 def test_dense_tuner(gpu):
