@@ -447,8 +447,13 @@ enum {
                           /* 5 = two workgroups per 128 x 128 tile over the two     */
                           /* halves of k (16-bit products, an even number of        */
                           /* 32-realization tiles; else as 1), bands; 6 = the same, */
-                          /* plain order (FP32 always runs 4 waves; bands apply     */
-                          /* when the row tiles split evenly over the 8 XCDs)       */
+                          /* plain order; 7 = 8 waves as 2 row halves x 4 k slices, */
+                          /* each with two register sets of fragments (16-bit       */
+                          /* products), bands; 8 = the same, plain order; 9 = 4     */
+                          /* waves, K fragments double-buffered in LDS (16-bit      */
+                          /* products), bands; 10 = the same, plain order (FP32     */
+                          /* always runs 4 waves; bands apply when the row tiles    */
+                          /* split evenly over the 8 XCDs)                          */
     SDE_OPT_KURA_MF_PAIRED = 10 /* register-resident mean field realizations per    */
                           /* workgroup: 0 (default) = tuned per shape class; 1 =    */
                           /* one; 2 = two (R even, 2 or 4 oscillators per lane, at  */
@@ -484,8 +489,10 @@ typedef struct {
     int32_t dense_xcd_bands; /* its row tiles were dealt to XCDs in bands (1)         */
     int32_t kura_mf_paired;  /* the last register-resident mean-field call held two   */
                              /* realizations per workgroup (1)                        */
-    int32_t dense_k_halves;  /* workgroups per output tile of the last dense call      */
-                             /* (2: the two halves of k, then a stage kernel)         */
+    int32_t dense_variant;   /* the last dense call's kernel: 0 k-sliced waves with   */
+                             /* 128 x 64 tiles, 1 two workgroups per tile over the    */
+                             /* halves of k (then a stage kernel), 2 row-half waves   */
+                             /* with two register sets, 3 four waves with K in LDS    */
 } sde_stats;
 /* Statistics of the last integration call on `ctx`. */
 int sde_get_stats(const sde_ctx* ctx, sde_stats* out);

@@ -72,7 +72,7 @@ class sde_stats(ctypes.Structure):
                 ("mf_streamed", ctypes.c_int32), ("kura_jsplit", ctypes.c_int32),
                 ("kura_tile", ctypes.c_int32), ("kura_mf_opt", ctypes.c_int32),
                 ("dense_waves", ctypes.c_int32), ("dense_xcd_bands", ctypes.c_int32),
-                ("kura_mf_paired", ctypes.c_int32), ("dense_k_halves", ctypes.c_int32)]
+                ("kura_mf_paired", ctypes.c_int32), ("dense_variant", ctypes.c_int32)]
 
 
 class sde_surrogate_scaling(ctypes.Structure):

@@ -62,6 +62,9 @@ constexpr int kDenseThreads = 256;
 constexpr uint32_t kRowTile = 128;
 constexpr uint32_t kRealTile = 32;
 constexpr uint32_t kKStep = 32;
+// s_waitcnt immediate (gfx9 encoding) waiting for LDS and scalar memory only:
+// lgkmcnt(0) with vmcnt and expcnt at their maxima
+constexpr int kWaitLdsOnly = (3 << 14) | (0 << 8) | (7 << 4) | 0xF;
 
 struct DenseArgs {
     const void* K;         // scaled K, packed: 16-bit hi/lo (frag_off) or FP32 (frag32_off)
@@ -474,6 +477,258 @@ __global__ __launch_bounds__(NW * 64, 1) void dense_mfma_kernel(DenseArgs A)
     dense_tile_store<T, V, kThreads>(A, mt, nt, tS, tC);
 }
 
+// ------------------------------------ split MFMA, row-half waves --------
+// The one-half kernel's 128 x 64 wave tiles leave no registers for a second
+// set of fragments, so a block's loads can only go out as the block before
+// it retires.  Here the 8 waves split the tile by rows as well: wave w
+// computes the 64 x 64 half r = w & 1 of the tile over every fourth k block
+// (slice s = w >> 1), with 64 accumulator registers, and holds two register
+// sets of its 16 fragments (4 K and 4 B, hi and lo): each block's loads are
+// issued as the block before it starts, a whole block of MFMAs ahead of
+// their use.  Per block a wave loads 16 KB for 48 MFMAs (the two row-half
+// waves of a slice load the same B fragments, the second from the L1).
+// Per accumulator the products enter in the order hi*hi, hi*lo, lo*hi of
+// each k block, and the slice partials are summed as
+// p0 + ((p1 + p2) + p3).
+constexpr int kRowHalfWaves = 8;
+
+template <typename T, typename V>
+__global__ __launch_bounds__(kRowHalfWaves * 64, 1) void dense_rowhalf_kernel(DenseArgs A)
+{
+    constexpr uint32_t kThreads = kRowHalfWaves * 64, kSlices = 4;
+    __shared__ f32x4 red[2][3][16][kWave];  // [row half][slice - 1][accumulator][lane]
+    __shared__ __attribute__((aligned(16))) float tile[2 * kRealTile * (kRowTile + 1)];
+    float (*tS)[kRowTile + 1] = reinterpret_cast<float (*)[kRowTile + 1]>(tile);
+    float (*tC)[kRowTile + 1] = reinterpret_cast<float (*)[kRowTile + 1]>(tile + kRealTile * (kRowTile + 1));
+    uint32_t mt, nt;
+    tile_of(blockIdx.x, A.Mp / kRowTile, A.Rp / kRealTile, A.band, mt, nt);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63u;
+    const uint32_t r = wave & 1u, sl = wave >> 1;
+    const uint32_t KB = A.Np / kKStep;
+    const uint64_t frag = 2 * 64 * 8;              // elements per k block (hi + lo)
+    const uint64_t stream = (uint64_t)KB * frag;  // elements per 16-row block
+    // wave-uniform bases (scalar registers); a lane's 16 bytes are element
+    // [lane] of each 1 KB fragment, so the loads need one offset register
+    const T* pa = static_cast<const T*>(A.K) + (uint64_t)(mt * 8 + 4 * r) * stream;
+    const T* pb = static_cast<const T*>(A.B) + (uint64_t)(nt * 4) * stream;
+
+    f32x4 acc[4][4];  // [16-row block of the half][column block: sin 0-15, sin 16-31, cos 0-15, cos 16-31]
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    V a0h[4], a0l[4], b0h[4], b0l[4], a1h[4], a1l[4], b1h[4], b1l[4];
+    auto load_set = [&](uint32_t kb, V* ah, V* al, V* bh, V* bl) {
+        const uint64_t o = (uint64_t)kb * frag;
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            ah[m] = reinterpret_cast<const V*>(pa + m * stream + o)[lane];
+            al[m] = reinterpret_cast<const V*>(pa + m * stream + o + kFragLo)[lane];
+        }
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            bh[n] = reinterpret_cast<const V*>(pb + n * stream + o)[lane];
+            bl[n] = reinterpret_cast<const V*>(pb + n * stream + o + kFragLo)[lane];
+        }
+    };
+    auto mfma_set = [&](const V* ah, const V* al, const V* bh, const V* bl) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = mfma16<T, V>(ah[m], bh[n], acc[m][n]);
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = mfma16<T, V>(ah[m], bl[n], acc[m][n]);
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = mfma16<T, V>(al[m], bh[n], acc[m][n]);
+        }
+    };
+    // Blocks kb (set 0) and kb + 4 (set 1) per iteration; the load of block
+    // kb + 8 is clamped to the last block (a spare load at the end, no
+    // branch around it), and an odd last block is left in set 0.
+    uint32_t kb = sl;
+    if (kb < KB) load_set(kb, a0h, a0l, b0h, b0l);
+    for (; kb + kSlices < KB; kb += 2 * kSlices) {
+        load_set(kb + kSlices, a1h, a1l, b1h, b1l);
+        __builtin_amdgcn_sched_barrier(0);  // the loads stay a whole block ahead of their use
+        mfma_set(a0h, a0l, b0h, b0l);
+        __builtin_amdgcn_sched_barrier(0);
+        load_set(min(kb + 2 * kSlices, KB - 1), a0h, a0l, b0h, b0l);
+        __builtin_amdgcn_sched_barrier(0);
+        mfma_set(a1h, a1l, b1h, b1l);
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (kb < KB) mfma_set(a0h, a0l, b0h, b0l);
+    // p0 + ((p1 + p2) + p3) per row half into the tile, transposed, times
+    // the exact power of two that undoes the scaling of K
+    const float inv = A.scale[1];
+    if (sl >= 1) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) red[r][sl - 1][m * 4 + n][lane] = acc[m][n];
+    } else {
+#pragma unroll
+        for (int m = 0; m < 4; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                float(*t)[kRowTile + 1] = (n >> 1) ? tC : tS;
+                const uint32_t rl = (n & 1) * 16 + (lane & 15u);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) t[rl][(4 * r + m) * 16 + 4 * (lane >> 4) + q] = acc[m][n][q] * inv;
+            }
+    }
+    __syncthreads();
+    for (uint32_t p = threadIdx.x; p < 2 * 16 * kWave; p += kThreads) {
+        const uint32_t h = p / (16 * kWave), quad = (p / kWave) % 16, l = p % kWave;
+        const f32x4 sum = (red[h][0][quad][l] + red[h][1][quad][l]) + red[h][2][quad][l];
+        const uint32_t m = 4 * h + quad / 4, n = quad % 4;
+        float(*t)[kRowTile + 1] = (n >> 1) ? tC : tS;
+        const uint32_t rl = (n & 1) * 16 + (l & 15u);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) t[rl][m * 16 + 4 * (l >> 4) + q] += sum[q] * inv;
+    }
+    __syncthreads();
+    dense_tile_stage<kThreads>(A, mt, nt, tS, tC);
+    dense_tile_store<T, V, kThreads>(A, mt, nt, tS, tC);
+}
+
+// ------------------------------ split MFMA, 4 waves, K through LDS ------
+// The one-half kernel's k-sliced 128 x 64 wave tiles with a whole block of
+// lookahead: one wave per SIMD, each with two LDS buffers of its own 16 K
+// fragments (a block's 8 row blocks, hi and lo; 4 waves x 2 x 16 KB) that
+// direct global->LDS loads fill without registers, and two register sets
+// of its 8 B fragments.  Every block's loads are issued as the block before
+// it starts, and row block m + 1's K fragments are read from LDS while row
+// block m's 12 MFMAs issue.  A wave touches only its own buffers, so no
+// wave waits for another inside the k loop.  After it the buffers hold the
+// slice partials, summed as (p0 + p2) + (p1 + p3), and the tile.
+constexpr int kLds4Waves = 4;
+
+template <typename T, typename V>
+__global__ __launch_bounds__(kLds4Waves * 64, 1) void dense_lds4_kernel(DenseArgs A)
+{
+    constexpr uint32_t kThreads = kLds4Waves * 64, kSlices = kLds4Waves;
+    __shared__ V xa[kLds4Waves][2][16][kWave];  // [wave][buffer][row block m: hi 2m, lo 2m + 1][lane]
+    f32x4 (*red)[32][kWave] = reinterpret_cast<f32x4 (*)[32][kWave]>(&xa[0][0][0][0]);
+    float* tile = reinterpret_cast<float*>(&xa[0][0][0][0]) + 2 * 32 * kWave * 4;
+    static_assert(2 * 32 * kWave * sizeof(f32x4) + 2 * kRealTile * (kRowTile + 1) * sizeof(float) <= sizeof(xa),
+                  "two slice partials and the tile fit in the fragment buffers");
+    float (*tS)[kRowTile + 1] = reinterpret_cast<float (*)[kRowTile + 1]>(tile);
+    float (*tC)[kRowTile + 1] = reinterpret_cast<float (*)[kRowTile + 1]>(tile + kRealTile * (kRowTile + 1));
+    uint32_t mt, nt;
+    tile_of(blockIdx.x, A.Mp / kRowTile, A.Rp / kRealTile, A.band, mt, nt);
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63u;
+    const uint32_t KB = A.Np / kKStep;
+    const uint64_t frag = 2 * 64 * 8;              // elements per k block (hi + lo)
+    const uint64_t stream = (uint64_t)KB * frag;  // elements per 16-row block
+    const T* pa = static_cast<const T*>(A.K) + (uint64_t)(mt * 8) * stream;
+    const T* pb = static_cast<const T*>(A.B) + (uint64_t)(nt * 4) * stream;
+
+    f32x4 acc[8][4];  // [16-row block][column block: sin 0-15, sin 16-31, cos 0-15, cos 16-31]
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+#pragma unroll
+        for (int n = 0; n < 4; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    V b0h[4], b0l[4], b1h[4], b1l[4];
+    auto load = [&](uint32_t kb, uint32_t buf, V* bh, V* bl) {
+        const uint64_t o = (uint64_t)kb * frag;
+#pragma unroll
+        for (int f = 0; f < 16; ++f)
+            __builtin_amdgcn_global_load_lds(
+                static_cast<const void*>(pa + (f >> 1) * stream + o + (f & 1) * kFragLo + lane * 8),
+                (void __attribute__((address_space(3)))*)&xa[wave][buf][f][0], 16, 0, 0);
+#pragma unroll
+        for (int n = 0; n < 4; ++n) {
+            bh[n] = reinterpret_cast<const V*>(pb + n * stream + o)[lane];
+            bl[n] = reinterpret_cast<const V*>(pb + n * stream + o + kFragLo)[lane];
+        }
+    };
+    // block kb: its K in buffer buf, its B in (bh, bl); the next block's
+    // loads (clamped to the last block: a spare load at the end) go out first
+    auto block = [&](uint32_t kb, uint32_t buf, const V* bh, const V* bl, V* nh, V* nl) {
+        __builtin_amdgcn_s_waitcnt(0);  // block kb has landed; the reads of the other buffer are done
+        load(min(kb + kSlices, KB - 1), buf ^ 1u, nh, nl);
+        const V* xs = &xa[wave][buf][0][lane];
+        V ah = xs[0], al = xs[kWave];
+#pragma unroll
+        for (int m = 0; m < 8; ++m) {
+            __builtin_amdgcn_s_waitcnt(kWaitLdsOnly);
+            V qh, ql;
+            if (m < 7) {
+                qh = xs[(2 * m + 2) * kWave];
+                ql = xs[(2 * m + 3) * kWave];
+            }
+            __builtin_amdgcn_sched_barrier(0);  // the reads stay ahead of the MFMAs
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = mfma16<T, V>(ah, bh[n], acc[m][n]);
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = mfma16<T, V>(ah, bl[n], acc[m][n]);
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] = mfma16<T, V>(al, bh[n], acc[m][n]);
+            __builtin_amdgcn_sched_barrier(0);  // and the next wait stays behind them
+            if (m < 7) {
+                ah = qh;
+                al = ql;
+            }
+        }
+    };
+    uint32_t kb = wave;
+    if (kb < KB) load(kb, 0, b0h, b0l);
+    for (; kb + kSlices < KB; kb += 2 * kSlices) {
+        block(kb, 0, b0h, b0l, b1h, b1l);
+        block(kb + kSlices, 1, b1h, b1l, b0h, b0l);
+    }
+    if (kb < KB) block(kb, 0, b0h, b0l, b1h, b1l);
+    __builtin_amdgcn_s_waitcnt(0);  // the spare loads have landed before the buffers are reused
+    __syncthreads();
+    // (p0 + p2) + (p1 + p3), then the tile, transposed, times the exact power
+    // of two that undoes the scaling of K
+    if (wave >= 2) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) red[wave - 2][m * 4 + n][lane] = acc[m][n];
+    }
+    __syncthreads();
+    if (wave < 2) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) acc[m][n] += red[wave][m * 4 + n][lane];
+    }
+    __syncthreads();
+    const float inv = A.scale[1];
+    if (wave == 1) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) red[0][m * 4 + n][lane] = acc[m][n];
+    } else if (wave == 0) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+            for (int n = 0; n < 4; ++n) {
+                float(*t)[kRowTile + 1] = (n >> 1) ? tC : tS;
+                const uint32_t rl = (n & 1) * 16 + (lane & 15u);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) t[rl][m * 16 + 4 * (lane >> 4) + q] = acc[m][n][q] * inv;
+            }
+    }
+    __syncthreads();
+    for (uint32_t p = threadIdx.x; p < 32 * kWave; p += kThreads) {
+        const uint32_t quad = p / kWave, l = p % kWave;
+        const f32x4 v = red[0][quad][l];
+        const uint32_t m = quad / 4, n = quad % 4;
+        float(*t)[kRowTile + 1] = (n >> 1) ? tC : tS;
+        const uint32_t rl = (n & 1) * 16 + (l & 15u);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) t[rl][m * 16 + 4 * (l >> 4) + q] += v[q] * inv;
+    }
+    __syncthreads();
+    dense_tile_stage<kThreads>(A, mt, nt, tS, tC);
+    dense_tile_store<T, V, kThreads>(A, mt, nt, tS, tC);
+}
+
 // ------------------------------------------- split MFMA, two K halves --
 // The same product with twice the tile per workgroup, to halve what each
 // CU loads per MFMA: a workgroup computes a 128-row x 64-realization tile (two
@@ -493,9 +748,6 @@ __global__ __launch_bounds__(NW * 64, 1) void dense_mfma_kernel(DenseArgs A)
 // its own loads of it have landed and its reads of block j - 1 are done, so
 // a partner that has seen block j published may refill the buffer of j - 1.
 constexpr int kSplit2Waves = 8;
-// s_waitcnt immediate (gfx9 encoding) waiting for LDS and scalar memory only:
-// lgkmcnt(0) with vmcnt and expcnt at their maxima
-constexpr int kWaitLdsOnly = (3 << 14) | (0 << 8) | (7 << 4) | 0xF;
 constexpr int kSplit2StageThreads = 512;  // the stage kernel: 8 waves, 4 partial fragments each
 
 // Partial tiles: [half][row tile][realization tile][row block 8][column
@@ -892,7 +1144,9 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
     const size_t part_bytes = (size_t)2 * n_mt * n_nt * 32 * kWave * sizeof(f32x4);
     // launch choice: bit 0 = 4 waves instead of 8 (16-bit variants), bit 1 =
     // row tiles in plain order instead of XCD bands, bit 2 = two workgroups
-    // per tile over the two halves of k (16-bit variants)
+    // per tile over the two halves of k, bit 3 = row-half waves with two
+    // register sets, bit 4 = 4 waves with K fragments through LDS (16-bit
+    // variants)
     int choice = 0;
     auto launch = [&](hipStream_t s) -> int {
         A.band = (choice & 2) ? 0 : 1;
@@ -900,7 +1154,11 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
             hipLaunchKernelGGL(dense_mfma32_kernel, grid, dim3(kDenseThreads), 0, s, A);
         } else {
             typedef typename std::conditional<__is_same(T, __bf16), bf16x8, f16x8>::type V;
-            if (choice & 4) {
+            if (choice & 16) {
+                hipLaunchKernelGGL((dense_lds4_kernel<T, V>), grid, dim3(kLds4Waves * 64), 0, s, A);
+            } else if (choice & 8) {
+                hipLaunchKernelGGL((dense_rowhalf_kernel<T, V>), grid, dim3(kRowHalfWaves * 64), 0, s, A);
+            } else if (choice & 4) {
                 f32x4* part = static_cast<f32x4*>(wpart);
                 hipLaunchKernelGGL((dense_split2_kernel<T, V>), dim3(n_mt * n_nt), dim3(kSplit2Waves * 64), 0, s, A,
                                    part);
@@ -922,9 +1180,9 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
     // is more than 3 % faster.
     {
         const bool band_matters = (Mp / kRowTile) % 8 == 0;
-        int cands[6], nc = 0;
-        for (int c : {0, 1, 2, 3, 4, 6}) {
-            if ((c & 1) && sizeof(T) == 4) continue;
+        int cands[10], nc = 0;
+        for (int c : {0, 1, 2, 3, 4, 6, 8, 10, 16, 18}) {
+            if ((c & 25) && sizeof(T) == 4) continue;
             if ((c & 2) && !band_matters) continue;
             if ((c & 4) && !split2_ok) continue;
             cands[nc++] = c;
@@ -935,7 +1193,8 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
         snprintf(tkey, sizeof tkey, "dense%d|%s|N2^%d|R2^%d", d->coupling, ctx->arch.c_str(), ilog2_dense(N),
                  ilog2_dense(R));
         if (ctx->dense_launch) {
-            choice = ctx->dense_launch <= 4 ? ctx->dense_launch - 1 : ctx->dense_launch == 5 ? 4 : 6;
+            static const int kForced[] = {0, 0, 1, 2, 3, 4, 6, 8, 10, 16, 18};
+            choice = kForced[ctx->dense_launch];
         } else if (!tune_lookup(ctx, tkey, &choice)) {
             choice = 0;
             if (ctx->autotune && n_cand > 1) {
@@ -960,7 +1219,7 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
                     (void)hipEventDestroy(e0);
                     return fail(ctx, SDE_ERR_DEVICE, "dense autotuner: hipEventCreate failed");
                 }
-                float ms[6] = {};
+                float ms[10] = {};
                 for (int c = 0; c < nc && st == SDE_OK; ++c) {
                     choice = cands[c];
                     for (int rep = 0; rep < 2 && st == SDE_OK; ++rep) {  // the first launch loads the code object
@@ -987,15 +1246,17 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
                 tune_store(ctx, tkey, choice);
             }
         }
-        if (choice < 0 || choice > 7) choice = 0;
+        if (choice < 0 || choice > 31) choice = 0;
         if (sizeof(T) == 4) choice &= 2;    // one FP32 kernel (4 waves)
-        if (!split2_ok) choice &= 3;        // the two-half kernel needs an even number of realization tiles
+        if (choice & 16) choice &= 18;      // the 4-wave LDS kernel: one workgroup per tile
+        if (choice & 8) choice &= 10;       // the row-half kernel: 8 waves, one workgroup per tile
+        if (!split2_ok) choice &= 11;       // the two-half kernel needs an even number of realization tiles
         if (choice & 4) choice &= 6;        // the two-half kernel has 8 waves
-        if (!band_matters) choice &= 5;     // bands or not: the same order
+        if (!band_matters) choice &= 29;    // bands or not: the same order
     }
-    ctx->last.dense_waves = sizeof(T) == 4 ? 4 : (choice & 1) ? 4 : 8;
+    ctx->last.dense_waves = sizeof(T) == 4 ? 4 : (choice & 17) ? 4 : 8;
     ctx->last.dense_xcd_bands = (choice & 2) || (Mp / kRowTile) % 8 != 0 ? 0 : 1;
-    ctx->last.dense_k_halves = (choice & 4) ? 2 : 1;
+    ctx->last.dense_variant = (choice & 16) ? 3 : (choice & 8) ? 2 : (choice & 4) ? 1 : 0;
     // `count` steps from the device step base, then advance it.  The operand
     // buffers alternate per stage; chunks hold an even number of stages so a
     // recorded chunk always starts from the same buffer.
