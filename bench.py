@@ -1066,8 +1066,21 @@ def bench_valu_costs(args):
             feed[f"{loads}_loads_per_96_mfma_{label}"] = {
                 "tflops": round(n * 16384 / t / 1e12, 1), "frac_of_peak": round(n * 16384 / t / PEAK_MFMA_16BIT, 3),
                 "bytes_per_clk_per_cu": round(blocks * 8.0 * it * loads * 1024 / t / 256 / 2.4e9, 1)}
-    return {"workload": "valu_costs", "unit": "SIMD cycles per wave64 instruction", "cycles": out,
-            "mfma_rate": mfma, "mfma_fed_from_memory": feed}
+    rec = {"workload": "valu_costs", "unit": "SIMD cycles per wave64 instruction", "cycles": out,
+           "mfma_rate": mfma, "mfma_fed_from_memory": feed}
+    if getattr(args, "mfma_sustained", False):
+        # the bf16 cases of the dense coupling over 20-80 ms launches (clock under sustained matrix load)
+        ms = ctypes.c_float()
+        if lib.mfma_rate_time(0, 512, 200000, ctypes.byref(ms)) != 0:
+            raise RuntimeError("mfma probe failed")
+        reg = 512 * 4.0 * 200000 * 8 * 16384 / (ms.value * 1e-3)
+        if lib.mfma_feed_time(24, 256, 50000, 2 << 20, ctypes.byref(ms)) != 0:
+            raise RuntimeError("mfma feed probe failed")
+        fed = 256 * 8.0 * 50000 * 96 * 16384 / (ms.value * 1e-3)
+        rec["mfma_sustained"] = {"register_only_2_waves_tflops": round(reg / 1e12, 1),
+                                 "fed_24_loads_l2_tflops": round(fed / 1e12, 1),
+                                 "fed_frac_of_peak": round(fed / PEAK_MFMA_16BIT, 3)}
+    return rec
 
 
 def main():
@@ -1080,6 +1093,8 @@ def main():
                              "sweep", "valu_costs"] + sorted(KURA))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kuramoto", action="store_true")
+    ap.add_argument("--mfma-sustained", action="store_true",
+                    help="valu_costs: also time the dense coupling's bf16 MFMA cases over 20-80 ms launches")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--model-steps", type=int, default=200000,
                     help="Heun steps per path (the workload uses 2e5; smaller only for profiling)")
