@@ -406,23 +406,61 @@ __global__ __launch_bounds__(NW * 64, 1) void dense_mfma_kernel(DenseArgs A)
             al[m] = *reinterpret_cast<const V*>(pa + m * stream + o + kFragLo);
         }
     }
+    // Two passes over the row blocks per k block: columns 0-1, then 2-3 (a
+    // pair of row blocks at a time, so 4 independent accumulators separate
+    // an accumulator's dependent MFMAs).  B fragments 0-1 of the next block
+    // load after the first pass, 2-3 after the second, and row block m's K
+    // fragments right after its last MFMAs: every load goes out at least
+    // half a block before its use.  The loads are unconditional (the last
+    // block loads itself again) and scheduling barriers keep them in place:
+    // with a branch around them the compiler's wait counts must also cover
+    // the path that issues none, and it drained every load in flight before
+    // the last row block; left free, it sank them to their uses.
     for (uint32_t kb = wave; kb < KB; kb += kSplit) {
-        const bool more = kb + kSplit < KB;
-        const uint64_t on = (uint64_t)(more ? kb + kSplit : kb) * frag;
+        const uint64_t on = (uint64_t)(kb + kSplit < KB ? kb + kSplit : kb) * frag;
 #pragma unroll
-        for (int m = 0; m < 8; ++m) {
+        for (int half = 0; half < 2; ++half) {
 #pragma unroll
-            for (int n = 0; n < 4; ++n) acc[m][n] = mfma16<T, V>(ah[m], bh[n], acc[m][n]);
+            for (int mp = 0; mp < 4; ++mp) {
 #pragma unroll
-            for (int n = 0; n < 4; ++n) acc[m][n] = mfma16<T, V>(ah[m], bl[n], acc[m][n]);
+                for (int mm = 0; mm < 2; ++mm)
 #pragma unroll
-            for (int n = 0; n < 4; ++n) acc[m][n] = mfma16<T, V>(al[m], bh[n], acc[m][n]);
-            if (more) {
-                ah[m] = *reinterpret_cast<const V*>(pa + m * stream + on);
-                al[m] = *reinterpret_cast<const V*>(pa + m * stream + on + kFragLo);
+                    for (int nn = 0; nn < 2; ++nn) {
+                        const int m = 2 * mp + mm, n = 2 * half + nn;
+                        acc[m][n] = mfma16<T, V>(ah[m], bh[n], acc[m][n]);
+                    }
+#pragma unroll
+                for (int mm = 0; mm < 2; ++mm)
+#pragma unroll
+                    for (int nn = 0; nn < 2; ++nn) {
+                        const int m = 2 * mp + mm, n = 2 * half + nn;
+                        acc[m][n] = mfma16<T, V>(ah[m], bl[n], acc[m][n]);
+                    }
+#pragma unroll
+                for (int mm = 0; mm < 2; ++mm)
+#pragma unroll
+                    for (int nn = 0; nn < 2; ++nn) {
+                        const int m = 2 * mp + mm, n = 2 * half + nn;
+                        acc[m][n] = mfma16<T, V>(al[m], bh[n], acc[m][n]);
+                    }
+                if (half == 1) {
+#pragma unroll
+                    for (int mm = 0; mm < 2; ++mm) {
+                        const int m = 2 * mp + mm;
+                        ah[m] = *reinterpret_cast<const V*>(pa + m * stream + on);
+                        al[m] = *reinterpret_cast<const V*>(pa + m * stream + on + kFragLo);
+                    }
+                }
+                __builtin_amdgcn_sched_barrier(0);  // the loads stay right behind their last MFMAs
             }
+#pragma unroll
+            for (int nn = 0; nn < 2; ++nn) {
+                const int n = 2 * half + nn;
+                bh[n] = *reinterpret_cast<const V*>(pb + n * stream + on);
+                bl[n] = *reinterpret_cast<const V*>(pb + n * stream + on + kFragLo);
+            }
+            __builtin_amdgcn_sched_barrier(0);
         }
-        if (more) load_b(on);
     }
     // round 1: wave w < 4 adds wave w + 4's partial
     if constexpr (NW == 8) {
