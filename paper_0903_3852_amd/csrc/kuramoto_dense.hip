@@ -366,9 +366,10 @@ __global__ __launch_bounds__(NW * 64, 1) void dense_mfma_kernel(DenseArgs A)
     static_assert(NW == 4 || NW == 8, "4 or 8 waves");
     constexpr uint32_t kThreads = NW * 64, kSplit = NW;
     // Partial tiles are summed in two rounds: waves 4-7 hand theirs to waves
-    // 0-3 (red[0..2] and slot3; 8 waves only), then waves 1-3 hand theirs to
-    // the tile (red[0..2]).  The transposed tile [realization][row] overlays
-    // slot3, whose contents are consumed before the tile is written.
+    // 0-3 (red[0..2] and slot3; 8 waves only), then waves 0-3 put theirs in
+    // slot3 and red[0..2] and every thread sums its share.  The transposed
+    // tile [realization][row] overlays slot3, whose contents are consumed
+    // before the tile is written.
     __shared__ f32x4 red[3][32][kWave];
     __shared__ __attribute__((aligned(16))) float tile[2 * kRealTile * (kRowTile + 1)];
     static_assert(sizeof(tile) >= sizeof(f32x4) * 32 * kWave, "slot3 fits under the tile");
@@ -481,34 +482,35 @@ __global__ __launch_bounds__(NW * 64, 1) void dense_mfma_kernel(DenseArgs A)
         }
         __syncthreads();
     }
-    // round 2: p0 + ((p1 + p2) + p3) into the tile, transposed, times the
-    // exact power of two that undoes the scaling of K
+    // round 2: all four partials to LDS (wave 0's to slot3), then every
+    // thread sums p0 + ((p1 + p2) + p3) for its quads, and after a barrier
+    // (slot3 lies under the tile) writes them transposed into the tile,
+    // times the exact power of two that undoes the scaling of K
     const float inv = A.scale[1];
-    if (wave >= 1 && wave < 4) {
+    if (wave < 4) {
+        f32x4 (*dst)[kWave] = wave == 0 ? slot3 : red[wave - 1];
 #pragma unroll
         for (int m = 0; m < 8; ++m)
 #pragma unroll
-            for (int n = 0; n < 4; ++n) red[wave - 1][m * 4 + n][lane] = acc[m][n];
-    } else if (wave == 0) {
-#pragma unroll
-        for (int m = 0; m < 8; ++m)
-#pragma unroll
-            for (int n = 0; n < 4; ++n) {
-                float(*t)[kRowTile + 1] = (n >> 1) ? tC : tS;
-                const uint32_t rl = (n & 1) * 16 + (lane & 15u);
-#pragma unroll
-                for (int q = 0; q < 4; ++q) t[rl][m * 16 + 4 * (lane >> 4) + q] = acc[m][n][q] * inv;
-            }
+            for (int n = 0; n < 4; ++n) dst[m * 4 + n][lane] = acc[m][n];
     }
     __syncthreads();
-    for (uint32_t p = threadIdx.x; p < 32 * kWave; p += kThreads) {
-        const uint32_t quad = p / kWave, l = p % kWave;
-        const f32x4 sum = (red[0][quad][l] + red[1][quad][l]) + red[2][quad][l];
+    constexpr uint32_t kQuads = 32 * kWave / kThreads;
+    f32x4 sum[kQuads];
+#pragma unroll
+    for (uint32_t k = 0; k < kQuads; ++k) {
+        const uint32_t p = threadIdx.x + k * kThreads, quad = p / kWave, l = p % kWave;
+        sum[k] = slot3[quad][l] + ((red[0][quad][l] + red[1][quad][l]) + red[2][quad][l]);
+    }
+    __syncthreads();
+#pragma unroll
+    for (uint32_t k = 0; k < kQuads; ++k) {
+        const uint32_t p = threadIdx.x + k * kThreads, quad = p / kWave, l = p % kWave;
         const uint32_t m = quad / 4, n = quad % 4;
         float(*t)[kRowTile + 1] = (n >> 1) ? tC : tS;
         const uint32_t rl = (n & 1) * 16 + (l & 15u);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) t[rl][m * 16 + 4 * (l >> 4) + q] += sum[q] * inv;
+        for (int q = 0; q < 4; ++q) t[rl][m * 16 + 4 * (l >> 4) + q] = sum[k][q] * inv;
     }
     __syncthreads();
     dense_tile_stage<kThreads>(A, mt, nt, tS, tC);
