@@ -732,6 +732,8 @@ def bench_kuramoto(name, args, sde, torch, dev, steps=None, reps=1):
     ph = torch.empty((R, N), dtype=torch.float32, device=dev)
     rs = torch.zeros((R, n // 100 + 1), dtype=torch.float64, device=dev)
     ctx = sde.sde_create(0)
+    if getattr(args, "dense_launch", 0) and spec["coupling"] >= 2:
+        sde.sde_set_option(ctx, sde.SDE_OPT_DENSE_LAUNCH, args.dense_launch)
     desc = sde.sde_kuramoto_desc(N, R, cfg["K"], cfg["D"], cfg["dt"], n, spec["coupling"], 0)
     run = sde.make_run(cfg["seed"], scheme=spec["scheme"])
     stream = torch.cuda.current_stream()
@@ -778,7 +780,10 @@ def bench_kuramoto(name, args, sde, torch, dev, steps=None, reps=1):
                            "unit": "T lane-op units/s", "frac": ops * pairs / t / PEAK_FMA_LANES,
                            "traffic": None, "counters": kura_counters("kuramoto_tiled")}
     else:
-        rec["launch"] = {"waves": st["dense_waves"], "xcd_bands": st["dense_xcd_bands"]}
+        rec["launch"] = {"waves": st["dense_waves"], "xcd_bands": st["dense_xcd_bands"],
+                         "kernel": ["k-sliced waves", "two k halves", "row-half waves", "4 waves, K in LDS"][
+                             st["dense_variant"]]}
+        rec["us_per_stage"] = t / (n * (2 if heun else 1)) * 1e6
         gemm_flop = 2.0 * N * N * 2 * R * n * (2 if heun else 1)
         if spec["coupling"] == 2:
             # FP32 MFMA (v_mfma_f32_16x16x4_f32): MI355X's FP32 matrix peak equals its FP32 vector peak
@@ -1093,6 +1098,8 @@ def main():
                              "sweep", "valu_costs"] + sorted(KURA))
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kuramoto", action="store_true")
+    ap.add_argument("--dense-launch", type=int, default=0,
+                    help="kuramoto_dense_*: force a dense launch choice (1-10, as SDE_OPT_DENSE_LAUNCH; 0 tunes)")
     ap.add_argument("--mfma-sustained", action="store_true",
                     help="valu_costs: also time the dense coupling's bf16 MFMA cases over 20-80 ms launches")
     ap.add_argument("--cpu-seconds", type=float, default=20.0)

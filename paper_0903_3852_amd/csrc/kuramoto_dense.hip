@@ -1213,11 +1213,11 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
         SDE_HIP(ctx, hipGetLastError());
         return SDE_OK;
     };
-    // The choice is tuned per shape class: one predictor stage of each
-    // candidate from the call's operand, its phases, carry and next operand
-    // going to scratch and to the operand buffer the call's first stage
-    // overwrites anyway; the default (8 waves, bands) is kept unless another
-    // is more than 3 % faster.
+    // The choice is tuned per shape class: predictor stages of each
+    // candidate from the call's operand (the fastest of three), its phases,
+    // carry and next operand going to scratch and to the operand buffer the
+    // call's first stage overwrites anyway; the default (8 waves, bands) is
+    // kept unless another is more than 3 % faster.
     {
         const bool band_matters = (Mp / kRowTile) % 8 == 0;
         int cands[10], nc = 0;
@@ -1259,16 +1259,21 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
                     (void)hipEventDestroy(e0);
                     return fail(ctx, SDE_ERR_DEVICE, "dense autotuner: hipEventCreate failed");
                 }
-                float ms[10] = {};
-                for (int c = 0; c < nc && st == SDE_OK; ++c) {
-                    choice = cands[c];
-                    for (int rep = 0; rep < 2 && st == SDE_OK; ++rep) {  // the first launch loads the code object
+                // one untimed launch of every candidate (the first launch
+                // loads the code object), then three timed rounds over all
+                // of them in turn; a candidate's time is its fastest launch
+                float ms[10];
+                for (int c = 0; c < nc; ++c) ms[c] = 3.4e38f;
+                for (int round = 0; round < 4 && st == SDE_OK; ++round) {
+                    for (int c = 0; c < nc && st == SDE_OK; ++c) {
+                        choice = cands[c];
+                        float t = 0.f;
                         if (hipEventRecord(e0, stream) != hipSuccess) st = SDE_ERR_DEVICE;
                         if (!st) st = launch(stream);
                         if (!st && hipEventRecord(e1, stream) != hipSuccess) st = SDE_ERR_DEVICE;
-                        if (!st && (hipEventSynchronize(e1) != hipSuccess ||
-                                    hipEventElapsedTime(&ms[c], e0, e1) != hipSuccess))
+                        if (!st && (hipEventSynchronize(e1) != hipSuccess || hipEventElapsedTime(&t, e0, e1) != hipSuccess))
                             st = SDE_ERR_DEVICE;
+                        if (!st && round > 0) ms[c] = std::min(ms[c], t);
                     }
                 }
                 (void)hipEventDestroy(e0);
