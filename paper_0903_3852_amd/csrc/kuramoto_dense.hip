@@ -71,9 +71,8 @@ struct DenseArgs {
     const void* B;         // current sin/cos operand (same layout family)
     void* Bnext;           // operand for the next product
     const float* src;      // [R][N] phases the drift is evaluated at
-    const float* base;     // [R][N] phases at the start of the step
     float* dst;            // [R][N] output phases
-    float* F1;             // [R][N] the predictor's carry for the corrector (dense_stage)
+    float* F1;             // [R][N] the predictor's carry for the corrector: th + (dt/2) F_1 / 2 pi + noise
     const float* omega;    // [N]
     const float* scale;    // device: {scale, 1/scale}
     uint32_t N, R, Np, Rp, Mp;  // Np: k extent of the product (N rounded up to 32)
@@ -125,29 +124,31 @@ __device__ __forceinline__ void store_split(T* p, uint64_t idx, float x)
 
 // The stage update of oscillator i of realization r at absolute step n,
 // given S = sum_j K_ij sin phi_j, C = sum_j K_ij cos phi_j, the phase ts the
-// drift F is evaluated at, the phase th at the start of the step and omega_i.
-// Both Heun stages of a step add the same noise (Alg. 2), so the predictor
-// leaves the corrector everything it needs from stage 1 in one number,
-// carry = (dt / 2) F_1 / 2 pi + noise, and the corrector draws no noise:
+// drift F is evaluated at (the predictor: the phase th at the start of the
+// step) and omega_i.  Both Heun stages of a step add the same noise
+// (Alg. 2), so the predictor leaves the corrector everything it needs from
+// stage 1 and the step's start in one number,
+// carry = th + (dt / 2) F_1 / 2 pi + noise, and the corrector neither draws
+// noise nor reads th again:
 //   predictor  t = th + dt F_1 / 2 pi + noise           (Euler: the step)
-//   corrector  t = th + (dt / 2) F_2 / 2 pi + carry
+//   corrector  t = carry + (dt / 2) F_2 / 2 pi
 // Returns the new phase; `carry` is written by the predictor, read by the
 // corrector.
 __device__ __forceinline__ float dense_stage(const DenseArgs& A, uint64_t n, uint32_t i, uint32_t r, float S, float C,
-                                             float ts, float th, float om, float& carry)
+                                             float ts, float om, float& carry)
 {
     const float F = fmaf(cos_rev(ts), S, fmaf(-sin_rev(ts), C, om));
     float t;
     if (A.stage == 1) {
         const float ns = gauss1_scaled(U4{(uint32_t)(n >> 2), i, r, (uint32_t)SDE_TAG_NOISE}, A.key0, A.key1, A.c2,
                                        (uint32_t)n & 3u);
-        t = fmaf(A.omega_scale, F, th) + ns;
+        t = fmaf(A.omega_scale, F, ts) + ns;
         if (A.euler)
             t -= floorf(t);
         else
-            carry = fmaf(A.hdt2pi, F, ns);
+            carry = ts + fmaf(A.hdt2pi, F, ns);  // one rounding at the phase's magnitude
     } else {
-        t = fmaf(A.hdt2pi, F, th) + carry;
+        t = fmaf(A.hdt2pi, F, carry);
         t -= floorf(t);
     }
     return t;
@@ -197,7 +198,7 @@ __device__ __forceinline__ void dense_tile_stage(const DenseArgs& A, uint32_t mt
     static_assert(kRowTile % kWave == 0 && NT % kRowTile == 0, "a wave stays in one realization");
     const uint64_t n = load_uniform(A.nbase) + A.k;
     const bool corrector = A.stage != 1;
-    float ts[kPer], th[kPer], cy[kPer], om[kPer];
+    float ts[kPer], cy[kPer], om[kPer];
 #pragma unroll
     for (uint32_t e = 0; e < kPer; ++e) {
         const uint32_t idx = threadIdx.x + e * NT;
@@ -207,17 +208,6 @@ __device__ __forceinline__ void dense_tile_stage(const DenseArgs& A, uint32_t mt
         ts[e] = ok ? A.src[gi] : 0.f;
         cy[e] = ok && corrector ? A.F1[gi] : 0.f;
         om[e] = ok ? A.omega[i] : 0.f;
-    }
-    if (A.src == A.base) {  // stage 1: the drift is evaluated at the step's start
-#pragma unroll
-        for (uint32_t e = 0; e < kPer; ++e) th[e] = ts[e];
-    } else {
-#pragma unroll
-        for (uint32_t e = 0; e < kPer; ++e) {
-            const uint32_t idx = threadIdx.x + e * NT;
-            const uint32_t r = nt * kRealTile + idx / kRowTile, i = mt * kRowTile + idx % kRowTile;
-            th[e] = r < A.R && i < A.N ? A.base[(uint64_t)r * A.N + i] : 0.f;
-        }
     }
     // The lane's 16 updates are independent: read all sums first and compute
     // them branch-free (lanes outside R x N draw noise nobody uses), so the
@@ -235,7 +225,7 @@ __device__ __forceinline__ void dense_tile_stage(const DenseArgs& A, uint32_t mt
     for (uint32_t e = 0; e < kPer; ++e) {
         const uint32_t idx = threadIdx.x + e * NT;
         const uint32_t r = nt * kRealTile + idx / kRowTile, i = mt * kRowTile + idx % kRowTile;
-        t[e] = dense_stage(A, n, i, r, S[e], C[e], ts[e], th[e], om[e], cy[e]);
+        t[e] = dense_stage(A, n, i, r, S[e], C[e], ts[e], om[e], cy[e]);
     }
 #pragma unroll
     for (uint32_t e = 0; e < kPer; ++e) {
@@ -1249,7 +1239,6 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
                 A.B = Bbuf[0];
                 A.Bnext = Bbuf[1];
                 A.src = phi;
-                A.base = phi;
                 A.dst = static_cast<float*>(scratch);
                 A.F1 = static_cast<float*>(scratch) + NR;
                 A.flag = ctx->tune_flag;
@@ -1315,7 +1304,6 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
             A.B = Bbuf[cur];
             A.Bnext = Bbuf[cur ^ 1];
             A.src = phi;
-            A.base = phi;
             A.dst = A.euler ? phi : tilde;
             int e = launch(s);
             if (e) return e;
@@ -1326,7 +1314,6 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
             A.B = Bbuf[cur];
             A.Bnext = Bbuf[cur ^ 1];
             A.src = tilde;
-            A.base = phi;
             A.dst = phi;
             if ((e = launch(s))) return e;
             cur ^= 1;
