@@ -39,8 +39,11 @@
 // so that each XCD sweeps a contiguous band of rows over all columns: its
 // slice of K is read from HBM/MALL once per product, B once per XCD, and the
 // workgroups that share a K slab or a B column block hit in the XCD's L2.
-// The wave count and the banding (against plain row-major order) are chosen
-// per shape class by timing one stage of each.
+// Three more 16-bit kernels with a whole block of load lookahead (two
+// workgroups per tile over the halves of k, row-half waves with two
+// register sets, 4 waves with K double-buffered in LDS) are candidates too:
+// the kernel and the banding (against plain row-major order) are chosen per
+// shape class by timing predictor stages of each.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
