@@ -781,8 +781,8 @@ def bench_kuramoto(name, args, sde, torch, dev, steps=None, reps=1):
                            "traffic": None, "counters": kura_counters("kuramoto_tiled")}
     else:
         rec["launch"] = {"waves": st["dense_waves"], "xcd_bands": st["dense_xcd_bands"],
-                         "kernel": ["k-sliced waves", "two k halves", "row-half waves", "4 waves, K in LDS"][
-                             st["dense_variant"]]}
+                         "kernel": ["k-sliced waves", "two k halves", "row-half waves", "4 waves, K in LDS",
+                                    "wave pairs, K in LDS"][st["dense_variant"]]}
         rec["us_per_stage"] = t / (n * (2 if heun else 1)) * 1e6
         gemm_flop = 2.0 * N * N * 2 * R * n * (2 if heun else 1)
         if spec["coupling"] == 2:

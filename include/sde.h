@@ -451,9 +451,12 @@ enum {
                           /* each with two register sets of fragments (16-bit       */
                           /* products), bands; 8 = the same, plain order; 9 = 4     */
                           /* waves, K fragments double-buffered in LDS (16-bit      */
-                          /* products), bands; 10 = the same, plain order (FP32     */
-                          /* always runs 4 waves; bands apply when the row tiles    */
-                          /* split evenly over the 8 XCDs)                          */
+                          /* products), bands; 10 = the same, plain order; 11 = 8   */
+                          /* waves as 4 k slices x 2 column halves, each pair       */
+                          /* sharing its K fragments through LDS (16-bit products), */
+                          /* bands; 12 = the same, plain order (FP32 always runs 4  */
+                          /* waves; bands apply when the row tiles split evenly     */
+                          /* over the 8 XCDs)                                       */
     SDE_OPT_KURA_MF_PAIRED = 10 /* register-resident mean field realizations per    */
                           /* workgroup: 0 (default) = tuned per shape class; 1 =    */
                           /* one; 2 = two (R even, 2 or 4 oscillators per lane, at  */
@@ -492,7 +495,8 @@ typedef struct {
     int32_t dense_variant;   /* the last dense call's kernel: 0 k-sliced waves with   */
                              /* 128 x 64 tiles, 1 two workgroups per tile over the    */
                              /* halves of k (then a stage kernel), 2 row-half waves   */
-                             /* with two register sets, 3 four waves with K in LDS    */
+                             /* with two register sets, 3 four waves with K in LDS,   */
+                             /* 4 wave pairs sharing K through LDS                    */
 } sde_stats;
 /* Statistics of the last integration call on `ctx`. */
 int sde_get_stats(const sde_ctx* ctx, sde_stats* out);

@@ -762,6 +762,185 @@ __global__ __launch_bounds__(kLds4Waves * 64, 1) void dense_lds4_kernel(DenseArg
     dense_tile_store<T, V, kThreads>(A, mt, nt, tS, tC);
 }
 
+// Acquire load of a workgroup-scope LDS counter (the wave-pair handshakes).
+__device__ __forceinline__ uint32_t lds_acquire_u32(const uint32_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
+// ---------------------------- split MFMA, wave pairs sharing K in LDS ----
+// One workgroup per 128-row x 32-realization tile, as in the k-sliced
+// kernel, but its 8 waves are 4 k slices x 2 column halves: wave w computes
+// columns 2c, 2c + 1 (c = w & 1) of the tile over every fourth k block
+// (slice s = w >> 1), with 16 accumulators, so two waves need the same K
+// fragments of every block.  Each loads its four row blocks (hi and lo)
+// straight into the slice's LDS buffer (global_load_lds_dwordx4, no
+// registers, double-buffered), and both read all eight from there, a pair
+// of row blocks ahead of the MFMAs; the B fragments go to a second register
+// set.  Every block's loads are issued as the block before it starts: a
+// whole block of lookahead, with the bytes per MFMA of the k-sliced kernel
+// (K shared in the pair, no fragment loaded twice into the CU).  The pair
+// paces itself through an LDS counter of blocks published (a wave publishes
+// block j once its own loads of it have landed and its reads of block j - 1
+// are done, so a partner that has seen j published may refill j - 1's
+// buffer).  The slice partials are summed as p0 + ((p1 + p2) + p3).
+constexpr int kPairWaves = 8;
+
+template <typename T, typename V>
+__global__ __launch_bounds__(kPairWaves * 64, 1) void dense_pair_kernel(DenseArgs A)
+{
+    constexpr uint32_t kThreads = kPairWaves * 64;
+    constexpr size_t kXaBytes = 4 * 2 * 16 * kWave * sizeof(V);
+    constexpr size_t kRedBytes = 2 * 3 * 16 * kWave * sizeof(f32x4);
+    constexpr size_t kTileBytes = 2 * kRealTile * (kRowTile + 1) * sizeof(float);
+    constexpr size_t kLdsBytes = kXaBytes > kRedBytes + kTileBytes ? kXaBytes : kRedBytes + kTileBytes;
+    // K fragments [slice][buffer][row block m: hi 2m, lo 2m + 1][lane]; after
+    // the k loop the same memory holds the partials [column half][slice - 1]
+    // and, behind them, the transposed tile.
+    __shared__ __attribute__((aligned(16))) unsigned char lds[kLdsBytes];
+    __shared__ uint32_t pub[4][2];
+    V (*xa)[2][16][kWave] = reinterpret_cast<V (*)[2][16][kWave]>(lds);
+    f32x4 (*red)[3][16][kWave] = reinterpret_cast<f32x4 (*)[3][16][kWave]>(lds);
+    float* tile = reinterpret_cast<float*>(lds + kRedBytes);
+    float (*tS)[kRowTile + 1] = reinterpret_cast<float (*)[kRowTile + 1]>(tile);
+    float (*tC)[kRowTile + 1] = reinterpret_cast<float (*)[kRowTile + 1]>(tile + kRealTile * (kRowTile + 1));
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63u;
+    const uint32_t c = wave & 1u, s = wave >> 1;
+    if (threadIdx.x < 8) (&pub[0][0])[threadIdx.x] = 0u;
+    __syncthreads();
+    uint32_t mt, nt;
+    tile_of(blockIdx.x, A.Mp / kRowTile, A.Rp / kRealTile, A.band, mt, nt);
+    const uint32_t KB = A.Np / kKStep;
+    const uint32_t n_j = s < KB ? (KB - s + 3) / 4 : 0u;
+    const uint64_t frag = 2 * 64 * 8;              // elements per k block (hi + lo)
+    const uint64_t stream = (uint64_t)KB * frag;  // elements per 16-row block
+    const T* pa = static_cast<const T*>(A.K) + (uint64_t)(mt * 8) * stream;
+    const T* pb = static_cast<const T*>(A.B) + (uint64_t)(nt * 4 + 2 * c) * stream + lane * 8;
+
+    f32x4 acc[8][2];  // [row block][this wave's column block: 2c, 2c + 1]
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+#pragma unroll
+        for (int n = 0; n < 2; ++n) acc[m][n] = f32x4{0.f, 0.f, 0.f, 0.f};
+    V bh[2][2], bl[2][2];  // B of the current block and of the next, by block parity
+    // this wave's four row blocks (hi and lo) of block j into buffer j & 1
+    auto load_a = [&](uint32_t j) {
+        const uint64_t o = (uint64_t)(s + 4 * j) * frag;
+#pragma unroll
+        for (int mm = 0; mm < 4; ++mm) {
+            const uint32_t m = 4 * c + mm;
+#pragma unroll
+            for (int lo = 0; lo < 2; ++lo)
+                __builtin_amdgcn_global_load_lds(
+                    static_cast<const void*>(pa + m * stream + o + lo * kFragLo + lane * 8),
+                    (void __attribute__((address_space(3)))*)&xa[s][j & 1u][2 * m + lo][0], 16, 0, 0);
+        }
+    };
+    auto load_b = [&](uint32_t j, V* dh, V* dl) {
+        const uint64_t o = (uint64_t)(s + 4 * j) * frag;
+#pragma unroll
+        for (int n = 0; n < 2; ++n) {
+            dh[n] = *reinterpret_cast<const V*>(pb + n * stream + o);
+            dl[n] = *reinterpret_cast<const V*>(pb + n * stream + o + kFragLo);
+        }
+    };
+    auto spin_until = [&](const uint32_t* p, uint32_t v) {
+        uint32_t spins = 0;
+        while (lds_acquire_u32(p) < v) {
+            __builtin_amdgcn_s_sleep(1);
+            if (++spins > (1u << 24)) {  // a partner that never arrives: give up (error flag)
+                if (lane == 0) atomicOr(A.flag, 2);
+                break;
+            }
+        }
+    };
+    // block j with its B in register set P (= j & 1)
+    auto block = [&](uint32_t j, auto parity) {
+        constexpr int P = decltype(parity)::value;
+        __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of block j have landed, its reads of j - 1 are done
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        if (lane == 0) __hip_atomic_store(&pub[s][c], j + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        spin_until(&pub[s][c ^ 1u], j + 1);
+        if (j + 1 < n_j) {  // the partner is done with block j - 1's buffer
+            load_a(j + 1);
+            load_b(j + 1, bh[P ^ 1], bl[P ^ 1]);
+        }
+        // a pair of row blocks' fragments is read while the previous pair's
+        // 12 MFMAs issue (an LDS-only wait: the next block's loads stay in
+        // flight); 4 independent accumulators per group of MFMAs
+        const V* xs = &xa[s][j & 1u][0][lane];
+        V a[4];
+#pragma unroll
+        for (int f = 0; f < 4; ++f) a[f] = xs[f * kWave];
+#pragma unroll
+        for (int mp = 0; mp < 4; ++mp) {
+            __builtin_amdgcn_s_waitcnt(kWaitLdsOnly);
+            V q[4];
+            if (mp < 3) {
+#pragma unroll
+                for (int f = 0; f < 4; ++f) q[f] = xs[(4 * mp + 4 + f) * kWave];
+            }
+            __builtin_amdgcn_sched_barrier(0);  // the reads stay ahead of the MFMAs
+#pragma unroll
+            for (int mm = 0; mm < 2; ++mm)
+#pragma unroll
+                for (int n = 0; n < 2; ++n)
+                    acc[2 * mp + mm][n] = mfma16<T, V>(a[2 * mm], bh[P][n], acc[2 * mp + mm][n]);
+#pragma unroll
+            for (int mm = 0; mm < 2; ++mm)
+#pragma unroll
+                for (int n = 0; n < 2; ++n)
+                    acc[2 * mp + mm][n] = mfma16<T, V>(a[2 * mm], bl[P][n], acc[2 * mp + mm][n]);
+#pragma unroll
+            for (int mm = 0; mm < 2; ++mm)
+#pragma unroll
+                for (int n = 0; n < 2; ++n)
+                    acc[2 * mp + mm][n] = mfma16<T, V>(a[2 * mm + 1], bh[P][n], acc[2 * mp + mm][n]);
+            __builtin_amdgcn_sched_barrier(0);  // and the next wait stays behind them
+            if (mp < 3) {
+#pragma unroll
+                for (int f = 0; f < 4; ++f) a[f] = q[f];
+            }
+        }
+    };
+    if (n_j > 0) {
+        load_a(0);
+        load_b(0, bh[0], bl[0]);
+    }
+    for (uint32_t j = 0; j < n_j; j += 2) {
+        block(j, std::integral_constant<int, 0>{});
+        if (j + 1 < n_j) block(j + 1, std::integral_constant<int, 1>{});
+    }
+    __syncthreads();  // every wave is done with the fragment buffers the partials overwrite
+    if (s >= 1) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+            for (int n = 0; n < 2; ++n) red[c][s - 1][m * 2 + n][lane] = acc[m][n];
+    }
+    __syncthreads();
+    // p0 + ((p1 + p2) + p3), transposed into the tile, times the exact power
+    // of two that undoes the scaling of K
+    const float inv = A.scale[1];
+    if (s == 0) {
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+#pragma unroll
+            for (int n = 0; n < 2; ++n) {
+                const uint32_t q = m * 2 + n;
+                const f32x4 sum = acc[m][n] + ((red[c][0][q][lane] + red[c][1][q][lane]) + red[c][2][q][lane]);
+                const uint32_t cb = 2 * c + n;  // column block: sin 0-15, sin 16-31, cos 0-15, cos 16-31
+                float(*t)[kRowTile + 1] = (cb >> 1) ? tC : tS;
+                const uint32_t rl = (cb & 1) * 16 + (lane & 15u);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) t[rl][m * 16 + 4 * (lane >> 4) + e] = sum[e] * inv;
+            }
+    }
+    __syncthreads();
+    dense_tile_stage<kThreads>(A, mt, nt, tS, tC);
+    dense_tile_store<T, V, kThreads>(A, mt, nt, tS, tC);
+}
+
 // ------------------------------------------- split MFMA, two K halves --
 // The same product with twice the tile per workgroup, to halve what each
 // CU loads per MFMA: a workgroup computes a 128-row x 64-realization tile (two
@@ -789,11 +968,6 @@ constexpr int kSplit2StageThreads = 512;  // the stage kernel: 8 waves, 4 partia
 __device__ __forceinline__ uint64_t split2_part(uint32_t h, uint32_t mt, uint32_t nt, uint32_t n_mt, uint32_t n_nt)
 {
     return (((uint64_t)h * n_mt + mt) * n_nt + nt) * (32 * kWave);
-}
-
-__device__ __forceinline__ uint32_t lds_acquire_u32(const uint32_t* p)
-{
-    return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 template <typename T, typename V>
@@ -1187,7 +1361,9 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
             hipLaunchKernelGGL(dense_mfma32_kernel, grid, dim3(kDenseThreads), 0, s, A);
         } else {
             typedef typename std::conditional<__is_same(T, __bf16), bf16x8, f16x8>::type V;
-            if (choice & 16) {
+            if (choice & 32) {
+                hipLaunchKernelGGL((dense_pair_kernel<T, V>), grid, dim3(kPairWaves * 64), 0, s, A);
+            } else if (choice & 16) {
                 hipLaunchKernelGGL((dense_lds4_kernel<T, V>), grid, dim3(kLds4Waves * 64), 0, s, A);
             } else if (choice & 8) {
                 hipLaunchKernelGGL((dense_rowhalf_kernel<T, V>), grid, dim3(kRowHalfWaves * 64), 0, s, A);
@@ -1213,9 +1389,9 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
     // kept unless another is more than 3 % faster.
     {
         const bool band_matters = (Mp / kRowTile) % 8 == 0;
-        int cands[10], nc = 0;
-        for (int c : {0, 1, 2, 3, 4, 6, 8, 10, 16, 18}) {
-            if ((c & 25) && sizeof(T) == 4) continue;
+        int cands[12], nc = 0;
+        for (int c : {0, 1, 2, 3, 4, 6, 8, 10, 16, 18, 32, 34}) {
+            if ((c & 57) && sizeof(T) == 4) continue;
             if ((c & 2) && !band_matters) continue;
             if ((c & 4) && !split2_ok) continue;
             cands[nc++] = c;
@@ -1226,7 +1402,7 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
         snprintf(tkey, sizeof tkey, "dense%d|%s|N2^%d|R2^%d", d->coupling, ctx->arch.c_str(), ilog2_dense(N),
                  ilog2_dense(R));
         if (ctx->dense_launch) {
-            static const int kForced[] = {0, 0, 1, 2, 3, 4, 6, 8, 10, 16, 18};
+            static const int kForced[] = {0, 0, 1, 2, 3, 4, 6, 8, 10, 16, 18, 32, 34};
             choice = kForced[ctx->dense_launch];
         } else if (!tune_lookup(ctx, tkey, &choice)) {
             choice = 0;
@@ -1254,7 +1430,7 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
                 // one untimed launch of every candidate (the first launch
                 // loads the code object), then three timed rounds over all
                 // of them in turn; a candidate's time is its fastest launch
-                float ms[10];
+                float ms[12];
                 for (int c = 0; c < nc; ++c) ms[c] = 3.4e38f;
                 for (int round = 0; round < 4 && st == SDE_OK; ++round) {
                     for (int c = 0; c < nc && st == SDE_OK; ++c) {
@@ -1283,17 +1459,18 @@ static int dense_run_typed(sde_ctx* ctx, const sde_kuramoto_desc* d, const sde_r
                 tune_store(ctx, tkey, choice);
             }
         }
-        if (choice < 0 || choice > 31) choice = 0;
+        if (choice < 0 || choice > 63) choice = 0;
         if (sizeof(T) == 4) choice &= 2;    // one FP32 kernel (4 waves)
+        if (choice & 32) choice &= 34;      // the pair kernel: 8 waves, one workgroup per tile
         if (choice & 16) choice &= 18;      // the 4-wave LDS kernel: one workgroup per tile
         if (choice & 8) choice &= 10;       // the row-half kernel: 8 waves, one workgroup per tile
-        if (!split2_ok) choice &= 11;       // the two-half kernel needs an even number of realization tiles
+        if (!split2_ok) choice &= ~4;       // the two-half kernel needs an even number of realization tiles
         if (choice & 4) choice &= 6;        // the two-half kernel has 8 waves
-        if (!band_matters) choice &= 29;    // bands or not: the same order
+        if (!band_matters) choice &= ~2;    // bands or not: the same order
     }
     ctx->last.dense_waves = sizeof(T) == 4 ? 4 : (choice & 17) ? 4 : 8;
     ctx->last.dense_xcd_bands = (choice & 2) || (Mp / kRowTile) % 8 != 0 ? 0 : 1;
-    ctx->last.dense_variant = (choice & 16) ? 3 : (choice & 8) ? 2 : (choice & 4) ? 1 : 0;
+    ctx->last.dense_variant = (choice & 32) ? 4 : (choice & 16) ? 3 : (choice & 8) ? 2 : (choice & 4) ? 1 : 0;
     // `count` steps from the device step base, then advance it.  The operand
     // buffers alternate per stage; chunks hold an even number of stages so a
     // recorded chunk always starts from the same buffer.

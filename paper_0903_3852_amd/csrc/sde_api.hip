@@ -337,7 +337,7 @@ int sde_set_option(sde_ctx* ctx, int option, int64_t value)
         ctx->kura_mf_paired = (int)value;
         return SDE_OK;
     case SDE_OPT_DENSE_LAUNCH:
-        if (value < 0 || value > 10) break;
+        if (value < 0 || value > 12) break;
         ctx->dense_launch = (int)value;
         return SDE_OK;
     default: break;

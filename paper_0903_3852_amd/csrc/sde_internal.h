@@ -72,7 +72,8 @@ struct sde_ctx {
     int dense_launch = 0;         // dense launch: 0 tuned; 1-4: 1 + (4 waves ? 1 : 0) + (plain order ? 2 : 0);
                                   // 5, 6: two workgroups per tile over the halves of k, bands / plain order;
                                   // 7, 8: row-half waves with two register sets, bands / plain order;
-                                  // 9, 10: 4 waves with K double-buffered in LDS, bands / plain order
+                                  // 9, 10: 4 waves with K double-buffered in LDS, bands / plain order;
+                                  // 11, 12: wave pairs sharing K through LDS, bands / plain order
     std::map<std::string, int> tune;
     std::string tune_path;
     sde_stats last{};

@@ -173,23 +173,23 @@ def test_dense_launch_choices(gpu):
                                        omega.astype(np.float64), Kmat=Kmat.astype(np.float64))
     for coupling, tol in [(2, 1e-5), (3, 1e-4), (4, 1e-5)]:
         got = {}
-        for launch in range(1, 11):
+        for launch in range(1, 13):
             sde.sde_set_option(ctx, sde.SDE_OPT_DENSE_LAUNCH, launch)
             ph, _ = _run(gpu, N, R, 4.0, 0.05, 0.005, n, coupling, 0, 33, omega, Kmat, samples=False)
             st = sde.sde_get_stats(ctx)
             waves = 4 if coupling == 2 or launch in (2, 4, 9, 10) else 8
-            variant = 0 if coupling == 2 else {5: 1, 6: 1, 7: 2, 8: 2, 9: 3, 10: 3}.get(launch, 0)
+            variant = 0 if coupling == 2 else {5: 1, 6: 1, 7: 2, 8: 2, 9: 3, 10: 3, 11: 4, 12: 4}.get(launch, 0)
             assert st["dense_waves"] == waves and st["dense_variant"] == variant
-            assert st["dense_xcd_bands"] == (1 if launch in (1, 2, 5, 7, 9) else 0)
+            assert st["dense_xcd_bands"] == (1 if launch in (1, 2, 5, 7, 9, 11) else 0)
             err = _circ_err(ph.cpu().numpy(), ref)
             print(f"dense coupling {coupling}, launch {launch}: max phase error {err.max():.2e}")
             assert err.max() <= tol
             got[launch] = ph.clone()
         assert torch.equal(got[1], got[3]) and torch.equal(got[2], got[4]) and torch.equal(got[5], got[6])
-        assert torch.equal(got[7], got[8]) and torch.equal(got[9], got[10])
+        assert torch.equal(got[7], got[8]) and torch.equal(got[9], got[10]) and torch.equal(got[11], got[12])
         if coupling == 2:
-            assert all(torch.equal(got[1], got[k]) for k in (2, 5, 7, 9))
-    for bad in (-1, 11):
+            assert all(torch.equal(got[1], got[k]) for k in (2, 5, 7, 9, 11))
+    for bad in (-1, 13):
         with pytest.raises(sde.SDEError):
             sde.sde_set_option(ctx, sde.SDE_OPT_DENSE_LAUNCH, bad)
 
@@ -216,6 +216,13 @@ def test_dense_two_halves(gpu, N, R):
         assert st["dense_variant"] == (1 if even else 0) and st["dense_waves"] == 8
         err = _circ_err(ph.cpu().numpy(), ref)
         print(f"two halves N={N} R={R} coupling {coupling}: max phase error {err.max():.2e}", flush=True)
+        assert err.max() <= tol
+        # the same shapes through the wave-pair kernel (K shared through LDS)
+        sde.sde_set_option(ctx, sde.SDE_OPT_DENSE_LAUNCH, 11)
+        ph, _ = _run(gpu, N, R, 4.0, 0.05, 0.005, n, coupling, 0, 63, omega, Kmat, samples=False)
+        assert sde.sde_get_stats(ctx)["dense_variant"] == 4
+        err = _circ_err(ph.cpu().numpy(), ref)
+        print(f"wave pairs N={N} R={R} coupling {coupling}: max phase error {err.max():.2e}", flush=True)
         assert err.max() <= tol
 
 
