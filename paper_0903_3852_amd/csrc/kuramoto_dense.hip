@@ -39,9 +39,10 @@
 // so that each XCD sweeps a contiguous band of rows over all columns: its
 // slice of K is read from HBM/MALL once per product, B once per XCD, and the
 // workgroups that share a K slab or a B column block hit in the XCD's L2.
-// Three more 16-bit kernels with a whole block of load lookahead (two
+// Four more 16-bit kernels with a whole block of load lookahead (two
 // workgroups per tile over the halves of k, row-half waves with two
-// register sets, 4 waves with K double-buffered in LDS) are candidates too:
+// register sets, 4 waves with K double-buffered in LDS, wave pairs sharing
+// K through LDS) are candidates too:
 // the kernel and the banding (against plain row-major order) are chosen per
 // shape class by timing predictor stages of each.
 #include <hip/hip_runtime.h>
