@@ -240,12 +240,16 @@ def test_dense_tuner(gpu):
     a, _ = _run(gpu, N, R, 4.0, 0.05, 0.005, n, 3, 0, 53, omega, Kmat, samples=False)
     st2 = sde.sde_get_stats(ctx)
     assert st2["tuned"] == 0
-    assert (st2["dense_waves"], st2["dense_xcd_bands"]) == (st1["dense_waves"], st1["dense_xcd_bands"])
-    launch = 1 + (1 if st1["dense_waves"] == 4 else 0) + (0 if st1["dense_xcd_bands"] else 2)
+    chosen = (st1["dense_variant"], st1["dense_waves"], st1["dense_xcd_bands"])
+    assert (st2["dense_variant"], st2["dense_waves"], st2["dense_xcd_bands"]) == chosen
+    # the forced launch of the same kernel, wave count and tile order
+    launch = {(0, 8, 1): 1, (0, 4, 1): 2, (0, 8, 0): 3, (0, 4, 0): 4, (1, 8, 1): 5, (1, 8, 0): 6,
+              (2, 8, 1): 7, (2, 8, 0): 8, (3, 4, 1): 9, (3, 4, 0): 10, (4, 8, 1): 11, (4, 8, 0): 12}[chosen]
     sde.sde_set_option(ctx, sde.SDE_OPT_DENSE_LAUNCH, launch)
     b, _ = _run(gpu, N, R, 4.0, 0.05, 0.005, n, 3, 0, 53, omega, Kmat, samples=False)
     assert torch.equal(a, b)
-    print(f"dense tuner: {st1['dense_waves']} waves, bands {st1['dense_xcd_bands']} ({st1['tune_ms']:.2f} ms)")
+    print(f"dense tuner: kernel {st1['dense_variant']}, {st1['dense_waves']} waves, "
+          f"bands {st1['dense_xcd_bands']} ({st1['tune_ms']:.2f} ms)")
 
 
 def test_dense_full_size_sampled(gpu):
