@@ -347,13 +347,13 @@ __device__ __forceinline__ void dense_reduce_tile(const f32x4 (&acc)[8][4], f32x
 // twice within the CU: 64 B per clock per CU at the MFMA rate, half of what a
 // 2 x 2 grid of 64 x 32 wave tiles needs (there the L1 bounds the loop).
 // Accumulators and one block of fragments fill a wave's 256 registers, so
-// there is no second register set for a prefetch; instead the next block's K
-// fragments of row block m load into the registers of row block m as soon
-// as its 12 MFMAs are issued, the B fragments after the last row block, and
-// the SIMD's other wave computes while one waits.  Per accumulator the
-// products still enter in the order hi*hi, hi*lo, lo*hi of each k block.
-// A 4-wave variant (one wave per SIMD, every fourth k block) is the other
-// candidate of the autotuner.
+// there is no second register set for a prefetch; instead each block is
+// swept in two column passes and every fragment register is reloaded for
+// the next block as soon as its last MFMA of this block is issued (the loop
+// below), at least half a block ahead of its use, and the SIMD's other wave
+// computes while one waits.  Per accumulator the products still enter in
+// the order hi*hi, hi*lo, lo*hi of each k block.  A 4-wave variant (one
+// wave per SIMD, every fourth k block) is a candidate of the autotuner too.
 template <typename T, typename V, int NW>
 __global__ __launch_bounds__(NW * 64, 1) void dense_mfma_kernel(DenseArgs A)
 {
