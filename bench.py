@@ -647,7 +647,7 @@ def bench_fig2(args, sde, torch, dev):
 KURA = {
     "kuramoto_mf": dict(cfg="uniform", coupling=0, scheme=0, steps=100000),
     "kuramoto_mf_em": dict(cfg="uniform", coupling=0, scheme=1, steps=100000),
-    "kuramoto_tiled": dict(cfg="uniform", coupling=1, scheme=0, steps=100),
+    "kuramoto_tiled": dict(cfg="uniform", coupling=1, scheme=0, steps=1000),  # a 10^3-step window of 10^5
     "kuramoto_dense_fp32": dict(cfg="dense", coupling=2, scheme=0, steps=20000),
     "kuramoto_dense_bf16x3": dict(cfg="dense", coupling=3, scheme=0, steps=20000),
     "kuramoto_dense_fp16x3": dict(cfg="dense", coupling=4, scheme=0, steps=20000),
